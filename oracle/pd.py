@@ -1,0 +1,373 @@
+"""FP64 reference for one projective-dynamics (PD) time step (paper Sec. 7).
+
+TEST INFRASTRUCTURE ONLY -- see the package docstring.  Plain numpy/scipy in
+float64; library primitives used as steps: batched LAPACK SVD
+(``numpy.linalg.svd``), sparse LU (``scipy.sparse.linalg.splu``).
+
+What one step computes (paper Sec. 7, Sec. 7.1):
+
+* per element e, the energy of Eq. (energy) with projections of Eq. (pd_local):
+  E_e = gs_e V_e ||F_e - R(F_e)||^2 + gv_e V_e ||F_e - V(F_e)||^2, where R is the
+  nearest rotation (polar factor) and V the nearest volume-preserving matrix,
+  found on the singular values by the problem of Eq. (vol_pre);
+* the time discretisation of Sec. 7: a = x - x* - dt v* - dt^2 M^{-1} f, which
+  makes the inertial target y = x* + dt v* + dt^2 g (gravity as f = M g);
+* the PD split of Sec. 7.1: a local step (per-element projections) and a
+  global step K x = b with the constant matrix and right-hand side printed
+  there (the trailing "x" after K's parenthesis is read as a typo; b is taken
+  with M y / dt^2 as its inertial term and with the projections of the current
+  iterate, not of the previous time step -- otherwise the iteration would not
+  iterate);
+* ``pd_iters`` local/global iterations per step from x^(0) = y, then BDF1
+  velocity v = (x_{n+1} - x_n) / dt.
+
+The global matrix is separable: row c of F only involves coordinate c of the
+four corners, so the paper's 3n x 3n K equals L (x) I_3 with the scalar
+L = M / dt^2 + sum_e (gs_e + gv_e) V_e G_e, (G_e)_ab = gradN_a . gradN_b.
+Pinned vertices are Dirichlet at their rest positions and eliminated.
+"""
+
+from __future__ import annotations
+
+import math
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+SL3_CLAMP = 0.01          # lower bound on a projected singular value (Sec. 7.1)
+
+
+# ----------------------------------------------------------------------------
+# Element geometry (Sec. 5: the operator D with F = D . (B_e x), and V_e)
+# ----------------------------------------------------------------------------
+def element_geometry(X, tets):
+    """Rest-shape quantities per tet.
+
+    Returns (V, grads) with V_e = det(Dm)/6, Dm = [X1-X0, X2-X0, X3-X0], and
+    grads[e, a] = gradient of the linear shape function of corner a, so that
+    F_e = sum_a x_a (outer) grads[e, a].  Rows 1..3 are the rows of Dm^{-1};
+    row 0 is minus their sum.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    t = np.asarray(tets, dtype=np.int64)
+    Dm = np.stack([X[t[:, 1]] - X[t[:, 0]], X[t[:, 2]] - X[t[:, 0]], X[t[:, 3]] - X[t[:, 0]]], axis=2)
+    V = np.linalg.det(Dm) / 6.0
+    Dinv = np.linalg.inv(Dm)
+    grads = np.empty((t.shape[0], 4, 3))
+    grads[:, 1:, :] = Dinv
+    grads[:, 0, :] = -Dinv.sum(axis=1)
+    return V, grads
+
+
+def deformation_gradient(x, tets, grads):
+    """F_e = sum_a x_a (outer) gradN_a  (nt, 3, 3)."""
+    xe = np.asarray(x, dtype=np.float64)[np.asarray(tets, dtype=np.int64)]  # (nt, 4, 3)
+    return np.einsum("eai,eaj->eij", xe, grads)
+
+
+# ----------------------------------------------------------------------------
+# Global matrix (Sec. 7.1, K)
+# ----------------------------------------------------------------------------
+def assemble_L(nv, tets, V, grads, gamma_s, gamma_v, mass, dt):
+    """Scalar L = diag(m)/dt^2 + sum_e V_e (gs_e + gv_e) gradN_a . gradN_b (CSR)."""
+    t = np.asarray(tets, dtype=np.int64)
+    w = V * (np.asarray(gamma_s) + np.asarray(gamma_v))
+    Ge = np.einsum("eai,ebi->eab", grads, grads) * w[:, None, None]
+    rows = np.repeat(t, 4, axis=1).ravel()
+    cols = np.tile(t, (1, 4)).ravel()
+    L = sp.coo_matrix((Ge.ravel(), (rows, cols)), shape=(nv, nv)).tocsr()
+    L = L + sp.diags(np.asarray(mass, dtype=np.float64) / (dt * dt))
+    L.sum_duplicates()
+    return L.tocsr()
+
+
+# ----------------------------------------------------------------------------
+# Local step: SO(3) and SL(3) projections (Sec. 7.1, Eq. pd_local, Eq. vol_pre)
+# ----------------------------------------------------------------------------
+def signed_svd(F):
+    """F = U diag(sigma) W^T with det U = det W = +1, sigma_1 >= sigma_2 >= |sigma_3|
+    and sign(sigma_3) = sign(det F).  LAPACK SVD, then a sign fix."""
+    U, S, Wt = np.linalg.svd(F)
+    W = np.swapaxes(Wt, 1, 2).copy()
+    U = U.copy()
+    S = S.copy()
+    du = np.linalg.det(U) < 0
+    U[du, :, 2] *= -1.0
+    S[du, 2] *= -1.0
+    dw = np.linalg.det(W) < 0
+    W[dw, :, 2] *= -1.0
+    S[dw, 2] *= -1.0
+    return U, S, W
+
+
+def _plus_root(sig, mu):
+    """Larger root of s^2 - sig s - mu = 0, evaluated without cancellation."""
+    d = np.sqrt(np.maximum(sig * sig + 4.0 * mu, 0.0))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        neg = np.where(d - sig > 0, 2.0 * mu / (d - sig), 0.0)
+    return np.where(sig >= 0, 0.5 * (sig + d), neg), d
+
+
+def _plus_branch(sig, logc=0.0):
+    """Solve prod_i s_i(mu) = exp(logc) on the + branch s_i = (sig_i + sqrt(sig_i^2 + 4 mu))/2.
+
+    Stationarity of the Lagrangian of Eq. (vol_pre) gives s_i (s_i - sig_i) = mu
+    for every i; h(mu) = sum ln s_i(mu) - logc is increasing, so the root is
+    bracketed and found by bisection, then polished by Newton.  Returns
+    (s, mu, ok) where ok is False when the + branch has no root.
+    """
+    sig = np.atleast_2d(np.asarray(sig, dtype=np.float64))
+    n = sig.shape[0]
+    smin = sig.min(axis=1)
+    allpos = smin > 0
+    with np.errstate(divide="ignore"):
+        logdet = np.where(allpos, np.log(np.abs(sig)).sum(axis=1), -np.inf)
+    grow = logdet <= logc                      # root at mu >= 0
+    lo = np.where(grow, 0.0, -0.25 * smin * smin)
+    hi = np.where(grow, 1.0, 0.0)
+
+    def h(mu):
+        s, _ = _plus_root(sig, mu[:, None])
+        with np.errstate(divide="ignore"):
+            return np.log(s).sum(axis=1) - logc
+
+    ok = np.ones(n, dtype=bool)
+    # bracket: h(hi) > 0 where the root is above zero
+    for _ in range(200):
+        need = grow & (h(hi) <= 0)
+        if not need.any():
+            break
+        hi = np.where(need, 2.0 * hi + 1.0, hi)
+    # below zero: a root exists only if h(lo) < 0
+    hlo = h(lo)
+    ok &= grow | (hlo < 0)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        hm = h(mid)
+        up = hm > 0
+        hi = np.where(up, mid, hi)
+        lo = np.where(up, lo, mid)
+    mu = 0.5 * (lo + hi)
+    for _ in range(4):                     # Newton polish, kept inside [lo, hi]
+        s, d = _plus_root(sig, mu[:, None])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            dh = (1.0 / (d * s)).sum(axis=1)
+            f = np.log(s).sum(axis=1) - logc
+            step = np.where(np.isfinite(dh) & (dh > 0), f / dh, 0.0)
+        cand = mu - step
+        mu = np.where((cand >= lo) & (cand <= hi), cand, mu)
+    s, _ = _plus_root(sig, mu[:, None])
+    return s, mu, ok
+
+
+def _squash_candidates(sig):
+    """Stationary points of Eq. (vol_pre) with one axis on the minus root.
+
+    For det F > 1 the Lagrange condition s_i (s_i - sig_i) = mu < 0 also admits
+    s_k = (sig_k - sqrt(sig_k^2 + 4 mu))/2 on one axis k.  These exist only when
+    det F >= 2 (then s_k <= sig_k/2 and s_j <= sig_j).  Scalar search: dense
+    bracketing in mu, then bisection.  Returns a list of candidate s vectors.
+    """
+    sig = np.asarray(sig, dtype=np.float64)
+    if sig.min() <= 0 or np.prod(sig) < 2.0:
+        return []
+    lo = -0.25 * sig.min() ** 2
+    out = []
+    for k in range(3):
+        def lnp(mu):
+            d = np.sqrt(np.maximum(sig * sig + 4.0 * mu, 0.0))
+            s = 0.5 * (sig + d)
+            s[k] = -2.0 * mu / (sig[k] + d[k])
+            return float(np.log(s).sum()), s
+
+        ts = np.concatenate([np.geomspace(1e-14, 1.0, 4000)])
+        mus = lo * ts
+        vals = np.array([lnp(m)[0] for m in mus])
+        for i in range(len(mus) - 1):
+            if np.sign(vals[i]) != np.sign(vals[i + 1]) and np.isfinite(vals[i]) and np.isfinite(vals[i + 1]):
+                a, b = mus[i], mus[i + 1]
+                fa = vals[i]
+                for _ in range(200):
+                    m = 0.5 * (a + b)
+                    fm = lnp(m)[0]
+                    if np.sign(fm) == np.sign(fa):
+                        a, fa = m, fm
+                    else:
+                        b = m
+                out.append(lnp(0.5 * (a + b))[1].copy())
+    return out
+
+
+def proj_sl3(sigma):
+    """Nearest point on {s : s1 s2 s3 = 1, s_i > 0} to the signed singular values
+    (Eq. vol_pre), then the paper's clamp of any component to [0.01, inf) with
+    that component frozen and the rest re-solved (Sec. 7.1).
+
+    Returns (s, info) with info counting elements where the + branch had no
+    root, where a squash candidate was nearer, and where the clamp fired.
+    """
+    sigma = np.atleast_2d(np.asarray(sigma, dtype=np.float64))
+    s, _, ok = _plus_branch(sigma)
+    n_noroot = int((~ok).sum())
+    n_squash = 0
+    big = np.nonzero((~ok) | ((sigma.min(axis=1) > 0) & (np.prod(sigma, axis=1) >= 2.0)))[0]
+    for e in big:
+        cands = []
+        if ok[e]:
+            cands.append(s[e].copy())
+        cands += _squash_candidates(sigma[e])
+        if not cands:
+            continue
+        d = [float(((c - sigma[e]) ** 2).sum()) for c in cands]
+        best = int(np.argmin(d))          # ties: first (the + branch, then lowest axis)
+        if best != 0 or not ok[e]:
+            n_squash += 1
+        s[e] = cands[best]
+    n_clamp = 0
+    low = np.nonzero((s < SL3_CLAMP).any(axis=1))[0]
+    for e in low:
+        n_clamp += 1
+        frozen = np.zeros(3, dtype=bool)
+        se = s[e].copy()
+        for _ in range(3):
+            newly = (~frozen) & (se < SL3_CLAMP)
+            if not newly.any():
+                break
+            frozen |= newly
+            se[frozen] = SL3_CLAMP
+            free = ~frozen
+            if free.any():
+                logc = -math.log(SL3_CLAMP) * frozen.sum()
+                sub, _, _ = _plus_branch(sigma[e, free][None, :], logc=logc)
+                se[free] = sub[0]
+        s[e] = se
+    return s, {"no_plus_root": n_noroot, "squash": n_squash, "clamped": n_clamp}
+
+
+def local_step(x, tets, grads, w_s, w_v):
+    """Per-element projections (Sec. 7.1): R = U W^T (polar rotation),
+    V = U diag(Proj_SL3(sigma)) W^T, and the projection mix P = w_s R + w_v V
+    with w = V_e gamma."""
+    F = deformation_gradient(x, tets, grads)
+    U, S, W = signed_svd(F)
+    s, info = proj_sl3(S)
+    Wt = np.swapaxes(W, 1, 2)
+    R = U @ Wt
+    Vp = (U * s[:, None, :]) @ Wt
+    P = w_s[:, None, None] * R + w_v[:, None, None] * Vp
+    return {"F": F, "U": U, "sigma": S, "W": W, "R": R, "s": s, "Vproj": Vp, "P": P, "info": info}
+
+
+def scatter_corners(nv, tets, vec_e):
+    """sum over (e, a) of vec_e[e, a, :] into vertex tets[e, a]  ->  (nv, 3)."""
+    t = np.asarray(tets, dtype=np.int64).ravel()
+    v = vec_e.reshape(-1, 3)
+    return np.stack([np.bincount(t, weights=v[:, c], minlength=nv) for c in range(3)], axis=1)
+
+
+def pd_energy(x, y, mass, dt, tets, grads, w_s, w_v):
+    """Inertial plus elastic energy minimised by the PD iteration:
+    (1/2dt^2) ||x - y||_M^2 + sum_e 1/2 (w_s ||F-R||^2 + w_v ||F-V||^2).
+
+    The 1/2 on the elastic term matches K and b as printed (Sec. 7.1), which
+    carry no factor 2; it is Eq. (energy) with gamma halved.
+    """
+    loc = local_step(x, tets, grads, w_s, w_v)
+    F = loc["F"]
+    el = 0.5 * (w_s * ((F - loc["R"]) ** 2).sum(axis=(1, 2)) + w_v * ((F - loc["Vproj"]) ** 2).sum(axis=(1, 2)))
+    d = x - y
+    return float(0.5 / (dt * dt) * (mass[:, None] * d * d).sum() + el.sum())
+
+
+# ----------------------------------------------------------------------------
+# The simulator
+# ----------------------------------------------------------------------------
+class OracleSim:
+    """Plain FP64 PD simulator.  ``solver`` is 'exact' (global sparse LU of the
+    free block of L) or 'dd' (the exact domain-decomposed solve of oracle.dd)."""
+
+    def __init__(self, X, tets, gamma_s, gamma_v, mass, pinned, gravity, dt, pd_iters=10,
+                 solver="exact", n_subdomains=4):
+        self.X = np.asarray(X, dtype=np.float64)
+        self.tets = np.asarray(tets, dtype=np.int64)
+        self.nv = self.X.shape[0]
+        self.gamma_s = np.asarray(gamma_s, dtype=np.float64)
+        self.gamma_v = np.asarray(gamma_v, dtype=np.float64)
+        self.mass = np.asarray(mass, dtype=np.float64)
+        self.pinned = np.asarray(pinned).astype(bool)
+        self.g = np.asarray(gravity, dtype=np.float64)
+        self.dt = float(dt)
+        self.pd_iters = int(pd_iters)
+        self.V, self.grads = element_geometry(self.X, self.tets)
+        if (self.V <= 0).any():
+            raise ValueError("non-positive rest volume")
+        self.w_s = self.V * self.gamma_s
+        self.w_v = self.V * self.gamma_v
+        self.L = assemble_L(self.nv, self.tets, self.V, self.grads, self.gamma_s, self.gamma_v,
+                            self.mass, self.dt)
+        self.free = np.nonzero(~self.pinned)[0]
+        self.fixed = np.nonzero(self.pinned)[0]
+        self.L_ff = self.L[self.free][:, self.free].tocsc()
+        self.L_fp = self.L[self.free][:, self.fixed].tocsr()
+        self.solver_kind = solver
+        if solver == "exact":
+            self._lu = spla.splu(self.L_ff)
+            self._solve = lambda b: self._lu.solve(b)
+        elif solver == "dd":
+            from .dd import DDSolver, bisect_elements
+            part = bisect_elements(self.tets, n_subdomains)
+            self._dd = DDSolver(self.L_ff, self.free, self.tets, part)
+            self._solve = self._dd.solve
+        else:
+            raise ValueError(solver)
+        self.last_info = {}
+        self.energies = []
+
+    def predictor(self, x, v):
+        """y = x* + dt v* + dt^2 g on free vertices, rest position on pinned ones."""
+        y = x + self.dt * v + self.dt * self.dt * self.g[None, :]
+        y[self.fixed] = self.X[self.fixed]
+        return y
+
+    def rhs(self, y, P):
+        """b = M y / dt^2 + sum_e B_e^T (D^T : P_e), restricted to free rows, minus L_fp x_p."""
+        f = np.einsum("eij,eaj->eai", P, self.grads)        # P_e gradN_a per corner
+        b = self.mass[:, None] * y / (self.dt * self.dt) + scatter_corners(self.nv, self.tets, f)
+        return b[self.free] - self.L_fp @ self.X[self.fixed]
+
+    def step(self, x, v, track_energy=False):
+        """One time step (pd_iters local/global iterations).  Returns (x1, v1)."""
+        x = np.asarray(x, dtype=np.float64)
+        v = np.asarray(v, dtype=np.float64)
+        y = self.predictor(x, v)
+        xk = y.copy()
+        info = {"no_plus_root": 0, "squash": 0, "clamped": 0}
+        self.energies = []
+        for _ in range(self.pd_iters):
+            if track_energy:
+                self.energies.append(pd_energy(xk, y, self.mass, self.dt, self.tets, self.grads,
+                                               self.w_s, self.w_v))
+            loc = local_step(xk, self.tets, self.grads, self.w_s, self.w_v)
+            for k in info:
+                info[k] += loc["info"][k]
+            b = self.rhs(y, loc["P"])
+            xk = xk.copy()
+            xk[self.free] = self._solve(b)
+        if track_energy:
+            self.energies.append(pd_energy(xk, y, self.mass, self.dt, self.tets, self.grads,
+                                           self.w_s, self.w_v))
+        self.last_info = info
+        v1 = (xk - x) / self.dt
+        v1[self.fixed] = 0.0
+        return xk, v1
+
+    def run(self, x, v, frames):
+        for _ in range(frames):
+            x, v = self.step(x, v)
+        return x, v
+
+    @classmethod
+    def from_problem(cls, p, solver="exact", n_subdomains=None):
+        return cls(p.X, p.tets, p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt,
+                   p.pd_iters, solver=solver,
+                   n_subdomains=p.n_subdomains if n_subdomains is None else n_subdomains)

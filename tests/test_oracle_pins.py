@@ -1,0 +1,344 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+closed forms, invariants, library routines on special cases and brute force on
+tiny inputs.  Each pin is chosen so that a plausible slip in the oracle (a
+dropped term, a wrong sign, a transposed operand, a wrong index) fails it."""
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+import synth
+from oracle import pd as opd
+
+
+def _rand_rot(rng, n):
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], -1),
+        np.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], -1),
+        np.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], -1),
+    ], 1)
+
+
+# --- element geometry --------------------------------------------------------
+def test_shape_gradients_partition_of_unity_and_identity():
+    p = synth.problem_by_name("box")
+    V, grads = oracle.element_geometry(p.X, p.tets)
+    assert np.allclose(grads.sum(axis=1), 0.0, atol=1e-9)
+    F = oracle.deformation_gradient(p.X, p.tets, grads)          # rest shape -> identity
+    assert np.abs(F - np.eye(3)).max() < 1e-12
+    # volumes: a 1 cm cube split into 5 tets -> the central tet holds a third
+    assert np.all(V > 0)
+    assert abs(V.sum() - 0.1 * 0.1 * 0.02) < 1e-15
+    # affine map x = A X + t gives F = A exactly
+    rng = np.random.default_rng(0)
+    A = np.eye(3) + 0.2 * rng.standard_normal((3, 3))
+    F = oracle.deformation_gradient(p.X @ A.T + 0.3, p.tets, grads)
+    assert np.abs(F - A).max() < 1e-12
+
+
+# --- global matrix -------------------------------------------------------------
+def _brute_K(X, tets, gs, gv, mass, dt):
+    """Dense 3n x 3n K from an explicit 9x12 operator per tet, vec(F) = D x_e
+    (row-major F, x_e = corners' xyz), with the weights of Sec. 7.1."""
+    n = X.shape[0]
+    K = np.diag(np.repeat(mass, 3)) / dt ** 2
+    for e, t in enumerate(tets):
+        Dm = np.stack([X[t[1]] - X[t[0]], X[t[2]] - X[t[0]], X[t[3]] - X[t[0]]], axis=1)
+        Dinv = np.linalg.inv(Dm)
+        D = np.zeros((9, 12))
+        # F = Ds Dinv, Ds[:, k] = x_{k+1} - x_0
+        for r in range(3):           # row of F
+            for c in range(3):       # column of F
+                for k in range(3):
+                    D[3 * r + c, 3 * (k + 1) + r] += Dinv[k, c]
+                    D[3 * r + c, 3 * 0 + r] -= Dinv[k, c]
+        Vol = np.linalg.det(Dm) / 6
+        Ke = Vol * (gs[e] + gv[e]) * D.T @ D
+        idx = np.concatenate([[3 * a, 3 * a + 1, 3 * a + 2] for a in t])
+        K[np.ix_(idx, idx)] += Ke
+    return K
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 2, 1)])
+def test_L_kron_I3_equals_bruteforce_K(dims):
+    X, tets, _ = synth.box_grid(*dims, h=0.01)
+    rng = np.random.default_rng(1)
+    gs = rng.uniform(1e3, 1e5, len(tets))
+    gv = rng.uniform(1e3, 1e4, len(tets))
+    mass = rng.uniform(1e-5, 1e-4, len(X))
+    dt = 1 / 150
+    V, grads = oracle.element_geometry(X, tets)
+    L = oracle.assemble_L(len(X), tets, V, grads, gs, gv, mass, dt).toarray()
+    K = _brute_K(X, tets, gs, gv, mass, dt)
+    assert np.abs(np.kron(L, np.eye(3)) - K).max() <= 1e-9 * np.abs(K).max()
+    assert np.abs(L - L.T).max() <= 1e-12 * np.abs(L).max()
+    Lstiff = L - np.diag(mass) / dt ** 2
+    assert np.abs(Lstiff.sum(axis=1)).max() <= 1e-9 * np.abs(Lstiff).max()   # Laplacian rows
+
+
+# --- SVD and rotation ----------------------------------------------------------
+def test_signed_svd_conventions():
+    rng = np.random.default_rng(2)
+    F = rng.standard_normal((500, 3, 3))
+    U, S, W = oracle.signed_svd(F)
+    rec = (U * S[:, None, :]) @ np.swapaxes(W, 1, 2)
+    assert np.abs(rec - F).max() < 1e-13
+    I = np.eye(3)
+    assert np.abs(np.swapaxes(U, 1, 2) @ U - I).max() < 1e-13
+    assert np.abs(np.swapaxes(W, 1, 2) @ W - I).max() < 1e-13
+    assert np.allclose(np.linalg.det(U), 1) and np.allclose(np.linalg.det(W), 1)
+    assert np.all(S[:, 0] >= S[:, 1]) and np.all(S[:, 1] >= np.abs(S[:, 2]))
+    assert np.all(np.sign(S[:, 2]) == np.sign(np.linalg.det(F)))
+
+
+def test_rotation_is_polar_factor():
+    rng = np.random.default_rng(3)
+    n = 200
+    Q = _rand_rot(rng, n)
+    A = rng.standard_normal((n, 3, 3))
+    S = np.swapaxes(A, 1, 2) @ A + 0.5 * np.eye(3)            # SPD
+    F = Q @ S
+    U, s, W = oracle.signed_svd(F)
+    R = U @ np.swapaxes(W, 1, 2)
+    assert np.abs(R - Q).max() < 1e-10
+    RtF = np.swapaxes(R, 1, 2) @ F
+    assert np.abs(RtF - np.swapaxes(RtF, 1, 2)).max() < 1e-10
+
+
+def test_rotation_maximises_trace_bruteforce():
+    rng = np.random.default_rng(4)
+    F = np.eye(3) + 0.4 * rng.standard_normal((5, 3, 3))
+    U, s, W = oracle.signed_svd(F)
+    R = U @ np.swapaxes(W, 1, 2)
+    cand = _rand_rot(rng, 20000)
+    for e in range(5):
+        best = np.einsum("kij,ij->k", cand, F[e]).max()
+        assert np.trace(R[e].T @ F[e]) >= best - 1e-12
+
+
+# --- SL(3) projection (Eq. vol_pre) --------------------------------------------
+def test_sl3_kkt_and_det():
+    rng = np.random.default_rng(5)
+    sig = np.sort(np.exp(0.2 * rng.standard_normal((2000, 3))), axis=1)[:, ::-1]
+    s, info = oracle.proj_sl3(sig)
+    assert np.abs(np.prod(s, axis=1) - 1).max() < 1e-13
+    mu = s * (s - sig)                                       # Lagrange condition
+    assert np.abs(mu - mu[:, :1]).max() < 1e-12
+    # the + branch covers every det F < 2 (a squash point needs det F >= 2)
+    small = np.prod(sig, axis=1) < 2.0
+    _, info = oracle.proj_sl3(sig[small])
+    assert info == {"no_plus_root": 0, "squash": 0, "clamped": 0}
+
+
+def test_sl3_special_cases():
+    # c^3 < 27/4: the nearest point of (c, c, c) is (1, 1, 1)
+    for c in (0.5, 0.9, 1.0, 1.3, 1.85):
+        s, _ = oracle.proj_sl3([[c, c, c]])
+        assert np.abs(s - 1).max() < 1e-14
+    # already volume preserving: unchanged
+    sig = np.array([[2.0, 1.0, 0.5], [1.25, 1.0, 0.8]])
+    s, _ = oracle.proj_sl3(sig)
+    assert np.abs(s - sig).max() < 1e-14
+    # inverted element: sign(sigma_3) < 0 still projects to positive values
+    s, _ = oracle.proj_sl3([[1.1, 0.9, -0.2]])
+    assert np.all(s > 0) and abs(np.prod(s) - 1) < 1e-13
+
+
+@pytest.mark.parametrize("a,b", [(1.1, 0.7), (0.9, 1.4), (1.02, 0.97), (1.5, -0.3)])
+def test_sl3_two_equal_reduces_to_polynomial(a, b):
+    """sigma = (a, a, b): s = (t, t, 1/t^2) with t^6 - a t^5 + b t^2 - 1 = 0;
+    the nearest real positive root (numpy.roots) is the projection."""
+    roots = np.roots([1, -a, 0, 0, b, 0, -1])
+    roots = roots[(np.abs(roots.imag) < 1e-9) & (roots.real > 0)].real
+    d = [2 * (t - a) ** 2 + (1 / t ** 2 - b) ** 2 for t in roots]
+    t = roots[int(np.argmin(d))]
+    s, _ = oracle.proj_sl3([[a, a, b]])
+    assert np.abs(np.sort(s[0]) - np.sort([t, t, 1 / t ** 2])).max() < 1e-10
+
+
+def test_sl3_bruteforce_grid():
+    """s = (e^u1, e^u2, e^{-u1-u2}) over a dense grid: no grid point is nearer."""
+    rng = np.random.default_rng(6)
+    u = np.linspace(-1.5, 1.5, 1201)
+    U1, U2 = np.meshgrid(u, u, indexing="ij")
+    cand = np.stack([np.exp(U1), np.exp(U2), np.exp(-U1 - U2)], -1).reshape(-1, 3)
+    for _ in range(6):
+        sig = np.sort(np.exp(0.3 * rng.standard_normal(3)))[::-1]
+        s, _ = oracle.proj_sl3(sig[None])
+        dbest = ((cand - sig) ** 2).sum(axis=1).min()
+        assert ((s[0] - sig) ** 2).sum() <= dbest + 1e-12
+
+
+def test_sl3_squash_regime():
+    """For det F > 1 a stationary point with one axis on the minus root can be
+    nearer than the + branch; sigma = (10, 10, 10) projects near (10, 10, 0.01)."""
+    s, info = oracle.proj_sl3([[10.0, 10.0, 10.0]])
+    assert info["squash"] == 1
+    assert abs(np.prod(s) - 1) < 1e-9
+    d_sq = ((s - 10) ** 2).sum()
+    assert d_sq < 3 * 9 ** 2                      # nearer than (1, 1, 1)
+    # brute force agrees
+    U1, U2 = np.meshgrid(np.linspace(1.5, 3, 801), np.linspace(1.5, 3, 801), indexing="ij")
+    cand = np.stack([np.exp(U1), np.exp(U2), np.exp(-U1 - U2)], -1).reshape(-1, 3)
+    assert d_sq <= ((cand - 10) ** 2).sum(axis=1).min() + 1e-6
+
+
+# --- local step ------------------------------------------------------------------
+def test_local_step_at_rest_and_rigid_motion():
+    p = synth.problem_by_name("box")
+    V, grads = oracle.element_geometry(p.X, p.tets)
+    ws, wv = V * p.gamma_s, V * p.gamma_v
+    loc = oracle.local_step(p.X, p.tets, grads, ws, wv)
+    assert np.abs(loc["P"] - (ws + wv)[:, None, None] * np.eye(3)).max() < 1e-9 * (ws + wv).max()
+    # rigid motion: elastic force sum_e w G_e^T (P - wF) is zero
+    Q = _rand_rot(np.random.default_rng(7), 1)[0]
+    x = p.X @ Q.T + np.array([0.1, -0.2, 0.3])
+    loc = oracle.local_step(x, p.tets, grads, ws, wv)
+    T = loc["P"] - (ws + wv)[:, None, None] * loc["F"]
+    f = opd.scatter_corners(p.nv, p.tets, np.einsum("eij,eaj->eai", T, grads))
+    assert np.abs(f).max() < 1e-9 * (ws + wv).max() / 0.01
+
+
+def test_global_step_minimises_quadratic():
+    """The solution of K x = b is the stationary point of the PD quadratic
+    (1/2dt^2)|x-y|_M^2 + 1/2 sum w_s|F(x)-R|^2 + w_v|F(x)-V|^2 with R, V fixed:
+    check by central differences of that energy written via F(x) directly."""
+    X, tets, _ = synth.box_grid(1, 2, 1, h=0.01)
+    rng = np.random.default_rng(8)
+    nv = len(X)
+    gs = rng.uniform(1e3, 1e5, len(tets))
+    gv = rng.uniform(1e3, 1e4, len(tets))
+    mass = rng.uniform(1e-5, 1e-4, nv)
+    pinned = np.zeros(nv, dtype=np.uint8)
+    pinned[:2] = 1
+    dt = 1 / 150
+    sim = oracle.OracleSim(X, tets, gs, gv, mass, pinned, [0, -9.81, 0], dt, pd_iters=1)
+    x0 = X + 1e-3 * rng.standard_normal(X.shape)
+    x0[:2] = X[:2]
+    v0 = 0.1 * rng.standard_normal(X.shape)
+    y = sim.predictor(x0, v0)
+    loc = oracle.local_step(y, tets, sim.grads, sim.w_s, sim.w_v)
+    R, Vp = loc["R"], loc["Vproj"]
+    xs = y.copy()
+    xs[sim.free] = sim._solve(sim.rhs(y, loc["P"]))
+
+    def Q(x):
+        F = oracle.deformation_gradient(x, tets, sim.grads)
+        el = 0.5 * (sim.w_s * ((F - R) ** 2).sum((1, 2)) + sim.w_v * ((F - Vp) ** 2).sum((1, 2)))
+        return 0.5 / dt ** 2 * (mass[:, None] * (x - y) ** 2).sum() + el.sum()
+
+    h = 1e-7
+    g = np.zeros_like(xs)
+    for a in sim.free:
+        for c in range(3):
+            xp = xs.copy(); xp[a, c] += h
+            xm = xs.copy(); xm[a, c] -= h
+            g[a, c] = (Q(xp) - Q(xm)) / (2 * h)
+    scale = (mass.max() / dt ** 2) * 1e-3
+    assert np.abs(g).max() < 1e-5 * scale
+
+
+# --- solves ------------------------------------------------------------------------
+def test_exact_solve_residual_and_dense_lapack():
+    p = synth.problem_by_name("box")
+    sim = oracle.OracleSim.from_problem(p)
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal((sim.L_ff.shape[0], 3))
+    x = sim._solve(b)
+    assert np.linalg.norm(b - sim.L_ff @ x) <= 1e-12 * np.linalg.norm(b)
+    xd = sla.cho_solve(sla.cho_factor(sim.L_ff.toarray()), b)
+    assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("name,nparts", [("box", 4), ("box", 1), ("shell_small", 8)])
+def test_dd_equals_exact(name, nparts):
+    p = synth.problem_by_name(name)
+    ex = oracle.OracleSim.from_problem(p)
+    dd = oracle.OracleSim.from_problem(p, solver="dd", n_subdomains=nparts)
+    rng = np.random.default_rng(10)
+    b = rng.standard_normal((ex.L_ff.shape[0], 3))
+    xe = ex._solve(b)
+    xd = dd._solve(b)
+    assert np.linalg.norm(xd - xe) <= 1e-12 * np.linalg.norm(xe)
+    if nparts == 1:
+        assert dd._dd.gamma.size == 0
+
+
+def test_dd_schur_matches_dense_bruteforce():
+    p = synth.problem_by_name("box")
+    dd = oracle.OracleSim.from_problem(p, solver="dd", n_subdomains=4)
+    A = dd.L_ff.toarray()
+    g = dd._dd.gamma
+    I = np.setdiff1d(np.arange(A.shape[0]), g)
+    S = A[np.ix_(g, g)] - A[np.ix_(g, I)] @ np.linalg.solve(A[np.ix_(I, I)], A[np.ix_(I, g)])
+    assert np.abs(S - dd._dd.S).max() <= 1e-10 * np.abs(S).max()
+
+
+def test_partition_balanced_power_of_two():
+    p = synth.problem_by_name("box")
+    part = oracle.bisect_elements(p.tets, 4)
+    assert np.bincount(part).tolist() == [250, 250, 250, 250]
+    with pytest.raises(ValueError):
+        oracle.bisect_elements(p.tets, 3)
+
+
+# --- whole step ----------------------------------------------------------------------
+def test_rest_is_fixed_point_without_gravity():
+    p = synth.problem_by_name("box")
+    sim = oracle.OracleSim(p.X, p.tets, p.gamma_s, p.gamma_v, p.mass, p.pinned, [0, 0, 0], p.dt)
+    x, v = sim.run(p.X.copy(), np.zeros_like(p.X), 2)
+    assert np.abs(x - p.X).max() < 1e-14 and np.abs(v).max() < 1e-11
+
+
+def test_free_fall_without_stiffness():
+    """gamma = 0: x_{n+1} = x_n + dt (v_n + dt g) on free vertices (BDF1)."""
+    p = synth.problem_by_name("box")
+    z = np.zeros(p.nt)
+    sim = oracle.OracleSim(p.X, p.tets, z, z, p.mass, p.pinned, p.gravity, p.dt)
+    rng = np.random.default_rng(11)
+    v0 = rng.standard_normal(p.X.shape) * 0.1
+    v0[p.pinned.astype(bool)] = 0
+    x1, v1 = sim.step(p.X, v0)
+    free = ~p.pinned.astype(bool)
+    want = p.X + p.dt * (v0 + p.dt * p.gravity)
+    assert np.abs(x1[free] - want[free]).max() < 1e-15
+    assert np.abs(v1[free] - (v0 + p.dt * p.gravity)[free]).max() < 1e-11
+
+
+def test_momentum_conserved_unpinned():
+    p = synth.problem_by_name("box")
+    sim = oracle.OracleSim(p.X, p.tets, p.gamma_s, p.gamma_v, p.mass, np.zeros(p.nv), [0, 0, 0], p.dt)
+    rng = np.random.default_rng(12)
+    v0 = 0.05 * rng.standard_normal(p.X.shape)
+    x, v = p.X.copy(), v0
+    mom0 = (p.mass[:, None] * v0).sum(0)
+    for _ in range(3):
+        x, v = sim.step(x, v)
+    assert np.abs((p.mass[:, None] * v).sum(0) - mom0).max() < 1e-10 * np.abs(p.mass[:, None] * v0).sum()
+
+
+def test_pd_energy_non_increasing():
+    p = synth.problem_by_name("box")
+    sim = oracle.OracleSim.from_problem(p)
+    x, v = p.initial_state()
+    for _ in range(3):
+        x, v = sim.step(x, v, track_energy=True)
+        e = np.array(sim.energies)
+        assert np.all(np.diff(e) <= 1e-12 * e[0])
+
+
+def test_gravity_sag_direction_and_scale():
+    """Under gravity the slab sags along -y, pinned row stays at rest."""
+    p = synth.problem_by_name("box")
+    sim = oracle.OracleSim.from_problem(p)
+    x, v = sim.run(*p.initial_state(), 5)
+    pin = p.pinned.astype(bool)
+    assert np.abs(x[pin] - p.X[pin]).max() == 0.0
+    d = x - p.X
+    assert d[~pin, 1].mean() < 0
+    # bounded by free fall over 5 steps
+    assert -d[~pin, 1].min() <= 0.5 * 9.81 * (5 * p.dt) ** 2 * 1.5
