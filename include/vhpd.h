@@ -1,0 +1,169 @@
+/*
+ * vhpd -- projective dynamics for volumetric homogenization on MI355X (gfx950).
+ *
+ * C ABI of the native library libvhpd.so.  One simulated garment is a
+ * tetrahedral mesh with a per-element material (gamma_s, gamma_v), simulated
+ * by the projective-dynamics (PD) step of the paper "Volumetric Homogenization
+ * for Knitwear Simulation", Sec. 7:
+ *
+ *   - time discretisation (Sec. 7): the implicit-Euler target
+ *       y = x* + dt v* + dt^2 g,
+ *   - local step (Sec. 7.1, Eq. pd_local, Eq. vol_pre): per element the polar
+ *     rotation R(F_e) and the nearest volume-preserving V(F_e),
+ *   - global step (Sec. 7.1): the constant SPD system K x = b,
+ *       K = M/dt^2 + sum_e V_e (gs_e + gv_e) B_e^T (D^T:D) B_e,
+ *       b = M y/dt^2 + sum_e V_e B_e^T D^T:(gs_e R_e + gv_e V_e),
+ *     solved by domain decomposition (Sec. 7.2): per-subdomain interior
+ *     Cholesky solves plus the interface (Schur complement) solve that the
+ *     boundary modes Psi_d = -(K_d^ii)^{-1} K_d^ib of Eq. (cms_boundary) and the
+ *     shared boundary unknowns of Eq. (global_subspace) lead to.
+ *   - BDF1 velocity v = (x_{n+1} - x_n)/dt after pd_iters local/global
+ *     iterations started from x^(0) = y.
+ *
+ * Conventions for every entry point:
+ *   - Return value: VH_OK (0) on success, a negative VH_E* code on failure; the
+ *     message of the last failure on the calling thread is vh_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Host arrays passed in are read during the call and copied; the caller
+ *     keeps ownership.  Host arrays passed out are written during the call.
+ *   - Layouts are C-contiguous row-major: positions [nv][3] float64,
+ *     tets [nt][4] int32 (vertex ids, positively oriented), per-element
+ *     arrays [nt], per-vertex arrays [nv].
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued on it; entry points that return host data
+ *     synchronise it.
+ *   - Handles are opaque and owned by the library; destroy them with the
+ *     matching *_destroy call.  A handle is not thread-safe: calls on one
+ *     handle must not overlap.
+ */
+#ifndef VHPD_H
+#define VHPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VH_OK = 0,
+    VH_EINVAL = -1,   /* invalid argument (sizes, ids, orientation, gamma < 0, ...) */
+    VH_ENOMEM = -2,   /* host or device allocation failed, or over the HBM budget */
+    VH_ENOTSPD = -3,  /* a non-positive pivot in the FP64 factorization */
+    VH_ESTATE = -4,   /* call out of order (e.g. step before prefactor) */
+    VH_ENUMERIC = -5, /* a NaN/Inf appeared in the device state */
+    VH_EDEVICE = -6   /* a HIP runtime call failed */
+};
+
+typedef struct vh_ctx vh_ctx;
+typedef struct vh_mesh vh_mesh;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* vh_last_error(void);
+
+/* Context: one GPU.  hbm_budget_bytes bounds the device memory the library
+ * holds for all meshes of this context (0 = unlimited).  The device is made
+ * current on the calling thread. */
+int vh_ctx_create(vh_ctx** out, int device, size_t hbm_budget_bytes);
+int vh_ctx_destroy(vh_ctx* ctx);
+/* Device bytes currently held by the context's meshes. */
+int vh_ctx_hbm_in_use(const vh_ctx* ctx, size_t* bytes);
+
+/* Mesh: rest positions X [nv][3] (metres) and tets [nt][4].  Every tet must
+ * have positive rest volume det([X1-X0, X2-X0, X3-X0])/6 > 0 (VH_EINVAL
+ * otherwise; tets are never reoriented silently).  Sec. 5 defines the per-tet
+ * operator D and volume V_e this uses. */
+int vh_mesh_create(vh_ctx* ctx, vh_mesh** out, const double* rest_xyz, int32_t nv,
+                   const int32_t* tets, int32_t nt);
+int vh_mesh_destroy(vh_mesh* mesh);
+
+/* Material and step settings.  gamma_s, gamma_v [nt] >= 0 (Pa; Eq. energy,
+ * Sec. 6.3 requires gamma >= 0); mass [nv] lumped nodal masses, > 0 on every
+ * free vertex (kg); pinned [nv] 1 = Dirichlet at the rest position; gravity
+ * [3] (m/s^2); dt > 0 (s); pd_iters >= 1 local/global iterations per step.
+ * Invalidates any previous factorization and resets the state to rest with
+ * zero velocity. */
+int vh_mesh_set_params(vh_mesh* mesh, const double* gamma_s, const double* gamma_v,
+                       const double* mass, const uint8_t* pinned, const double* gravity,
+                       double dt, int32_t pd_iters);
+
+/* Prefactor (host FP64): partitions the elements into n_subdomains (a power of
+ * two, >= 1) by recursive breadth-first bisection, orders each subdomain's
+ * interior by nested dissection and the interface by the bisection tree,
+ * factors the global matrix (interior Cholesky factors and the interface
+ * Schur complement), and uploads it.  refine_steps (>= 0) extra solves of the
+ * global system against its FP64 residual are done every PD iteration.
+ * VH_ENOTSPD on a non-positive pivot, VH_ENOMEM over the HBM budget. */
+int vh_mesh_prefactor(vh_mesh* mesh, int32_t n_subdomains, int32_t refine_steps);
+
+/* Advance n_frames time steps on `stream` (asynchronous). */
+int vh_mesh_step(vh_mesh* mesh, int32_t n_frames, void* stream);
+
+/* Copy the state to host x, v [nv][3] (float64); synchronises `stream` and
+ * returns VH_ENUMERIC if the state holds a NaN/Inf. */
+int vh_mesh_read_state(vh_mesh* mesh, double* x, double* v, void* stream);
+/* Overwrite the state from host x, v [nv][3]; pinned vertices keep their rest
+ * position and zero velocity whatever is passed. */
+int vh_mesh_write_state(vh_mesh* mesh, const double* x, const double* v, void* stream);
+/* Same with device pointers (e.g. torch tensors' data_ptr), [nv][3] float64 in
+ * user vertex order; asynchronous on `stream`. */
+int vh_mesh_read_state_device(vh_mesh* mesh, double* x_dev, double* v_dev, void* stream);
+int vh_mesh_write_state_device(vh_mesh* mesh, const double* x_dev, const double* v_dev,
+                               void* stream);
+
+typedef struct vh_mesh_info {
+    int32_t nv, nt, n_free, n_interior, n_interface, n_subdomains;
+    int32_t n_supernodes, n_coarse_levels, max_interior_phases;
+    int64_t nnz_interior;   /* stored entries of the FP32 interior factor blocks */
+    int64_t nnz_coarse;     /* stored entries of the FP64 interface factor blocks */
+    size_t device_bytes;
+    double prefactor_seconds;
+} vh_mesh_info;
+int vh_mesh_get_info(const vh_mesh* mesh, vh_mesh_info* info);
+
+/* Per-kernel timing with HIP events recorded on the step's stream around each
+ * launch group of a kernel class (bit c of class_mask enables class c):
+ *   0 predictor, 1 local step, 2 residual gather, 3 interior forward solve,
+ *   4 interface solve (all tree levels), 5 interior backward solve + update,
+ *   6 refinement residual, 7 velocity.
+ * vh_mesh_profile resets the record and sets the mask (0 = off);
+ * vh_mesh_profile_read synchronises and returns, per class, the summed
+ * milliseconds ms[8] and the number of timed groups launches[8] since then. */
+#define VH_PROFILE_CLASSES 8
+int vh_mesh_profile(vh_mesh* mesh, uint32_t class_mask);
+int vh_mesh_profile_read(vh_mesh* mesh, double* ms, int64_t* launches);
+
+/* ---- Entry points that run one part of the step, for testing each kernel
+ * against a reference.  All arrays are host arrays in user vertex order. ---- */
+
+/* Local step (Sec. 7.1) at positions x [nv][3]: per tet e, writes the
+ * residual stress T_e = gs_e V_e (R_e - F_e) + gv_e V_e (V_e - F_e) [nt][9]
+ * (row-major 3x3, float64 copy of the FP32 result) and, if not NULL, the signed
+ * singular values sigma [nt][3] and projected ones s [nt][3]. */
+int vh_debug_local_step(vh_mesh* mesh, const double* x, double* T, double* sigma, double* s);
+
+/* Residual of the global system (Sec. 7.1) at positions x with inertial
+ * target y: r = b(x) - K x on free vertices, written to r [nv][3] (pinned rows
+ * are 0).  Uses the local-step and scatter kernels. */
+int vh_debug_residual(vh_mesh* mesh, const double* x, const double* y, double* r);
+
+/* Solve K_ff d = rhs with the decomposed solver; rhs and d are [nv][3]
+ * (pinned rows ignored on input, 0 on output). */
+int vh_debug_solve(vh_mesh* mesh, const double* rhs, double* d);
+
+/* ---- Serving: continuous batching of step requests across meshes. ---- */
+
+typedef struct vh_serve_stats {
+    int64_t frames_done;
+    int64_t requests_done;
+    double frames_per_second;
+    double latency_p50_s, latency_p99_s;
+    size_t hbm_in_use;
+    int32_t meshes_resident, meshes_waiting;
+} vh_serve_stats;
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VHPD_H */

@@ -1,0 +1,574 @@
+// C ABI of libvhpd (declared in include/vhpd.h): handles, device buffers,
+// the frame loop and the per-kernel test entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vhpd.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define VH_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(VH_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define VH_TRY(expr)           \
+    do {                       \
+        int rc_ = (expr);      \
+        if (rc_ != VH_OK) return rc_; \
+    } while (0)
+
+}  // namespace
+
+struct vh_ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t in_use = 0;
+    std::vector<vh_mesh*> meshes;
+};
+
+struct vh_mesh {
+    vh_ctx* ctx = nullptr;
+    int32_t nv = 0, nt = 0;
+    std::vector<double> X;
+    std::vector<int32_t> tets;
+    bool has_params = false, factored = false;
+    std::vector<double> gs, gv, mass;
+    std::vector<uint8_t> pinned;
+    double g[3] = {0, 0, 0};
+    double dt = 0;
+    int32_t iters = 10;
+    vh::Plan plan;
+    vh::DevMesh dm;
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    std::vector<vh::PhaseLaunch> fwd, bwd;
+    int32_t refine = 0;
+    std::vector<double> stage;   // host staging, nv*3
+    // optional per-kernel-class timing with HIP events on the step's stream
+    uint32_t prof_mask = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<size_t, int>> ev_pairs;   // start event index, class
+};
+
+namespace {
+
+void release_events(vh_mesh* m) {
+    for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
+    m->ev_pool.clear();
+    m->ev_used = 0;
+    m->ev_pairs.clear();
+}
+
+// Records an event pair around a group of launches of one kernel class.
+struct ProfScope {
+    vh_mesh* m;
+    hipStream_t s;
+    int cls;
+    size_t start = 0;
+    bool on = false;
+    hipError_t err = hipSuccess;
+    hipEvent_t next() {
+        if (m->ev_used == m->ev_pool.size()) {
+            hipEvent_t e;
+            err = hipEventCreate(&e);
+            if (err != hipSuccess) return nullptr;
+            m->ev_pool.push_back(e);
+        }
+        return m->ev_pool[m->ev_used++];
+    }
+    ProfScope(vh_mesh* m_, hipStream_t s_, int cls_) : m(m_), s(s_), cls(cls_) {
+        on = (m->prof_mask >> cls) & 1u;
+        if (!on) return;
+        start = m->ev_used;
+        hipEvent_t e = next();
+        if (e) err = hipEventRecord(e, s);
+    }
+    ~ProfScope() {
+        if (!on || err != hipSuccess) return;
+        hipEvent_t e = next();
+        if (e && hipEventRecord(e, s) == hipSuccess) m->ev_pairs.push_back({start, cls});
+    }
+};
+
+void free_device(vh_mesh* m) {
+    for (void* p : m->allocs) (void)hipFree(p);
+    m->allocs.clear();
+    if (m->ctx) m->ctx->in_use -= std::min(m->ctx->in_use, m->bytes);
+    m->bytes = 0;
+    m->dm = vh::DevMesh();
+    m->factored = false;
+}
+
+template <class T>
+int dalloc(vh_mesh* m, T** p, size_t count) {
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (m->ctx->budget && m->ctx->in_use + bytes > m->ctx->budget)
+        return fail(VH_ENOMEM, "HBM budget exceeded");
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(VH_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    m->allocs.push_back(q);
+    m->bytes += bytes;
+    m->ctx->in_use += bytes;
+    *p = static_cast<T*>(q);
+    return VH_OK;
+}
+
+template <class T>
+int upload(vh_mesh* m, T** p, const std::vector<T>& v) {
+    VH_TRY(dalloc(m, p, v.size()));
+    if (!v.empty()) VH_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return VH_OK;
+}
+
+int set_device(vh_mesh* m) {
+    VH_HIP(hipSetDevice(m->ctx->device));
+    return VH_OK;
+}
+
+int solve(vh_mesh* m, hipStream_t s, bool apply, bool keep_delta) {
+    const vh::DevMesh& d = m->dm;
+    {
+        ProfScope ps(m, s, 3);
+        VH_HIP(vh::launch_interior_fwd(d, s));
+    }
+    {
+        ProfScope ps(m, s, 4);
+        for (const auto& ph : m->fwd) VH_HIP(vh::launch_interface_phase(d, ph, s));
+        for (const auto& ph : m->bwd) VH_HIP(vh::launch_interface_phase(d, ph, s));
+    }
+    {
+        ProfScope ps(m, s, 5);
+        VH_HIP(vh::launch_interior_bwd(d, s, apply, keep_delta));
+    }
+    return VH_OK;
+}
+
+int pd_iteration(vh_mesh* m, hipStream_t s) {
+    const vh::DevMesh& d = m->dm;
+    {
+        ProfScope ps(m, s, 1);
+        VH_HIP(vh::launch_local(d, s, false));
+    }
+    {
+        ProfScope ps(m, s, 2);
+        VH_HIP(vh::launch_residual(d, s));
+    }
+    const bool refine = m->refine > 0;
+    VH_TRY(solve(m, s, true, refine));
+    for (int32_t k = 0; k < m->refine; ++k) {
+        {
+            ProfScope ps(m, s, 6);
+            VH_HIP(vh::launch_refine_residual(d, s));
+        }
+        VH_TRY(solve(m, s, true, k + 1 < m->refine));
+    }
+    return VH_OK;
+}
+
+int check_ready(vh_mesh* m) {
+    if (!m) return fail(VH_EINVAL, "null mesh");
+    if (!m->factored) return fail(VH_ESTATE, "mesh is not prefactored");
+    return VH_OK;
+}
+
+// user [nv][3] host -> internal device buffer (pinned rows: X or 0)
+int put_user(vh_mesh* m, const double* host, double* dev_int, bool positions, hipStream_t s) {
+    const vh::Plan& P = m->plan;
+    std::vector<double>& st = m->stage;
+    st.resize((size_t)P.nv * 3);
+    for (int32_t i = 0; i < P.nv; ++i) {
+        const int32_t u = P.perm[i];
+        for (int c = 0; c < 3; ++c)
+            st[3 * i + c] = (i < P.n_free) ? host[3 * u + c] : (positions ? P.X_int[3 * i + c] : 0.0);
+    }
+    VH_HIP(hipMemcpyAsync(dev_int, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    VH_HIP(hipStreamSynchronize(s));
+    return VH_OK;
+}
+
+int get_user(vh_mesh* m, const double* dev_int, double* host, int32_t rows, hipStream_t s) {
+    const vh::Plan& P = m->plan;
+    std::vector<double>& st = m->stage;
+    st.resize((size_t)P.nv * 3);
+    VH_HIP(hipMemcpyAsync(st.data(), dev_int, (size_t)rows * 3 * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+    VH_HIP(hipStreamSynchronize(s));
+    std::fill(host, host + (size_t)P.nv * 3, 0.0);
+    for (int32_t i = 0; i < rows; ++i) {
+        const int32_t u = P.perm[i];
+        for (int c = 0; c < 3; ++c) host[3 * u + c] = st[3 * i + c];
+    }
+    return VH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vh_last_error(void) { return g_err.c_str(); }
+
+int vh_ctx_create(vh_ctx** out, int device, size_t hbm_budget_bytes) {
+    if (!out) return fail(VH_EINVAL, "null output handle");
+    int n = 0;
+    VH_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(VH_EINVAL, "device id out of range");
+    VH_HIP(hipSetDevice(device));
+    vh_ctx* c = new vh_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return VH_OK;
+}
+
+int vh_ctx_destroy(vh_ctx* ctx) {
+    if (!ctx) return VH_OK;
+    std::vector<vh_mesh*> ms = ctx->meshes;
+    for (vh_mesh* m : ms) vh_mesh_destroy(m);
+    delete ctx;
+    return VH_OK;
+}
+
+int vh_ctx_hbm_in_use(const vh_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return fail(VH_EINVAL, "null argument");
+    *bytes = ctx->in_use;
+    return VH_OK;
+}
+
+int vh_mesh_create(vh_ctx* ctx, vh_mesh** out, const double* rest_xyz, int32_t nv,
+                   const int32_t* tets, int32_t nt) {
+    if (!ctx || !out) return fail(VH_EINVAL, "null argument");
+    std::string msg;
+    if (vh::check_mesh(rest_xyz, nv, tets, nt, msg) != 0) return fail(VH_EINVAL, msg);
+    vh_mesh* m = new vh_mesh();
+    m->ctx = ctx;
+    m->nv = nv;
+    m->nt = nt;
+    m->X.assign(rest_xyz, rest_xyz + (size_t)nv * 3);
+    m->tets.assign(tets, tets + (size_t)nt * 4);
+    ctx->meshes.push_back(m);
+    *out = m;
+    return VH_OK;
+}
+
+int vh_mesh_destroy(vh_mesh* m) {
+    if (!m) return VH_OK;
+    if (m->ctx) {
+        (void)hipSetDevice(m->ctx->device);
+        release_events(m);
+        free_device(m);
+        auto& v = m->ctx->meshes;
+        v.erase(std::remove(v.begin(), v.end(), m), v.end());
+    }
+    delete m;
+    return VH_OK;
+}
+
+int vh_mesh_set_params(vh_mesh* m, const double* gamma_s, const double* gamma_v, const double* mass,
+                       const uint8_t* pinned, const double* gravity, double dt, int32_t pd_iters) {
+    if (!m || !gamma_s || !gamma_v || !mass || !pinned || !gravity)
+        return fail(VH_EINVAL, "null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(VH_EINVAL, "dt must be positive");
+    if (pd_iters < 1) return fail(VH_EINVAL, "pd_iters must be >= 1");
+    for (int32_t e = 0; e < m->nt; ++e)
+        if (!(gamma_s[e] >= 0.0) || !(gamma_v[e] >= 0.0) || !std::isfinite(gamma_s[e]) ||
+            !std::isfinite(gamma_v[e]))
+            return fail(VH_EINVAL, "gamma must be finite and >= 0 (element " + std::to_string(e) + ")");
+    for (int32_t v = 0; v < m->nv; ++v)
+        if (!pinned[v] && !(mass[v] > 0.0))
+            return fail(VH_EINVAL, "mass must be > 0 on free vertex " + std::to_string(v));
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(gravity[c])) return fail(VH_EINVAL, "gravity must be finite");
+    if (m->factored) {
+        (void)hipSetDevice(m->ctx->device);
+        free_device(m);
+    }
+    m->gs.assign(gamma_s, gamma_s + m->nt);
+    m->gv.assign(gamma_v, gamma_v + m->nt);
+    m->mass.assign(mass, mass + m->nv);
+    m->pinned.assign(pinned, pinned + m->nv);
+    for (int c = 0; c < 3; ++c) m->g[c] = gravity[c];
+    m->dt = dt;
+    m->iters = pd_iters;
+    m->has_params = true;
+    return VH_OK;
+}
+
+int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
+    if (!m) return fail(VH_EINVAL, "null mesh");
+    if (!m->has_params) return fail(VH_ESTATE, "set_params must precede prefactor");
+    if (refine_steps < 0) return fail(VH_EINVAL, "refine_steps must be >= 0");
+    VH_TRY(set_device(m));
+    free_device(m);
+    std::string msg;
+    int rc = vh::build_plan(m->X.data(), m->nv, m->tets.data(), m->nt, m->gs.data(), m->gv.data(),
+                            m->mass.data(), m->pinned.data(), m->g, m->dt, m->iters, n_subdomains,
+                            refine_steps, 32, m->plan, msg);
+    if (rc != 0) return fail(rc, msg);
+    const vh::Plan& P = m->plan;
+    // the interior kernels keep three 3-column FP32 vectors of a subdomain in LDS
+    if ((size_t)P.max_sub_n * 9 * sizeof(float) > 65536)
+        return fail(VH_EINVAL, "a subdomain interior has " + std::to_string(P.max_sub_n) +
+                                   " vertices (LDS holds at most 1820); use more subdomains");
+    vh::DevMesh& d = m->dm;
+    d.nv = P.nv;
+    d.nt = P.nt;
+    d.n_free = P.n_free;
+    d.n_int = P.n_int;
+    d.n_gamma = P.n_gamma;
+    d.D = P.D;
+    d.max_sub_n = std::max(P.max_sub_n, 1);
+    d.dt = P.dt;
+    for (int c = 0; c < 3; ++c) d.g[c] = P.gravity[c];
+    const size_t nv3 = (size_t)P.nv * 3;
+    int r = VH_OK;
+    auto chk = [&](int x) {
+        if (r == VH_OK) r = x;
+    };
+    chk(upload(m, &d.X, P.X_int));
+    chk(upload(m, &d.x, P.X_int));
+    chk(dalloc(m, &d.v, nv3));
+    chk(dalloc(m, &d.xprev, nv3));
+    chk(dalloc(m, &d.y, nv3));
+    chk(upload(m, &d.mass, P.mass_int));
+    chk(upload(m, &d.perm, P.perm));
+    chk(dalloc(m, &d.u, (size_t)P.nv));
+    chk(upload(m, &d.tet, P.tet_soa));
+    chk(upload(m, &d.ginv, P.ginv_soa));
+    chk(upload(m, &d.w, P.w_soa));
+    chk(dalloc(m, &d.fout, (size_t)P.nt * 12));
+    chk(upload(m, &d.inc_ptr, P.inc_ptr));
+    chk(upload(m, &d.inc_slot, P.inc_slot));
+    chk(dalloc(m, &d.r, (size_t)P.n_free * 3));
+    chk(dalloc(m, &d.zf, (size_t)P.n_int * 3));
+    chk(dalloc(m, &d.rg, (size_t)P.n_gamma * 3));
+    chk(dalloc(m, &d.zg, (size_t)P.n_gamma * 3));
+    chk(dalloc(m, &d.dg, (size_t)P.n_gamma * 3));
+    chk(dalloc(m, &d.delta, (size_t)P.n_free * 3));
+    chk(upload(m, &d.fvals, P.fvals));
+    chk(upload(m, &d.dvals, P.dvals));
+    chk(upload(m, &d.gidx, P.gidx));
+    chk(upload(m, &d.segs, P.segs));
+    chk(upload(m, &d.tasks, P.tasks));
+    chk(upload(m, &d.phases, P.phases));
+    chk(upload(m, &d.sub_off, P.sub_off));
+    chk(upload(m, &d.sub_fwd_ph, P.sub_fwd_ph));
+    chk(upload(m, &d.sub_bwd_ph, P.sub_bwd_ph));
+    chk(upload(m, &d.K_ptr, P.K_ptr));
+    chk(upload(m, &d.K_col, P.K_col));
+    chk(upload(m, &d.K_val, P.K_val));
+    chk(dalloc(m, &d.flags, 4));
+    if (r != VH_OK) {
+        free_device(m);
+        return r;
+    }
+    VH_HIP(hipMemset(d.v, 0, nv3 * sizeof(double)));
+    VH_HIP(hipMemset(d.flags, 0, 4 * sizeof(uint32_t)));
+    VH_HIP(hipMemset(d.delta, 0, (size_t)P.n_free * 3 * sizeof(double)));
+    m->fwd.clear();
+    m->bwd.clear();
+    for (int32_t ph : P.coarse_fwd_ph)
+        m->fwd.push_back({P.phases[ph].kind, P.phases[ph].task0, P.phases[ph].task1 - P.phases[ph].task0});
+    for (int32_t ph : P.coarse_bwd_ph)
+        m->bwd.push_back({P.phases[ph].kind, P.phases[ph].task0, P.phases[ph].task1 - P.phases[ph].task0});
+    m->refine = refine_steps;
+    VH_HIP(vh::launch_refresh_u(d, nullptr));
+    VH_HIP(hipDeviceSynchronize());
+    m->factored = true;
+    return VH_OK;
+}
+
+int vh_mesh_step(vh_mesh* m, int32_t n_frames, void* stream) {
+    VH_TRY(check_ready(m));
+    if (n_frames < 0) return fail(VH_EINVAL, "n_frames must be >= 0");
+    VH_TRY(set_device(m));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int32_t f = 0; f < n_frames; ++f) {
+        {
+            ProfScope ps(m, s, 0);
+            VH_HIP(vh::launch_predictor(m->dm, s));
+        }
+        for (int32_t k = 0; k < m->plan.pd_iters; ++k) VH_TRY(pd_iteration(m, s));
+        {
+            ProfScope ps(m, s, 7);
+            VH_HIP(vh::launch_velocity(m->dm, s));
+        }
+    }
+    return VH_OK;
+}
+
+int vh_mesh_read_state(vh_mesh* m, double* x, double* v, void* stream) {
+    VH_TRY(check_ready(m));
+    if (!x && !v) return fail(VH_EINVAL, "null output arrays");
+    VH_TRY(set_device(m));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (x) VH_TRY(get_user(m, m->dm.x, x, m->plan.nv, s));
+    if (v) VH_TRY(get_user(m, m->dm.v, v, m->plan.nv, s));
+    uint32_t flags[4];
+    VH_HIP(hipMemcpy(flags, m->dm.flags, sizeof(flags), hipMemcpyDeviceToHost));
+    if (flags[0]) return fail(VH_ENUMERIC, "non-finite value in the state");
+    return VH_OK;
+}
+
+int vh_mesh_write_state(vh_mesh* m, const double* x, const double* v, void* stream) {
+    VH_TRY(check_ready(m));
+    if (!x || !v) return fail(VH_EINVAL, "null input arrays");
+    VH_TRY(set_device(m));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    VH_TRY(put_user(m, x, m->dm.x, true, s));
+    VH_TRY(put_user(m, v, m->dm.v, false, s));
+    VH_HIP(vh::launch_refresh_u(m->dm, s));
+    VH_HIP(hipMemsetAsync(m->dm.flags, 0, sizeof(uint32_t), s));
+    VH_HIP(hipStreamSynchronize(s));
+    return VH_OK;
+}
+
+int vh_mesh_read_state_device(vh_mesh* m, double* x_dev, double* v_dev, void* stream) {
+    VH_TRY(check_ready(m));
+    VH_TRY(set_device(m));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (x_dev) VH_HIP(vh::launch_to_user(m->dm.nv, m->dm.perm, m->dm.x, x_dev, s));
+    if (v_dev) VH_HIP(vh::launch_to_user(m->dm.nv, m->dm.perm, m->dm.v, v_dev, s));
+    return VH_OK;
+}
+
+int vh_mesh_write_state_device(vh_mesh* m, const double* x_dev, const double* v_dev, void* stream) {
+    VH_TRY(check_ready(m));
+    if (!x_dev || !v_dev) return fail(VH_EINVAL, "null input arrays");
+    VH_TRY(set_device(m));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    VH_HIP(vh::launch_from_user(m->dm.nv, m->dm.n_free, m->dm.perm, x_dev, m->dm.X, m->dm.x, s));
+    VH_HIP(vh::launch_from_user(m->dm.nv, m->dm.n_free, m->dm.perm, v_dev, nullptr, m->dm.v, s));
+    VH_HIP(vh::launch_refresh_u(m->dm, s));
+    return VH_OK;
+}
+
+int vh_mesh_get_info(const vh_mesh* m, vh_mesh_info* info) {
+    if (!m || !info) return fail(VH_EINVAL, "null argument");
+    if (!m->factored) return fail(VH_ESTATE, "mesh is not prefactored");
+    const vh::Plan& P = m->plan;
+    info->nv = P.nv;
+    info->nt = P.nt;
+    info->n_free = P.n_free;
+    info->n_interior = P.n_int;
+    info->n_interface = P.n_gamma;
+    info->n_subdomains = P.D;
+    info->n_supernodes = (int32_t)P.sn.size();
+    info->n_coarse_levels = P.n_clevels;
+    info->max_interior_phases = P.max_sub_phases;
+    info->nnz_interior = P.nnz_int;
+    info->nnz_coarse = P.nnz_coarse;
+    info->device_bytes = m->bytes;
+    info->prefactor_seconds = P.seconds;
+    return VH_OK;
+}
+
+int vh_debug_local_step(vh_mesh* m, const double* x, double* T, double* sigma, double* s_out) {
+    VH_TRY(check_ready(m));
+    if (!x || !T) return fail(VH_EINVAL, "null argument");
+    VH_TRY(set_device(m));
+    vh::DevMesh& d = m->dm;
+    const int32_t nt = d.nt;
+    if (!d.dbg_T) {
+        VH_TRY(dalloc(m, &d.dbg_T, (size_t)nt * 9));
+        VH_TRY(dalloc(m, &d.dbg_sig, (size_t)nt * 3));
+        VH_TRY(dalloc(m, &d.dbg_s, (size_t)nt * 3));
+    }
+    VH_TRY(put_user(m, x, d.x, true, nullptr));
+    VH_HIP(vh::launch_refresh_u(d, nullptr));
+    VH_HIP(vh::launch_local(d, nullptr, true));
+    VH_HIP(hipDeviceSynchronize());
+    std::vector<float> hT((size_t)nt * 9), hs((size_t)nt * 3), hss((size_t)nt * 3);
+    VH_HIP(hipMemcpy(hT.data(), d.dbg_T, hT.size() * 4, hipMemcpyDeviceToHost));
+    VH_HIP(hipMemcpy(hs.data(), d.dbg_sig, hs.size() * 4, hipMemcpyDeviceToHost));
+    VH_HIP(hipMemcpy(hss.data(), d.dbg_s, hss.size() * 4, hipMemcpyDeviceToHost));
+    const auto& ep = m->plan.elem_perm;
+    for (int32_t e = 0; e < nt; ++e) {
+        const int32_t u = ep[e];
+        for (int k = 0; k < 9; ++k) T[(size_t)u * 9 + k] = hT[(size_t)e * 9 + k];
+        for (int k = 0; k < 3; ++k) {
+            if (sigma) sigma[(size_t)u * 3 + k] = hs[(size_t)e * 3 + k];
+            if (s_out) s_out[(size_t)u * 3 + k] = hss[(size_t)e * 3 + k];
+        }
+    }
+    return VH_OK;
+}
+
+int vh_debug_residual(vh_mesh* m, const double* x, const double* y, double* r) {
+    VH_TRY(check_ready(m));
+    if (!x || !y || !r) return fail(VH_EINVAL, "null argument");
+    VH_TRY(set_device(m));
+    vh::DevMesh& d = m->dm;
+    VH_TRY(put_user(m, x, d.x, true, nullptr));
+    VH_TRY(put_user(m, y, d.y, true, nullptr));
+    VH_HIP(vh::launch_refresh_u(d, nullptr));
+    VH_HIP(vh::launch_local(d, nullptr, false));
+    VH_HIP(vh::launch_residual(d, nullptr));
+    VH_HIP(hipDeviceSynchronize());
+    return get_user(m, d.r, r, d.n_free, nullptr);
+}
+
+int vh_debug_solve(vh_mesh* m, const double* rhs, double* out) {
+    VH_TRY(check_ready(m));
+    if (!rhs || !out) return fail(VH_EINVAL, "null argument");
+    VH_TRY(set_device(m));
+    vh::DevMesh& d = m->dm;
+    const vh::Plan& P = m->plan;
+    std::vector<double> st((size_t)P.n_free * 3);
+    for (int32_t i = 0; i < P.n_free; ++i)
+        for (int c = 0; c < 3; ++c) st[3 * i + c] = rhs[3 * P.perm[i] + c];
+    VH_HIP(hipMemcpy(d.r, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice));
+    VH_TRY(solve(m, nullptr, false, true));
+    VH_HIP(hipDeviceSynchronize());
+    return get_user(m, d.delta, out, d.n_free, nullptr);
+}
+
+int vh_mesh_profile(vh_mesh* m, uint32_t class_mask) {
+    VH_TRY(check_ready(m));
+    VH_TRY(set_device(m));
+    m->prof_mask = class_mask & 0xFFu;
+    m->ev_used = 0;
+    m->ev_pairs.clear();
+    return VH_OK;
+}
+
+int vh_mesh_profile_read(vh_mesh* m, double* ms, int64_t* launches) {
+    VH_TRY(check_ready(m));
+    if (!ms || !launches) return fail(VH_EINVAL, "null argument");
+    VH_TRY(set_device(m));
+    for (int c = 0; c < VH_PROFILE_CLASSES; ++c) {
+        ms[c] = 0.0;
+        launches[c] = 0;
+    }
+    for (const auto& pr : m->ev_pairs) {
+        VH_HIP(hipEventSynchronize(m->ev_pool[pr.first + 1]));
+        float t = 0.0f;
+        VH_HIP(hipEventElapsedTime(&t, m->ev_pool[pr.first], m->ev_pool[pr.first + 1]));
+        ms[pr.second] += t;
+        launches[pr.second] += 1;
+    }
+    m->ev_used = 0;
+    m->ev_pairs.clear();
+    return VH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1002 @@
+// Host prefactor of the decomposed PD global step (FP64).
+//
+// The global matrix of the PD global step (Sec. 7.1) is constant, so it is
+// factored once per material.  Because row c of F_e depends only on
+// coordinate c of the corners, the 3n x 3n matrix K is L (x) I_3 with the
+// scalar L = M/dt^2 + sum_e V_e (gs_e + gv_e) G_e, (G_e)_ab = gradN_a . gradN_b;
+// every solve here is a scalar solve with three right-hand-side columns.
+//
+// Domain decomposition (Sec. 7.2): the elements are split into subdomains, the
+// free vertices touched by one subdomain are its internal DOFs, the rest are
+// boundary (interface) DOFs shared by neighbours -- the paper's duplicated
+// boundary DOFs made unique as in Eq. (global_subspace).  With the interior
+// unknowns ordered first, block elimination gives the interior factors and the
+// interface Schur complement S = K^bb - sum_d K_d^bi (K_d^ii)^{-1} K_d^ib, which
+// is what the reduced system of the paper's boundary modes
+// Psi_d = -(K_d^ii)^{-1} K_d^ib (Eq. cms_boundary) becomes when the interior
+// eigenmodes are replaced by exact interior solves.  The interface is ordered
+// by the bisection tree (each interface vertex goes to the lowest tree node
+// whose subtree holds every subdomain touching it) and each interior by nested
+// dissection, so the whole factor is one supernodal tree: per supernode a dense
+// diagonal block (stored inverted, so the device solves are dot products
+// without a sequential chain) and a dense block of rows below it.
+#include "plan.h"
+
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace vh {
+
+namespace {
+
+constexpr int OK = 0, EINVAL_ = -1, ENOMEM_ = -2, ENOTSPD_ = -3;
+
+inline void tet_dm(const double* X, const int32_t* t, double Dm[9]) {
+    // Dm[r][k] = X[t[k+1]][r] - X[t[0]][r]
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) Dm[r * 3 + k] = X[t[k + 1] * 3 + r] - X[t[0] * 3 + r];
+}
+
+inline double det3(const double* A) {
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+inline void inv3(const double* A, double det, double* B) {
+    double id = 1.0 / det;
+    B[0] = (A[4] * A[8] - A[5] * A[7]) * id;
+    B[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+    B[3] = (A[5] * A[6] - A[3] * A[8]) * id;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+    B[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+    B[6] = (A[3] * A[7] - A[4] * A[6]) * id;
+    B[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+}
+
+// ---------------------------------------------------------------------------
+// Element partition: recursive breadth-first bisection of the face graph.
+// ---------------------------------------------------------------------------
+void face_adjacency(int32_t nt, const int32_t* tets, std::vector<int32_t>& ptr,
+                    std::vector<int32_t>& adj) {
+    struct Face {
+        int32_t a, b, c, e;
+    };
+    std::vector<Face> faces((size_t)nt * 4);
+    for (int32_t e = 0; e < nt; ++e) {
+        int32_t v[4] = {tets[4 * e], tets[4 * e + 1], tets[4 * e + 2], tets[4 * e + 3]};
+        std::sort(v, v + 4);
+        faces[4 * (size_t)e + 0] = {v[0], v[1], v[2], e};
+        faces[4 * (size_t)e + 1] = {v[0], v[1], v[3], e};
+        faces[4 * (size_t)e + 2] = {v[0], v[2], v[3], e};
+        faces[4 * (size_t)e + 3] = {v[1], v[2], v[3], e};
+    }
+    std::sort(faces.begin(), faces.end(), [](const Face& x, const Face& y) {
+        if (x.a != y.a) return x.a < y.a;
+        if (x.b != y.b) return x.b < y.b;
+        if (x.c != y.c) return x.c < y.c;
+        return x.e < y.e;
+    });
+    std::vector<std::pair<int32_t, int32_t>> pairs;
+    for (size_t i = 0; i + 1 < faces.size(); ++i) {
+        const Face& f = faces[i];
+        const Face& g = faces[i + 1];
+        if (f.a == g.a && f.b == g.b && f.c == g.c) {
+            pairs.push_back({f.e, g.e});
+            pairs.push_back({g.e, f.e});
+        }
+    }
+    std::sort(pairs.begin(), pairs.end());
+    ptr.assign(nt + 1, 0);
+    adj.resize(pairs.size());
+    for (size_t i = 0; i < pairs.size(); ++i) {
+        ptr[pairs[i].first + 1]++;
+        adj[i] = pairs[i].second;
+    }
+    for (int32_t i = 0; i < nt; ++i) ptr[i + 1] += ptr[i];
+}
+
+// BFS over elements with part[e] == p, from `start`, continuing from the
+// lowest unvisited member when a component ends.  members: ascending.
+void bfs_part(int32_t start, int32_t p, const std::vector<int32_t>& members,
+              const std::vector<int32_t>& part, const std::vector<int32_t>& ptr,
+              const std::vector<int32_t>& adj, std::vector<int32_t>& stamp, int32_t tok,
+              std::vector<int32_t>& order) {
+    order.clear();
+    order.reserve(members.size());
+    size_t head = 0, mi = 0;
+    stamp[start] = tok;
+    order.push_back(start);
+    while (order.size() < members.size()) {
+        while (head < order.size()) {
+            int32_t u = order[head++];
+            for (int32_t k = ptr[u]; k < ptr[u + 1]; ++k) {
+                int32_t w = adj[k];
+                if (part[w] == p && stamp[w] != tok) {
+                    stamp[w] = tok;
+                    order.push_back(w);
+                }
+            }
+        }
+        while (order.size() < members.size() && mi < members.size()) {
+            int32_t c = members[mi++];
+            if (stamp[c] != tok) {
+                stamp[c] = tok;
+                order.push_back(c);
+                break;
+            }
+        }
+    }
+}
+
+std::vector<int32_t> bisect_elements(int32_t nt, const int32_t* tets, int32_t D) {
+    std::vector<int32_t> ptr, adj;
+    face_adjacency(nt, tets, ptr, adj);
+    std::vector<int32_t> part(nt, 0), next(nt, 0), stamp(nt, -1), order, order2;
+    int32_t tok = 0;
+    for (int32_t nparts = 1; nparts < D; nparts *= 2) {
+        std::vector<std::vector<int32_t>> members(nparts);
+        for (int32_t e = 0; e < nt; ++e) members[part[e]].push_back(e);
+        for (int32_t p = 0; p < nparts; ++p) {
+            const auto& M = members[p];
+            if (M.empty()) continue;
+            bfs_part(M[0], p, M, part, ptr, adj, stamp, ++tok, order);
+            bfs_part(order.back(), p, M, part, ptr, adj, stamp, ++tok, order2);
+            size_t h = order2.size() / 2;
+            for (size_t i = 0; i < order2.size(); ++i) next[order2[i]] = 2 * p + (i < h ? 0 : 1);
+        }
+        part.swap(next);
+    }
+    return part;
+}
+
+// ---------------------------------------------------------------------------
+// Nested dissection of one subdomain's interior vertices.
+// ---------------------------------------------------------------------------
+struct NDNode {
+    std::vector<int32_t> verts;
+    int32_t left = -1, right = -1;
+};
+
+struct NDScratch {
+    std::vector<int32_t> mark, level;
+    int32_t tok = 0;
+};
+
+// BFS inside the set marked with `tok`; returns the visit order of the component.
+void bfs_set(int32_t s, int32_t tok, const std::vector<int32_t>& vptr,
+             const std::vector<int32_t>& vadj, NDScratch& sc, int32_t vtok,
+             std::vector<int32_t>& order) {
+    // mark[v] == tok: in the set and unvisited; set to vtok when visited
+    order.clear();
+    sc.mark[s] = vtok;
+    sc.level[s] = 0;
+    order.push_back(s);
+    size_t head = 0;
+    while (head < order.size()) {
+        int32_t u = order[head++];
+        for (int32_t k = vptr[u]; k < vptr[u + 1]; ++k) {
+            int32_t w = vadj[k];
+            if (sc.mark[w] == tok) {
+                sc.mark[w] = vtok;
+                sc.level[w] = sc.level[u] + 1;
+                order.push_back(w);
+            }
+        }
+    }
+    for (int32_t v : order) sc.mark[v] = tok;   // restore set membership
+}
+
+int32_t nd_build(std::vector<int32_t> S, int32_t leaf_max, const std::vector<int32_t>& vptr,
+                 const std::vector<int32_t>& vadj, NDScratch& sc, std::vector<NDNode>& T) {
+    int32_t id = (int32_t)T.size();
+    T.emplace_back();
+    if ((int32_t)S.size() <= leaf_max) {
+        std::sort(S.begin(), S.end());
+        T[id].verts = std::move(S);
+        return id;
+    }
+    int32_t tok = ++sc.tok;
+    int32_t vtok = ++sc.tok;
+    for (int32_t v : S) sc.mark[v] = tok;
+    int32_t smin = *std::min_element(S.begin(), S.end());
+    std::vector<int32_t> order;
+    bfs_set(smin, tok, vptr, vadj, sc, vtok, order);
+    std::vector<int32_t> A, B, sep;
+    if (order.size() < S.size()) {
+        // disconnected: first component versus the rest, no separator needed
+        int32_t ctok = ++sc.tok;
+        for (int32_t v : order) sc.mark[v] = ctok;
+        A = order;
+        for (int32_t v : S)
+            if (sc.mark[v] != ctok) B.push_back(v);
+    } else {
+        int32_t far = order.back();
+        vtok = ++sc.tok;
+        bfs_set(far, tok, vptr, vadj, sc, vtok, order);
+        int32_t maxlev = 0;
+        for (int32_t v : order) maxlev = std::max(maxlev, sc.level[v]);
+        std::vector<int32_t> cnt(maxlev + 2, 0);
+        for (int32_t v : order) cnt[sc.level[v]]++;
+        int32_t cum = 0, cut = maxlev;
+        for (int32_t l = 0; l <= maxlev; ++l) {
+            cum += cnt[l];
+            if (2 * cum >= (int32_t)S.size()) {
+                cut = l;
+                break;
+            }
+        }
+        if (cut == 0) cut = std::min(1, maxlev);
+        for (int32_t v : order) {
+            int32_t l = sc.level[v];
+            if (l < cut) A.push_back(v);
+            else if (l == cut) sep.push_back(v);
+            else B.push_back(v);
+        }
+    }
+    for (int32_t v : S) sc.mark[v] = 0;
+    std::sort(sep.begin(), sep.end());
+    T[id].verts = std::move(sep);
+    int32_t l = A.empty() ? -1 : nd_build(std::move(A), leaf_max, vptr, vadj, sc, T);
+    int32_t r = B.empty() ? -1 : nd_build(std::move(B), leaf_max, vptr, vadj, sc, T);
+    T[id].left = l;
+    T[id].right = r;
+    return id;
+}
+
+// ---------------------------------------------------------------------------
+// Dense kernels for the multifrontal factorization (column-major fronts).
+// ---------------------------------------------------------------------------
+// Factor the first n columns of the f x f symmetric front F (lower part,
+// column-major): F11 = L11 L11^T, L21 = F21 L11^{-T}, F22 -= L21 L21^T.
+int partial_cholesky(double* F, int32_t f, int32_t n, bool par) {
+    const int32_t NB = 32;
+    for (int32_t k0 = 0; k0 < n; k0 += NB) {
+        int32_t kb = std::min(NB, n - k0);
+        for (int32_t k = k0; k < k0 + kb; ++k) {
+            double* ck = F + (size_t)k * f;
+            double piv = ck[k];
+            if (!(piv > 0.0) || !std::isfinite(piv)) return ENOTSPD_;
+            double l = std::sqrt(piv);
+            ck[k] = l;
+            double il = 1.0 / l;
+            for (int32_t i = k + 1; i < f; ++i) ck[i] *= il;
+            for (int32_t j = k + 1; j < k0 + kb; ++j) {
+                double a = ck[j];
+                double* cj = F + (size_t)j * f;
+                for (int32_t i = j; i < f; ++i) cj[i] -= ck[i] * a;
+            }
+        }
+        int32_t j0 = k0 + kb;
+        auto update = [&](int32_t j) {
+            double* cj = F + (size_t)j * f;
+            for (int32_t k = k0; k < k0 + kb; ++k) {
+                const double* ck = F + (size_t)k * f;
+                double a = ck[j];
+                if (a == 0.0) continue;
+                for (int32_t i = j; i < f; ++i) cj[i] -= ck[i] * a;
+            }
+        };
+        if (par && (int64_t)(f - j0) * (f - j0) > 200000) {
+#pragma omp parallel for schedule(dynamic, 8)
+            for (int32_t j = j0; j < f; ++j) update(j);
+        } else {
+            for (int32_t j = j0; j < f; ++j) update(j);
+        }
+    }
+    return OK;
+}
+
+// Inverse of the n x n lower-triangular L (column-major with leading dim f)
+// into Ti (row-major n x n, lower part).
+void lower_inverse(const double* L, int32_t f, int32_t n, std::vector<double>& Ti, bool par) {
+    Ti.assign((size_t)n * n, 0.0);
+    auto col = [&](int32_t j) {
+        // solve L x = e_j, x[i] = 0 for i < j
+        std::vector<double> x(n, 0.0);
+        x[j] = 1.0 / L[(size_t)j * f + j];
+        for (int32_t i = j + 1; i < n; ++i) {
+            double s = 0.0;
+            for (int32_t k = j; k < i; ++k) s += L[(size_t)k * f + i] * x[k];
+            x[i] = -s / L[(size_t)i * f + i];
+        }
+        for (int32_t i = j; i < n; ++i) Ti[(size_t)i * n + j] = x[i];
+    };
+    if (par && n > 128) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int32_t j = 0; j < n; ++j) col(j);
+    } else {
+        for (int32_t j = 0; j < n; ++j) col(j);
+    }
+}
+
+}  // namespace
+
+int check_mesh(const double* X, int32_t nv, const int32_t* tets, int32_t nt, std::string& msg) {
+    if (nv <= 0 || nt <= 0 || !X || !tets) {
+        msg = "empty mesh";
+        return EINVAL_;
+    }
+    for (int32_t e = 0; e < nt; ++e) {
+        for (int c = 0; c < 4; ++c) {
+            int32_t v = tets[4 * e + c];
+            if (v < 0 || v >= nv) {
+                msg = "tet " + std::to_string(e) + " has a vertex id out of range";
+                return EINVAL_;
+            }
+        }
+        double Dm[9];
+        tet_dm(X, tets + 4 * e, Dm);
+        double vol = det3(Dm) / 6.0;
+        if (!(vol > 0.0)) {
+            msg = "tet " + std::to_string(e) + " has non-positive rest volume";
+            return EINVAL_;
+        }
+    }
+    return OK;
+}
+
+int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
+               const double* gamma_s, const double* gamma_v, const double* mass,
+               const uint8_t* pinned, const double* gravity, double dt, int32_t pd_iters,
+               int32_t D, int32_t refine_steps, int32_t leaf_max, Plan& P, std::string& msg) {
+    auto t_start = std::chrono::steady_clock::now();
+    if (D < 1 || (D & (D - 1))) {
+        msg = "n_subdomains must be a power of two >= 1";
+        return EINVAL_;
+    }
+    if (D > nt) {
+        msg = "more subdomains than elements";
+        return EINVAL_;
+    }
+    P = Plan();
+    P.nv = nv;
+    P.nt = nt;
+    P.D = D;
+    P.dt = dt;
+    P.pd_iters = pd_iters;
+    P.refine_steps = refine_steps;
+    for (int c = 0; c < 3; ++c) P.gravity[c] = gravity[c];
+    P.pinned_user.assign(pinned, pinned + nv);
+
+    // ---- partition and vertex classes --------------------------------------
+    std::vector<int32_t> part = bisect_elements(nt, tets, D);
+    int32_t kbits = 0;
+    while ((1 << kbits) < D) ++kbits;
+    std::vector<int32_t> first(nv, -1), xr(nv, 0);
+    for (int32_t e = 0; e < nt; ++e)
+        for (int c = 0; c < 4; ++c) {
+            int32_t v = tets[4 * e + c];
+            if (first[v] < 0) first[v] = part[e];
+            else xr[v] |= (part[e] ^ first[v]);
+        }
+    // heap node of each free vertex: D + p for interior of p, the LCA node otherwise
+    std::vector<int32_t> node(nv, -1);
+    for (int32_t v = 0; v < nv; ++v) {
+        if (pinned[v] || first[v] < 0) continue;
+        if (xr[v] == 0) {
+            node[v] = D + first[v];
+        } else {
+            int32_t bl = 32 - __builtin_clz((uint32_t)xr[v]);
+            int32_t lvl = kbits - bl;             // depth of the LCA
+            node[v] = (1 << lvl) + (first[v] >> bl);
+        }
+    }
+    for (int32_t v = 0; v < nv; ++v)
+        if (!pinned[v] && first[v] < 0) {
+            msg = "free vertex " + std::to_string(v) + " belongs to no element";
+            return EINVAL_;
+        }
+
+    // ---- vertex adjacency ------------------------------------------------------
+    std::vector<int32_t> vptr(nv + 1, 0), vadj;
+    {
+        std::vector<std::pair<int32_t, int32_t>> pr;
+        pr.reserve((size_t)nt * 12);
+        for (int32_t e = 0; e < nt; ++e)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    if (a != b) pr.push_back({tets[4 * e + a], tets[4 * e + b]});
+        std::sort(pr.begin(), pr.end());
+        pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+        vadj.resize(pr.size());
+        for (size_t i = 0; i < pr.size(); ++i) {
+            vptr[pr[i].first + 1]++;
+            vadj[i] = pr[i].second;
+        }
+        for (int32_t i = 0; i < nv; ++i) vptr[i + 1] += vptr[i];
+    }
+
+    // ---- orderings ---------------------------------------------------------------
+    std::vector<std::vector<int32_t>> sub_verts(D), gam_verts(D);   // gam_verts[h], h in [1, D)
+    for (int32_t v = 0; v < nv; ++v) {
+        if (node[v] < 0) continue;
+        if (node[v] >= D) sub_verts[node[v] - D].push_back(v);
+        else gam_verts[node[v]].push_back(v);
+    }
+    std::vector<std::vector<NDNode>> ndt(D);
+    std::vector<int32_t> ndroot(D, -1);
+#pragma omp parallel
+    {
+        NDScratch sc;
+        sc.mark.assign(nv, 0);
+        sc.level.assign(nv, 0);
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t d = 0; d < D; ++d)
+            if (!sub_verts[d].empty())
+                ndroot[d] = nd_build(sub_verts[d], leaf_max, vptr, vadj, sc, ndt[d]);
+    }
+
+    // supernodes in global postorder
+    std::vector<Supernode>& SN = P.sn;
+    std::vector<int32_t> order;   // internal id -> user vertex (free part)
+    order.reserve(nv);
+    P.sub_off.assign(D + 1, 0);
+    std::vector<int32_t> sub_root_sn(D, -1);
+    for (int32_t d = 0; d < D; ++d) {
+        P.sub_off[d] = (int32_t)order.size();
+        if (ndroot[d] < 0) continue;
+        // iterative postorder of the ND tree; returns supernode id of each ND node
+        std::vector<NDNode>& T = ndt[d];
+        std::vector<int32_t> snid(T.size(), -1);
+        std::vector<std::pair<int32_t, int>> st;
+        st.push_back({ndroot[d], 0});
+        while (!st.empty()) {
+            auto& top = st.back();
+            int32_t u = top.first;
+            if (top.second == 0) {
+                top.second = 1;
+                if (T[u].left >= 0) st.push_back({T[u].left, 0});
+            } else if (top.second == 1) {
+                top.second = 2;
+                if (T[u].right >= 0) st.push_back({T[u].right, 0});
+            } else {
+                st.pop_back();
+                if (!T[u].verts.empty()) {
+                    Supernode s;
+                    s.col0 = (int32_t)order.size();
+                    s.n = (int32_t)T[u].verts.size();
+                    s.sub = d;
+                    for (int32_t v : T[u].verts) order.push_back(v);
+                    snid[u] = (int32_t)SN.size();
+                    SN.push_back(std::move(s));
+                }
+            }
+        }
+        // parents inside the subdomain: nearest non-empty ND ancestor
+        std::vector<int32_t> ndpar(T.size(), -1);
+        for (size_t u = 0; u < T.size(); ++u) {
+            if (T[u].left >= 0) ndpar[T[u].left] = (int32_t)u;
+            if (T[u].right >= 0) ndpar[T[u].right] = (int32_t)u;
+        }
+        for (size_t u = 0; u < T.size(); ++u) {
+            if (snid[u] < 0) continue;
+            int32_t a = ndpar[u];
+            while (a >= 0 && snid[a] < 0) a = ndpar[a];
+            SN[snid[u]].parent = (a >= 0) ? snid[a] : -2;   // -2: attach to interface later
+        }
+    }
+    P.sub_off[D] = (int32_t)order.size();
+    P.n_int = (int32_t)order.size();
+    // interface supernodes in heap postorder
+    std::vector<int32_t> heap_sn(2 * D, -1);
+    {
+        std::vector<std::pair<int32_t, int>> st;
+        if (D > 1) st.push_back({1, 0});
+        while (!st.empty()) {
+            auto& top = st.back();
+            int32_t h = top.first;
+            if (top.second == 0) {
+                top.second = 1;
+                if (2 * h < D) st.push_back({2 * h, 0});
+            } else if (top.second == 1) {
+                top.second = 2;
+                if (2 * h + 1 < D) st.push_back({2 * h + 1, 0});
+            } else {
+                st.pop_back();
+                auto& gv = gam_verts[h];
+                if (!gv.empty()) {
+                    std::sort(gv.begin(), gv.end());
+                    Supernode s;
+                    s.col0 = (int32_t)order.size();
+                    s.n = (int32_t)gv.size();
+                    s.sub = -1;
+                    for (int32_t v : gv) order.push_back(v);
+                    heap_sn[h] = (int32_t)SN.size();
+                    SN.push_back(std::move(s));
+                }
+            }
+        }
+    }
+    P.n_free = (int32_t)order.size();
+    P.n_gamma = P.n_free - P.n_int;
+    auto heap_parent_sn = [&](int32_t h) {
+        h >>= 1;
+        while (h >= 1 && heap_sn[h] < 0) h >>= 1;
+        return h >= 1 ? heap_sn[h] : -1;
+    };
+    for (int32_t h = 1; h < D; ++h)
+        if (heap_sn[h] >= 0) SN[heap_sn[h]].parent = heap_parent_sn(h);
+    for (auto& s : SN)
+        if (s.parent == -2) s.parent = heap_parent_sn(D + s.sub);
+    for (int32_t t = 0; t < (int32_t)SN.size(); ++t)
+        if (SN[t].parent >= 0) SN[SN[t].parent].children.push_back(t);
+    // heights
+    for (int32_t t = 0; t < (int32_t)SN.size(); ++t) {
+        Supernode& s = SN[t];
+        if (s.sub >= 0) {
+            int32_t h = 0;
+            for (int32_t c : s.children) h = std::max(h, SN[c].height + 1);
+            s.height = h;
+        } else {
+            int32_t h = 0;
+            for (int32_t c : s.children)
+                if (SN[c].sub < 0) h = std::max(h, SN[c].clevel + 1);
+            s.clevel = h;
+            P.n_clevels = std::max(P.n_clevels, h + 1);
+        }
+    }
+
+    // internal numbering: free in `order`, then pinned
+    P.perm = order;
+    for (int32_t v = 0; v < nv; ++v)
+        if (pinned[v]) P.perm.push_back(v);
+    if ((int32_t)P.perm.size() != nv) {
+        msg = "vertex numbering failed";
+        return EINVAL_;
+    }
+    P.iperm.assign(nv, 0);
+    for (int32_t i = 0; i < nv; ++i) P.iperm[P.perm[i]] = i;
+    P.X_int.resize((size_t)nv * 3);
+    P.mass_int.resize(nv);
+    for (int32_t i = 0; i < nv; ++i) {
+        int32_t u = P.perm[i];
+        for (int c = 0; c < 3; ++c) P.X_int[3 * i + c] = X[3 * u + c];
+        P.mass_int[i] = mass[u];
+    }
+
+    // ---- elements: sorted by subdomain, SoA geometry -------------------------
+    P.elem_perm.resize(nt);
+    std::iota(P.elem_perm.begin(), P.elem_perm.end(), 0);
+    std::stable_sort(P.elem_perm.begin(), P.elem_perm.end(),
+                     [&](int32_t a, int32_t b) { return part[a] < part[b]; });
+    P.tet_soa.resize((size_t)nt * 4);
+    P.ginv_soa.resize((size_t)nt * 9);
+    P.w_soa.resize((size_t)nt * 2);
+    std::vector<double> Vol(nt), Gd((size_t)nt * 9);
+    for (int32_t e = 0; e < nt; ++e) {
+        int32_t u = P.elem_perm[e];
+        const int32_t* t = tets + 4 * u;
+        double Dm[9], G[9];
+        tet_dm(X, t, Dm);
+        double det = det3(Dm);
+        inv3(Dm, det, G);
+        Vol[e] = det / 6.0;
+        for (int c = 0; c < 4; ++c) P.tet_soa[(size_t)c * nt + e] = P.iperm[t[c]];
+        for (int k = 0; k < 9; ++k) {
+            P.ginv_soa[(size_t)k * nt + e] = (float)G[k];
+            Gd[(size_t)e * 9 + k] = G[k];
+        }
+        P.w_soa[e] = (float)(Vol[e] * gamma_s[u]);
+        P.w_soa[(size_t)nt + e] = (float)(Vol[e] * gamma_v[u]);
+    }
+
+    // ---- scatter incidence ---------------------------------------------------------
+    P.inc_ptr.assign(P.n_free + 1, 0);
+    for (int32_t c = 0; c < 4; ++c)
+        for (int32_t e = 0; e < nt; ++e) {
+            int32_t a = P.tet_soa[(size_t)c * nt + e];
+            if (a < P.n_free) P.inc_ptr[a + 1]++;
+        }
+    for (int32_t a = 0; a < P.n_free; ++a) P.inc_ptr[a + 1] += P.inc_ptr[a];
+    P.inc_slot.resize(P.inc_ptr[P.n_free]);
+    {
+        std::vector<int32_t> fill(P.inc_ptr.begin(), P.inc_ptr.end() - 1);
+        for (int32_t c = 0; c < 4; ++c)
+            for (int32_t e = 0; e < nt; ++e) {
+                int32_t a = P.tet_soa[(size_t)c * nt + e];
+                if (a < P.n_free) P.inc_slot[fill[a]++] = c * nt + e;
+            }
+        for (int32_t a = 0; a < P.n_free; ++a)
+            std::sort(P.inc_slot.begin() + P.inc_ptr[a], P.inc_slot.begin() + P.inc_ptr[a + 1]);
+    }
+
+    // ---- FP64 matrix on free unknowns (internal order) ------------------------------
+    const int32_t nf = P.n_free;
+    {
+        std::vector<std::vector<std::pair<int32_t, double>>> rows(nf);
+        for (int32_t e = 0; e < nt; ++e) {
+            double gr[4][3];
+            const double* G = &Gd[(size_t)e * 9];
+            for (int k = 0; k < 3; ++k) {
+                gr[0][k] = -(G[0 * 3 + k] + G[1 * 3 + k] + G[2 * 3 + k]);
+                for (int c = 1; c < 4; ++c) gr[c][k] = G[(c - 1) * 3 + k];
+            }
+            int32_t u = P.elem_perm[e];
+            double w = Vol[e] * (gamma_s[u] + gamma_v[u]);
+            for (int a = 0; a < 4; ++a) {
+                int32_t ia = P.tet_soa[(size_t)a * nt + e];
+                if (ia >= nf) continue;
+                for (int b = 0; b < 4; ++b) {
+                    int32_t ib = P.tet_soa[(size_t)b * nt + e];
+                    if (ib >= nf) continue;
+                    double g = gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2];
+                    rows[ia].push_back({ib, w * g});
+                }
+            }
+        }
+        P.K_ptr.assign(nf + 1, 0);
+        for (int32_t i = 0; i < nf; ++i) {
+            auto& r = rows[i];
+            r.push_back({i, P.mass_int[i] / (dt * dt)});
+            std::sort(r.begin(), r.end(),
+                      [](const auto& a, const auto& b) { return a.first < b.first; });
+            size_t w = 0;
+            for (size_t k = 0; k < r.size(); ++k) {
+                if (w > 0 && r[w - 1].first == r[k].first) r[w - 1].second += r[k].second;
+                else r[w++] = r[k];
+            }
+            r.resize(w);
+            P.K_ptr[i + 1] = P.K_ptr[i] + (int32_t)w;
+        }
+        P.K_col.resize(P.K_ptr[nf]);
+        P.K_val.resize(P.K_ptr[nf]);
+        for (int32_t i = 0; i < nf; ++i)
+            for (size_t k = 0; k < rows[i].size(); ++k) {
+                P.K_col[P.K_ptr[i] + k] = rows[i][k].first;
+                P.K_val[P.K_ptr[i] + k] = rows[i][k].second;
+            }
+    }
+
+    // ---- symbolic: rows below each supernode --------------------------------------
+    const int32_t nsn = (int32_t)SN.size();
+    auto symbolic = [&](int32_t t, std::vector<int32_t>& buf) {
+        Supernode& s = SN[t];
+        int32_t last = s.col0 + s.n - 1;
+        buf.clear();
+        for (int32_t c : s.children)
+            for (int32_t r : SN[c].rows)
+                if (r > last) buf.push_back(r);
+        for (int32_t j = s.col0; j <= last; ++j)
+            for (int32_t k = P.K_ptr[j]; k < P.K_ptr[j + 1]; ++k)
+                if (P.K_col[k] > last) buf.push_back(P.K_col[k]);
+        std::sort(buf.begin(), buf.end());
+        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+        s.rows = buf;
+    };
+    {
+        // interior supernodes: independent per subdomain (postorder inside)
+        std::vector<int32_t> sub_first(D + 1, nsn);
+        for (int32_t t = nsn - 1; t >= 0; --t)
+            if (SN[t].sub >= 0) sub_first[SN[t].sub] = t;
+#pragma omp parallel
+        {
+            std::vector<int32_t> buf;
+#pragma omp for schedule(dynamic, 1)
+            for (int32_t d = 0; d < D; ++d)
+                for (int32_t t = 0; t < nsn; ++t) {
+                    if (SN[t].sub != d) continue;
+                    symbolic(t, buf);
+                }
+        }
+        std::vector<int32_t> buf;
+        for (int32_t t = 0; t < nsn; ++t)
+            if (SN[t].sub < 0) symbolic(t, buf);
+        (void)sub_first;
+    }
+    // value offsets
+    int64_t fo = 0, dof = 0, go = 0;
+    for (int32_t t = 0; t < nsn; ++t) {
+        Supernode& s = SN[t];
+        int64_t n = s.n, m = (int64_t)s.rows.size();
+        int64_t tri = n * (n + 1) / 2;
+        int64_t& o = (s.sub >= 0) ? fo : dof;
+        s.tinv_off = o;
+        o += tri;
+        s.tinvT_off = o;
+        o += tri;
+        s.b_off = o;
+        o += m * n;
+        s.bT_off = o;
+        o += m * n;
+        s.rows_off = go;
+        go += m;
+        if (s.sub >= 0) P.nnz_int += tri + m * n;
+        else P.nnz_coarse += tri + m * n;
+    }
+    if (fo >= ((int64_t)1 << 31) || dof >= ((int64_t)1 << 31)) {
+        msg = "factor too large for 32-bit offsets";
+        return ENOMEM_;
+    }
+    try {
+        P.fvals.assign(fo, 0.0f);
+        P.dvals.assign(dof, 0.0);
+        P.gidx.resize(go);
+    } catch (...) {
+        msg = "host allocation of the factor failed";
+        return ENOMEM_;
+    }
+    for (int32_t t = 0; t < nsn; ++t)
+        std::copy(SN[t].rows.begin(), SN[t].rows.end(), P.gidx.begin() + SN[t].rows_off);
+
+    // ---- numeric: multifrontal FP64 --------------------------------------------------
+    std::vector<std::vector<double>> upd(nsn);
+    int err = OK;
+    auto numeric = [&](int32_t t, std::vector<int32_t>& pos, bool par) -> int {
+        Supernode& s = SN[t];
+        const int32_t n = s.n, m = (int32_t)s.rows.size(), f = n + m;
+        std::vector<double> F((size_t)f * f, 0.0);
+        for (int32_t a = 0; a < n; ++a) pos[s.col0 + a] = a;
+        for (int32_t b = 0; b < m; ++b) pos[s.rows[b]] = n + b;
+        for (int32_t a = 0; a < n; ++a) {
+            int32_t j = s.col0 + a;
+            for (int32_t k = P.K_ptr[j]; k < P.K_ptr[j + 1]; ++k) {
+                int32_t i = P.K_col[k];
+                if (i < j) continue;
+                F[(size_t)a * f + pos[i]] += P.K_val[k];
+            }
+        }
+        for (int32_t c : s.children) {
+            const Supernode& cs = SN[c];
+            const int32_t mc = (int32_t)cs.rows.size();
+            const std::vector<double>& U = upd[c];
+            for (int32_t b2 = 0; b2 < mc; ++b2) {
+                int32_t pb = pos[cs.rows[b2]];
+                for (int32_t a2 = b2; a2 < mc; ++a2)
+                    F[(size_t)pb * f + pos[cs.rows[a2]]] += U[(size_t)b2 * mc + a2];
+            }
+            std::vector<double>().swap(upd[c]);
+        }
+        int rc = partial_cholesky(F.data(), f, n, par);
+        if (rc != OK) return rc;
+        std::vector<double> Ti;
+        lower_inverse(F.data(), f, n, Ti, par);
+        auto store = [&](auto* vals) {
+            using T = std::remove_pointer_t<decltype(vals)>;
+            for (int32_t a = 0; a < n; ++a)
+                for (int32_t b = 0; b <= a; ++b)
+                    vals[s.tinv_off + (int64_t)a * (a + 1) / 2 + b] = (T)Ti[(size_t)a * n + b];
+            for (int32_t a = 0; a < n; ++a) {
+                int64_t off = s.tinvT_off + (int64_t)a * n - (int64_t)a * (a - 1) / 2;
+                for (int32_t i = a; i < n; ++i) vals[off + (i - a)] = (T)Ti[(size_t)i * n + a];
+            }
+            for (int32_t p = 0; p < m; ++p)
+                for (int32_t a = 0; a < n; ++a) {
+                    double v = F[(size_t)a * f + n + p];
+                    vals[s.b_off + (int64_t)p * n + a] = (T)v;
+                    vals[s.bT_off + (int64_t)a * m + p] = (T)v;
+                }
+        };
+        if (s.sub >= 0) store(P.fvals.data());
+        else store(P.dvals.data());
+        std::vector<double> U((size_t)m * m);
+        for (int32_t b = 0; b < m; ++b)
+            for (int32_t a = b; a < m; ++a) U[(size_t)b * m + a] = F[(size_t)(n + b) * f + n + a];
+        upd[t] = std::move(U);
+        return OK;
+    };
+#pragma omp parallel
+    {
+        std::vector<int32_t> pos(nf, 0);
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t d = 0; d < D; ++d) {
+            for (int32_t t = 0; t < nsn; ++t) {
+                if (SN[t].sub != d) continue;
+                int rc = numeric(t, pos, false);
+                if (rc != OK) {
+#pragma omp critical
+                    err = rc;
+                    break;
+                }
+            }
+        }
+    }
+    if (err != OK) {
+        msg = "non-positive pivot in an interior factor";
+        return err;
+    }
+    {
+        std::vector<int32_t> pos(nf, 0);
+        for (int32_t t = 0; t < nsn; ++t) {
+            if (SN[t].sub >= 0) continue;
+            int rc = numeric(t, pos, true);
+            if (rc != OK) {
+                msg = "non-positive pivot in the interface factor";
+                return rc;
+            }
+        }
+    }
+
+    // ---- solve programs ------------------------------------------------------------
+    // forward pull segments per row: for every supernode s and every row p of it
+    std::vector<std::vector<Seg>> pull_int(nf), pull_gam(nf);
+    for (int32_t s = 0; s < nsn; ++s) {
+        const Supernode& S = SN[s];
+        const int32_t m = (int32_t)S.rows.size();
+        for (int32_t p = 0; p < m; ++p) {
+            int32_t r = S.rows[p];
+            Seg g;
+            g.voff = (int32_t)(S.b_off + (int64_t)p * S.n);
+            g.len = S.n;
+            g.kind = (S.sub >= 0) ? 1 : 0;
+            if (S.sub >= 0) {
+                // interior source: x offset local to the subdomain for interior rows,
+                // global interior index for interface rows
+                g.xoff = (r < P.n_int) ? S.col0 - P.sub_off[S.sub] : S.col0;
+                pull_int[r].push_back(g);
+            } else {
+                g.xoff = S.col0 - P.n_int;
+                pull_gam[r].push_back(g);
+            }
+        }
+    }
+    auto add_task = [&](int32_t out, const std::vector<Seg>& sg) {
+        Task tk;
+        tk.out = out;
+        tk.seg0 = (int32_t)P.segs.size();
+        P.segs.insert(P.segs.end(), sg.begin(), sg.end());
+        tk.seg1 = (int32_t)P.segs.size();
+        tk.pad = 0;
+        P.tasks.push_back(tk);
+    };
+    auto begin_phase = [&](int32_t kind) {
+        Phase ph;
+        ph.kind = kind;
+        ph.task0 = (int32_t)P.tasks.size();
+        ph.task1 = ph.task0;
+        ph.pad = 0;
+        P.phases.push_back(ph);
+    };
+    auto end_phase = [&]() {
+        P.phases.back().task1 = (int32_t)P.tasks.size();
+        if (P.phases.back().task1 == P.phases.back().task0) P.phases.pop_back();
+    };
+    // interior programs
+    P.sub_fwd_ph.assign(D + 1, 0);
+    P.sub_bwd_ph.assign(D + 1, 0);
+    std::vector<std::vector<int32_t>> sub_sn(D);
+    for (int32_t t = 0; t < nsn; ++t)
+        if (SN[t].sub >= 0) sub_sn[SN[t].sub].push_back(t);
+    std::vector<Seg> one(1);
+    std::vector<int32_t> fwd_begin(D), bwd_begin(D), fwd_end(D), bwd_end(D);
+    for (int32_t d = 0; d < D; ++d) {
+        int32_t H = -1;
+        for (int32_t t : sub_sn[d]) H = std::max(H, SN[t].height);
+        const int32_t base = P.sub_off[d];
+        fwd_begin[d] = (int32_t)P.phases.size();
+        for (int32_t h = 0; h <= H; ++h) {
+            begin_phase(FWD_PULL);
+            for (int32_t t : sub_sn[d])
+                if (SN[t].height == h)
+                    for (int32_t a = 0; a < SN[t].n; ++a) {
+                        int32_t r = SN[t].col0 + a;
+                        if (!pull_int[r].empty()) add_task(r - base, pull_int[r]);
+                    }
+            end_phase();
+            begin_phase(FWD_TINV);
+            for (int32_t t : sub_sn[d])
+                if (SN[t].height == h)
+                    for (int32_t a = 0; a < SN[t].n; ++a) {
+                        one[0] = {(int32_t)(SN[t].tinv_off + (int64_t)a * (a + 1) / 2), a + 1,
+                                  SN[t].col0 - base, 1};
+                        add_task(SN[t].col0 + a - base, one);
+                    }
+            end_phase();
+        }
+        fwd_end[d] = (int32_t)P.phases.size();
+        P.max_sub_phases = std::max(P.max_sub_phases, fwd_end[d] - fwd_begin[d]);
+        P.max_sub_n = std::max(P.max_sub_n, P.sub_off[d + 1] - P.sub_off[d]);
+    }
+    for (int32_t d = 0; d < D; ++d) {
+        int32_t H = -1;
+        for (int32_t t : sub_sn[d]) H = std::max(H, SN[t].height);
+        const int32_t base = P.sub_off[d];
+        bwd_begin[d] = (int32_t)P.phases.size();
+        for (int32_t h = H; h >= 0; --h) {
+            begin_phase(BWD_PULL);
+            for (int32_t t : sub_sn[d])
+                if (SN[t].height == h) {
+                    const int32_t m = (int32_t)SN[t].rows.size();
+                    for (int32_t a = 0; a < SN[t].n; ++a) {
+                        if (m > 0) {
+                            one[0] = {(int32_t)(SN[t].bT_off + (int64_t)a * m), m,
+                                      (int32_t)SN[t].rows_off, 1};
+                            add_task(SN[t].col0 + a - base, one);
+                        } else {
+                            add_task(SN[t].col0 + a - base, std::vector<Seg>());
+                        }
+                    }
+                }
+            end_phase();
+            begin_phase(BWD_TINV);
+            for (int32_t t : sub_sn[d])
+                if (SN[t].height == h) {
+                    const int32_t n = SN[t].n;
+                    for (int32_t a = 0; a < n; ++a) {
+                        one[0] = {(int32_t)(SN[t].tinvT_off + (int64_t)a * n - (int64_t)a * (a - 1) / 2),
+                                  n - a, SN[t].col0 + a - base, 1};
+                        add_task(SN[t].col0 + a - base, one);
+                    }
+                }
+            end_phase();
+        }
+        bwd_end[d] = (int32_t)P.phases.size();
+        P.max_sub_phases = std::max(P.max_sub_phases, bwd_end[d] - bwd_begin[d]);
+    }
+    // per-subdomain phase ranges: [fwd_begin, fwd_end) and [bwd_begin, bwd_end)
+    for (int32_t d = 0; d < D; ++d) {
+        P.sub_fwd_ph[d] = fwd_begin[d];
+        P.sub_bwd_ph[d] = bwd_begin[d];
+    }
+    P.sub_fwd_ph[D] = D > 0 ? fwd_end[D - 1] : 0;
+    P.sub_bwd_ph[D] = D > 0 ? bwd_end[D - 1] : 0;
+    // (ranges are contiguous: subdomain d's forward phases end where d+1's begin)
+
+    // interface program: one launch per phase
+    auto close_into = [&](std::vector<int32_t>& lst) {
+        P.phases.back().task1 = (int32_t)P.tasks.size();
+        if (P.phases.back().task1 == P.phases.back().task0) P.phases.pop_back();
+        else lst.push_back((int32_t)P.phases.size() - 1);
+    };
+    P.coarse_fwd_ph.clear();
+    P.coarse_bwd_ph.clear();
+    for (int32_t l = 0; l < P.n_clevels; ++l) {
+        begin_phase(FWD_PULL);
+        for (int32_t t = 0; t < nsn; ++t)
+            if (SN[t].sub < 0 && SN[t].clevel == l)
+                for (int32_t a = 0; a < SN[t].n; ++a) {
+                    int32_t r = SN[t].col0 + a;
+                    std::vector<Seg> sg = pull_int[r];
+                    sg.insert(sg.end(), pull_gam[r].begin(), pull_gam[r].end());
+                    if (!sg.empty()) add_task(r - P.n_int, sg);
+                }
+        close_into(P.coarse_fwd_ph);
+        begin_phase(FWD_TINV);
+        for (int32_t t = 0; t < nsn; ++t)
+            if (SN[t].sub < 0 && SN[t].clevel == l)
+                for (int32_t a = 0; a < SN[t].n; ++a) {
+                    one[0] = {(int32_t)(SN[t].tinv_off + (int64_t)a * (a + 1) / 2), a + 1,
+                              SN[t].col0 - P.n_int, 0};
+                    add_task(SN[t].col0 + a - P.n_int, one);
+                }
+        close_into(P.coarse_fwd_ph);
+    }
+    for (int32_t l = P.n_clevels - 1; l >= 0; --l) {
+        begin_phase(BWD_PULL);
+        for (int32_t t = 0; t < nsn; ++t)
+            if (SN[t].sub < 0 && SN[t].clevel == l) {
+                const int32_t m = (int32_t)SN[t].rows.size();
+                for (int32_t a = 0; a < SN[t].n; ++a) {
+                    if (m > 0) {
+                        one[0] = {(int32_t)(SN[t].bT_off + (int64_t)a * m), m,
+                                  (int32_t)SN[t].rows_off, 0};
+                        add_task(SN[t].col0 + a - P.n_int, one);
+                    } else {
+                        add_task(SN[t].col0 + a - P.n_int, std::vector<Seg>());
+                    }
+                }
+            }
+        close_into(P.coarse_bwd_ph);
+        begin_phase(BWD_TINV);
+        for (int32_t t = 0; t < nsn; ++t)
+            if (SN[t].sub < 0 && SN[t].clevel == l) {
+                const int32_t n = SN[t].n;
+                for (int32_t a = 0; a < n; ++a) {
+                    one[0] = {(int32_t)(SN[t].tinvT_off + (int64_t)a * n - (int64_t)a * (a - 1) / 2),
+                              n - a, SN[t].col0 + a - P.n_int, 0};
+                    add_task(SN[t].col0 + a - P.n_int, one);
+                }
+            }
+        close_into(P.coarse_bwd_ph);
+    }
+    P.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    return OK;
+}
+
+}  // namespace vh

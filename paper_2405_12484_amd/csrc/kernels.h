@@ -1,0 +1,73 @@
+// Device kernels of the PD step (gfx950).  Launch helpers are declared here
+// and defined in kernels.hip; every launch takes the caller's stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.h"
+
+namespace vh {
+
+// Device-resident copy of a Plan plus the state of one garment.
+struct DevMesh {
+    int32_t nv = 0, nt = 0, n_free = 0, n_int = 0, n_gamma = 0, D = 1;
+    int32_t max_sub_n = 0;
+    double dt = 0, g[3] = {0, 0, 0};
+    // state, internal order, AoS xyz
+    double *x = nullptr, *v = nullptr, *xprev = nullptr, *y = nullptr, *X = nullptr;
+    double* mass = nullptr;
+    int32_t* perm = nullptr;        // internal vertex -> user vertex
+    float4* u = nullptr;            // float(x - X), w unused
+    // elements
+    int32_t* tet = nullptr;         // [4][nt]
+    float* ginv = nullptr;          // [9][nt]
+    float* w = nullptr;             // [2][nt]
+    float* fout = nullptr;          // [3][4 nt] element forces per (corner, element) slot
+    int32_t *inc_ptr = nullptr, *inc_slot = nullptr;
+    // solver
+    double* r = nullptr;            // [n_free][3] residual
+    float* zf = nullptr;            // [n_int][3] interior forward result
+    double *rg = nullptr, *zg = nullptr, *dg = nullptr;   // [n_gamma][3] interface work
+    double* delta = nullptr;        // [n_free][3] last correction
+    float* fvals = nullptr;
+    double* dvals = nullptr;
+    int32_t* gidx = nullptr;
+    Seg* segs = nullptr;
+    Task* tasks = nullptr;
+    Phase* phases = nullptr;
+    int32_t *sub_off = nullptr, *sub_fwd_ph = nullptr, *sub_bwd_ph = nullptr;
+    int32_t *K_ptr = nullptr, *K_col = nullptr;
+    double* K_val = nullptr;
+    uint32_t* flags = nullptr;      // [0] non-finite seen, [1] out-of-regime projections, [2] inverted
+    // debug outputs of the local step (allocated on demand)
+    float *dbg_T = nullptr, *dbg_sig = nullptr, *dbg_s = nullptr;
+};
+
+// Host copies of the interface phase launch shapes.
+struct PhaseLaunch {
+    int32_t kind, task0, ntasks;
+};
+
+hipError_t launch_predictor(const DevMesh& m, hipStream_t s);
+hipError_t launch_local(const DevMesh& m, hipStream_t s, bool debug);
+hipError_t launch_residual(const DevMesh& m, hipStream_t s);
+hipError_t launch_interior_fwd(const DevMesh& m, hipStream_t s);
+hipError_t launch_interface_phase(const DevMesh& m, const PhaseLaunch& ph, hipStream_t s);
+hipError_t launch_interior_bwd(const DevMesh& m, hipStream_t s, bool apply, bool keep_delta);
+hipError_t launch_refine_residual(const DevMesh& m, hipStream_t s);
+hipError_t launch_velocity(const DevMesh& m, hipStream_t s);
+
+}  // namespace vh
+
+namespace vh {
+// dst_user[perm[i]] = src_int[i] (3 doubles per vertex), i < nv
+hipError_t launch_to_user(int32_t nv, const int32_t* perm, const double* src_int, double* dst_user,
+                          hipStream_t s);
+// dst_int[i] = i < n_free ? src_user[perm[i]] : fixed (X for positions, 0 for velocities)
+hipError_t launch_from_user(int32_t nv, int32_t n_free, const int32_t* perm, const double* src_user,
+                            const double* X_or_null, double* dst_int, hipStream_t s);
+// u = float(x - X)
+hipError_t launch_refresh_u(const DevMesh& m, hipStream_t s);
+}  // namespace vh

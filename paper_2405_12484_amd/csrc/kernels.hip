@@ -1,0 +1,742 @@
+// HIP kernels of the projective-dynamics step for CDNA4 (gfx950, wave64).
+//
+//   k_predict   Sec. 7: inertial target y = x* + dt v* + dt^2 g, x^(0) = y
+//   k_local     Sec. 7.1 local step: per tet F, signed SVD, polar rotation R,
+//               volume projection (Eq. vol_pre), residual stress and forces
+//   k_residual  Sec. 7.1 global step right-hand side, as the residual
+//               r = b - K x^(k), gathered per vertex without atomics
+//   k_interior_fwd / k_iface / k_interior_bwd
+//               Sec. 7.2 decomposed solve K d = r: interior triangular
+//               solves (one workgroup per subdomain, vectors in LDS, FP32),
+//               interface solve (FP64, one launch per tree level), interior
+//               back-substitution with the interface values, x += d
+//   k_refine    r -= K d in FP64 (optional refinement passes)
+//   k_velocity  BDF1 velocity, non-finite check
+#include "kernels.h"
+
+namespace vh {
+
+namespace {
+
+constexpr int BLK = 256;
+
+// ---------------------------------------------------------------------------
+// 3x3 signed SVD in FP32: cyclic Jacobi eigen-decomposition of F^T F for W,
+// then Givens QR of F W for U and the (signed) singular values; McAdams et al.
+// (2011), "Computing the singular value decomposition of 3x3 matrices with
+// minimal branching and elementary floating point operations", with exact
+// Jacobi angles in place of their approximate quaternion ones.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void jacobi_pair(float& app, float& aqq, float& apq, float& arp,
+                                            float& arq, float* W, int p, int q) {
+    if (apq == 0.0f) return;
+    float tau = (aqq - app) / (2.0f * apq);
+    float t = copysignf(1.0f, tau) / (fabsf(tau) + sqrtf(1.0f + tau * tau));
+    float c = rsqrtf(1.0f + t * t);
+    float s = t * c;
+    app -= t * apq;
+    aqq += t * apq;
+    apq = 0.0f;
+    float rp = c * arp - s * arq;
+    float rq = s * arp + c * arq;
+    arp = rp;
+    arq = rq;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float wp = W[i * 3 + p], wq = W[i * 3 + q];
+        W[i * 3 + p] = c * wp - s * wq;
+        W[i * 3 + q] = s * wp + c * wq;
+    }
+}
+
+__device__ __forceinline__ void swap_cols(float* W, int a, int b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float t = W[i * 3 + a];
+        W[i * 3 + a] = W[i * 3 + b];
+        W[i * 3 + b] = -t;   // keep det = +1
+    }
+}
+
+// rows p, q of B (3x3 row-major): zero B[q][col] against B[p][col]; U <- U G^T
+__device__ __forceinline__ void givens_rows(float* B, float* U, int p, int q, int col) {
+    float a = B[p * 3 + col], b = B[q * 3 + col];
+    float r2 = a * a + b * b;
+    float c = 1.0f, s = 0.0f;
+    if (r2 > 1e-37f) {
+        float ir = rsqrtf(r2);
+        c = a * ir;
+        s = b * ir;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        float bp = B[p * 3 + j], bq = B[q * 3 + j];
+        B[p * 3 + j] = c * bp + s * bq;
+        B[q * 3 + j] = -s * bp + c * bq;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float up = U[i * 3 + p], uq = U[i * 3 + q];
+        U[i * 3 + p] = c * up + s * uq;
+        U[i * 3 + q] = -s * up + c * uq;
+    }
+}
+
+__device__ __forceinline__ void svd3(const float* F, float* U, float* sig, float* W) {
+    // A = F^T F
+    float a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float f0 = F[k * 3 + 0], f1 = F[k * 3 + 1], f2 = F[k * 3 + 2];
+        a00 += f0 * f0;
+        a01 += f0 * f1;
+        a02 += f0 * f2;
+        a11 += f1 * f1;
+        a12 += f1 * f2;
+        a22 += f2 * f2;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) W[i] = (i % 4 == 0) ? 1.0f : 0.0f;
+#pragma unroll
+    for (int sweep = 0; sweep < 5; ++sweep) {
+        jacobi_pair(a00, a11, a01, a02, a12, W, 0, 1);   // r = 2
+        jacobi_pair(a00, a22, a02, a01, a12, W, 0, 2);   // r = 1: a10 = a01, a12 -> a21
+        jacobi_pair(a11, a22, a12, a01, a02, W, 1, 2);   // r = 0: a01, a02
+    }
+    // sort eigenvalues descending (columns of W follow)
+    float l0 = a00, l1 = a11, l2 = a22, t;
+    if (l0 < l1) { t = l0; l0 = l1; l1 = t; swap_cols(W, 0, 1); }
+    if (l0 < l2) { t = l0; l0 = l2; l2 = t; swap_cols(W, 0, 2); }
+    if (l1 < l2) { t = l1; l1 = l2; l2 = t; swap_cols(W, 1, 2); }
+    // B = F W, QR by Givens
+    float B[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            B[i * 3 + j] = F[i * 3 + 0] * W[0 * 3 + j] + F[i * 3 + 1] * W[1 * 3 + j] + F[i * 3 + 2] * W[2 * 3 + j];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) U[i] = (i % 4 == 0) ? 1.0f : 0.0f;
+    givens_rows(B, U, 0, 1, 0);
+    givens_rows(B, U, 0, 2, 0);
+    givens_rows(B, U, 1, 2, 1);
+    sig[0] = B[0];
+    sig[1] = B[4];
+    sig[2] = B[8];
+}
+
+// s - sigma on the + branch s(mu) = (sigma + sqrt(sigma^2 + 4 mu)) / 2, written
+// without cancellation; returns the root distance q = sqrt(sigma^2 + 4 mu).
+__device__ __forceinline__ float plus_delta(float sg, float mu, float& q) {
+    q = sqrtf(fmaxf(sg * sg + 4.0f * mu, 0.0f));
+    if (sg >= 0.0f) return 2.0f * mu / (q + sg);
+    float s = 2.0f * mu / (q - sg);
+    return s - sg;
+}
+
+// Nearest volume-preserving singular values (Eq. vol_pre): the Lagrange
+// condition gives s_i (s_i - sigma_i) = mu for all i; Newton on
+// h(mu) = sum ln s_i(mu) from mu = 0, at most 8 steps, stop when
+// |s1 s2 s3 - 1| < 1e-7.  Returns ds_i = s_i - sigma_i.
+__device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_of_regime) {
+    const float lo = (sg[2] > 0.0f) ? -0.25f * sg[2] * sg[2] : 0.0f;
+    float mu = (sg[2] > 0.0f) ? 0.0f : 0.25f;
+    float q[3], s[3];
+#pragma unroll 1
+    for (int it = 0; it < 8; ++it) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ds[i] = plus_delta(sg[i], mu, q[i]);
+            s[i] = sg[i] + ds[i];
+        }
+        float p = s[0] * s[1] * s[2];
+        if (fabsf(p - 1.0f) < 1e-7f) break;
+        float h = logf(p);
+        float hp = 1.0f / (q[0] * s[0]) + 1.0f / (q[1] * s[1]) + 1.0f / (q[2] * s[2]);
+        float mun = mu - h / hp;
+        if (!(mun > lo)) mun = 0.5f * (mu + lo);
+        mu = mun;
+        if (it == 7) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                ds[i] = plus_delta(sg[i], mu, q[i]);
+                s[i] = sg[i] + ds[i];
+            }
+        }
+    }
+    out_of_regime = (sg[0] * sg[1] * sg[2] >= 2.0f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (s[i] < 0.01f) {
+            out_of_regime = true;
+            ds[i] = 0.01f - sg[i];
+        }
+}
+
+template <bool DBG>
+__global__ __launch_bounds__(BLK) void k_local(int32_t nt, const int32_t* __restrict__ tet,
+                                               const float* __restrict__ ginv,
+                                               const float* __restrict__ w,
+                                               const float4* __restrict__ u,
+                                               float* __restrict__ fout, uint32_t* flags,
+                                               float* dT, float* dsig, float* ds_out) {
+    const int32_t e = blockIdx.x * BLK + threadIdx.x;
+    if (e >= nt) return;
+    const int32_t i0 = tet[e], i1 = tet[nt + e], i2 = tet[2 * nt + e], i3 = tet[3 * nt + e];
+    const float4 u0 = u[i0], u1 = u[i1], u2 = u[i2], u3 = u[i3];
+    float G[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) G[k] = ginv[k * nt + e];
+    const float ws = w[e], wv = w[nt + e];
+    // displacement differences, columns k = corners 1..3
+    const float Du[3][3] = {{u1.x - u0.x, u2.x - u0.x, u3.x - u0.x},
+                            {u1.y - u0.y, u2.y - u0.y, u3.y - u0.y},
+                            {u1.z - u0.z, u2.z - u0.z, u3.z - u0.z}};
+    float F[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            F[r * 3 + j] = (r == j ? 1.0f : 0.0f) + Du[r][0] * G[0 * 3 + j] + Du[r][1] * G[1 * 3 + j] +
+                           Du[r][2] * G[2 * 3 + j];
+    float U[9], W[9], sg[3], dsv[3];
+    svd3(F, U, sg, W);
+    bool oor = false;
+    proj_sl3(sg, dsv, oor);
+    // residual stress T = U diag(ws (1 - sigma) + wv (s - sigma)) W^T = P - (ws + wv) F
+    float d0 = ws * (1.0f - sg[0]) + wv * dsv[0];
+    float d1 = ws * (1.0f - sg[1]) + wv * dsv[1];
+    float d2 = ws * (1.0f - sg[2]) + wv * dsv[2];
+    float T[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            T[i * 3 + j] = U[i * 3 + 0] * d0 * W[j * 3 + 0] + U[i * 3 + 1] * d1 * W[j * 3 + 1] +
+                           U[i * 3 + 2] * d2 * W[j * 3 + 2];
+    // corner forces f_c = T gradN_c, gradN_c = row c-1 of Dm^{-1}, f_0 = -(f_1+f_2+f_3)
+    const int32_t nt4 = 4 * nt;
+    float s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int c = 1; c < 4; ++c) {
+        float fx = T[0] * G[(c - 1) * 3 + 0] + T[1] * G[(c - 1) * 3 + 1] + T[2] * G[(c - 1) * 3 + 2];
+        float fy = T[3] * G[(c - 1) * 3 + 0] + T[4] * G[(c - 1) * 3 + 1] + T[5] * G[(c - 1) * 3 + 2];
+        float fz = T[6] * G[(c - 1) * 3 + 0] + T[7] * G[(c - 1) * 3 + 1] + T[8] * G[(c - 1) * 3 + 2];
+        fout[c * nt + e] = fx;
+        fout[nt4 + c * nt + e] = fy;
+        fout[2 * nt4 + c * nt + e] = fz;
+        s0 += fx;
+        s1 += fy;
+        s2 += fz;
+    }
+    fout[e] = -s0;
+    fout[nt4 + e] = -s1;
+    fout[2 * nt4 + e] = -s2;
+    const bool inv = sg[2] <= 0.0f;
+    if (__builtin_expect(oor || inv, 0)) {
+        if (oor) atomicAdd(&flags[1], 1u);
+        if (inv) atomicAdd(&flags[2], 1u);
+    }
+    if (DBG) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) dT[(size_t)e * 9 + k] = T[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            dsig[(size_t)e * 3 + k] = sg[k];
+            ds_out[(size_t)e * 3 + k] = sg[k] + dsv[k];
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_predict(int32_t nv, int32_t n_free, double dt, double gx,
+                                                 double gy, double gz, double* __restrict__ x,
+                                                 const double* __restrict__ v,
+                                                 double* __restrict__ xprev, double* __restrict__ y,
+                                                 const double* __restrict__ X,
+                                                 float4* __restrict__ u) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= nv) return;
+    const double g[3] = {gx, gy, gz};
+    float du[3];
+    if (i < n_free) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double xv = x[3 * i + c];
+            double yv = xv + dt * v[3 * i + c] + dt * dt * g[c];
+            xprev[3 * i + c] = xv;
+            y[3 * i + c] = yv;
+            x[3 * i + c] = yv;
+            du[c] = (float)(yv - X[3 * i + c]);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double Xv = X[3 * i + c];
+            xprev[3 * i + c] = Xv;
+            y[3 * i + c] = Xv;
+            x[3 * i + c] = Xv;
+            du[c] = 0.0f;
+        }
+    }
+    u[i] = make_float4(du[0], du[1], du[2], 0.0f);
+}
+
+// r_a = m_a (y_a - x_a) / dt^2 + sum over incident (corner, element) slots of
+// the element forces (fixed summation order: slots ascending).
+__global__ __launch_bounds__(BLK) void k_residual(int32_t n_free, int32_t nt4,
+                                                  const int32_t* __restrict__ inc_ptr,
+                                                  const int32_t* __restrict__ inc_slot,
+                                                  const float* __restrict__ fout,
+                                                  const double* __restrict__ mass,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ y, double inv_dt2,
+                                                  double* __restrict__ r) {
+    const int32_t a = blockIdx.x * BLK + threadIdx.x;
+    if (a >= n_free) return;
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    const int32_t j1 = inc_ptr[a + 1];
+    for (int32_t j = inc_ptr[a]; j < j1; ++j) {
+        const int32_t s = inc_slot[j];
+        fx += fout[s];
+        fy += fout[nt4 + s];
+        fz += fout[2 * nt4 + s];
+    }
+    const double m = mass[a] * inv_dt2;
+    r[3 * a + 0] = m * (y[3 * a + 0] - x[3 * a + 0]) + (double)fx;
+    r[3 * a + 1] = m * (y[3 * a + 1] - x[3 * a + 1]) + (double)fy;
+    r[3 * a + 2] = m * (y[3 * a + 2] - x[3 * a + 2]) + (double)fz;
+}
+
+// ---------------------------------------------------------------------------
+// Decomposed solve
+// ---------------------------------------------------------------------------
+constexpr int IG = 16;                 // lanes per task in the interior kernels
+
+template <int WIDTH, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int off = WIDTH / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WIDTH);
+    return v;
+}
+
+struct SolveArgs {
+    int32_t n_int, n_gamma, D;
+    const int32_t *sub_off, *sub_fwd_ph, *sub_bwd_ph;
+    const Phase* phases;
+    const Task* tasks;
+    const Seg* segs;
+    const float* fvals;
+    const double* dvals;
+    const int32_t* gidx;
+    const double* r;
+    float* zf;
+    double *rg, *zg, *dg, *delta, *x;
+    const double* X;
+    float4* u;
+};
+
+__global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a, int32_t max_n) {
+    extern __shared__ float sm[];
+    float* R = sm;
+    float* Z = sm + 3 * max_n;
+    const int32_t d = blockIdx.x;
+    const int32_t base = a.sub_off[d];
+    const int32_t n = a.sub_off[d + 1] - base;
+    const int tid = threadIdx.x;
+    for (int32_t i = tid; i < 3 * n; i += BLK) {
+        R[i] = (float)a.r[3 * base + i];
+        Z[i] = 0.0f;
+    }
+    // this block also copies a slice of the interface residual into the work vector
+    const int32_t chunk = (a.n_gamma + a.D - 1) / a.D;
+    const int32_t g0 = d * chunk, g1 = min(a.n_gamma, g0 + chunk);
+    for (int32_t i = 3 * g0 + tid; i < 3 * g1; i += BLK) a.rg[i] = a.r[3 * a.n_int + i];
+    __syncthreads();
+    const int grp = tid / IG, lane = tid % IG;
+    constexpr int NGRP = BLK / IG;
+    const int32_t ph1 = a.sub_fwd_ph[d + 1];
+    for (int32_t ph = a.sub_fwd_ph[d]; ph < ph1; ++ph) {
+        const Phase P = a.phases[ph];
+        const float* Xv = (P.kind == FWD_PULL) ? Z : R;
+        for (int32_t t = P.task0 + grp; t < P.task1; t += NGRP) {
+            const Task T = a.tasks[t];
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+            for (int32_t g = T.seg0; g < T.seg1; ++g) {
+                const Seg S = a.segs[g];
+                for (int32_t k = lane; k < S.len; k += IG) {
+                    const float v = a.fvals[S.voff + k];
+                    const float* xp = Xv + 3 * (S.xoff + k);
+                    s0 += v * xp[0];
+                    s1 += v * xp[1];
+                    s2 += v * xp[2];
+                }
+            }
+            s0 = group_sum<IG>(s0);
+            s1 = group_sum<IG>(s1);
+            s2 = group_sum<IG>(s2);
+            if (lane == 0) {
+                if (P.kind == FWD_PULL) {
+                    R[3 * T.out + 0] -= s0;
+                    R[3 * T.out + 1] -= s1;
+                    R[3 * T.out + 2] -= s2;
+                } else {
+                    Z[3 * T.out + 0] = s0;
+                    Z[3 * T.out + 1] = s1;
+                    Z[3 * T.out + 2] = s2;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int32_t i = tid; i < 3 * n; i += BLK) a.zf[3 * base + i] = Z[i];
+}
+
+// One wave per task.  FWD_PULL: rg[o] -= sum; FWD_TINV: zg[o] = sum;
+// BWD_PULL: rg[o] = zg[o] - sum (gathered dg); BWD_TINV: dg[o] = sum.
+__global__ __launch_bounds__(BLK) void k_iface(SolveArgs a, int32_t kind, int32_t task0,
+                                               int32_t ntasks) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int32_t t = blockIdx.x * (BLK / 64) + wave;
+    if (t >= ntasks) return;
+    const Task T = a.tasks[task0 + t];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int32_t g = T.seg0; g < T.seg1; ++g) {
+        const Seg S = a.segs[g];
+        if (kind == FWD_PULL && S.kind == 1) {
+            for (int32_t k = lane; k < S.len; k += 64) {
+                const double v = (double)a.fvals[S.voff + k];
+                const float* xp = a.zf + 3 * (S.xoff + k);
+                s0 += v * (double)xp[0];
+                s1 += v * (double)xp[1];
+                s2 += v * (double)xp[2];
+            }
+        } else if (kind == BWD_PULL) {
+            for (int32_t k = lane; k < S.len; k += 64) {
+                const double v = a.dvals[S.voff + k];
+                const double* xp = a.dg + 3 * (a.gidx[S.xoff + k] - a.n_int);
+                s0 += v * xp[0];
+                s1 += v * xp[1];
+                s2 += v * xp[2];
+            }
+        } else {
+            const double* xv = (kind == FWD_PULL) ? a.zg : a.rg;
+            for (int32_t k = lane; k < S.len; k += 64) {
+                const double v = a.dvals[S.voff + k];
+                const double* xp = xv + 3 * (S.xoff + k);
+                s0 += v * xp[0];
+                s1 += v * xp[1];
+                s2 += v * xp[2];
+            }
+        }
+    }
+    s0 = group_sum<64>(s0);
+    s1 = group_sum<64>(s1);
+    s2 = group_sum<64>(s2);
+    if (lane == 0) {
+        const int32_t o = 3 * T.out;
+        if (kind == FWD_PULL) {
+            a.rg[o] -= s0;
+            a.rg[o + 1] -= s1;
+            a.rg[o + 2] -= s2;
+        } else if (kind == FWD_TINV) {
+            a.zg[o] = s0;
+            a.zg[o + 1] = s1;
+            a.zg[o + 2] = s2;
+        } else if (kind == BWD_PULL) {
+            a.rg[o] = a.zg[o] - s0;
+            a.rg[o + 1] = a.zg[o + 1] - s1;
+            a.rg[o + 2] = a.zg[o + 2] - s2;
+        } else {
+            a.dg[o] = s0;
+            a.dg[o + 1] = s1;
+            a.dg[o + 2] = s2;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t max_n, int32_t apply,
+                                                      int32_t keep_delta) {
+    extern __shared__ float sm[];
+    float* Zl = sm;
+    float* Q = sm + 3 * max_n;
+    float* Dl = sm + 6 * max_n;
+    const int32_t d = blockIdx.x;
+    const int32_t base = a.sub_off[d];
+    const int32_t n = a.sub_off[d + 1] - base;
+    const int tid = threadIdx.x;
+    for (int32_t i = tid; i < 3 * n; i += BLK) {
+        Zl[i] = a.zf[3 * base + i];
+        Q[i] = 0.0f;
+        Dl[i] = 0.0f;
+    }
+    __syncthreads();
+    const int grp = tid / IG, lane = tid % IG;
+    constexpr int NGRP = BLK / IG;
+    const int32_t ph1 = a.sub_bwd_ph[d + 1];
+    for (int32_t ph = a.sub_bwd_ph[d]; ph < ph1; ++ph) {
+        const Phase P = a.phases[ph];
+        for (int32_t t = P.task0 + grp; t < P.task1; t += NGRP) {
+            const Task T = a.tasks[t];
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+            for (int32_t g = T.seg0; g < T.seg1; ++g) {
+                const Seg S = a.segs[g];
+                if (P.kind == BWD_PULL) {
+                    for (int32_t k = lane; k < S.len; k += IG) {
+                        const float v = a.fvals[S.voff + k];
+                        const int32_t gi = a.gidx[S.xoff + k];
+                        float x0, x1, x2;
+                        if (gi < a.n_int) {
+                            const float* xp = Dl + 3 * (gi - base);
+                            x0 = xp[0];
+                            x1 = xp[1];
+                            x2 = xp[2];
+                        } else {
+                            const double* xp = a.dg + 3 * (gi - a.n_int);
+                            x0 = (float)xp[0];
+                            x1 = (float)xp[1];
+                            x2 = (float)xp[2];
+                        }
+                        s0 += v * x0;
+                        s1 += v * x1;
+                        s2 += v * x2;
+                    }
+                } else {
+                    for (int32_t k = lane; k < S.len; k += IG) {
+                        const float v = a.fvals[S.voff + k];
+                        const float* xp = Q + 3 * (S.xoff + k);
+                        s0 += v * xp[0];
+                        s1 += v * xp[1];
+                        s2 += v * xp[2];
+                    }
+                }
+            }
+            s0 = group_sum<IG>(s0);
+            s1 = group_sum<IG>(s1);
+            s2 = group_sum<IG>(s2);
+            if (lane == 0) {
+                const int32_t o = 3 * T.out;
+                if (P.kind == BWD_PULL) {
+                    Q[o] = Zl[o] - s0;
+                    Q[o + 1] = Zl[o + 1] - s1;
+                    Q[o + 2] = Zl[o + 2] - s2;
+                } else {
+                    Dl[o] = s0;
+                    Dl[o + 1] = s1;
+                    Dl[o + 2] = s2;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // interior rows of this subdomain
+    for (int32_t i = tid; i < n; i += BLK) {
+        const int32_t gi = base + i;
+        float du[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double dv = (double)Dl[3 * i + c];
+            if (keep_delta) a.delta[3 * gi + c] = dv;
+            if (apply) {
+                const double xn = a.x[3 * gi + c] + dv;
+                a.x[3 * gi + c] = xn;
+                du[c] = (float)(xn - a.X[3 * gi + c]);
+            }
+        }
+        if (apply) a.u[gi] = make_float4(du[0], du[1], du[2], 0.0f);
+    }
+    // a slice of the interface rows
+    const int32_t chunk = (a.n_gamma + a.D - 1) / a.D;
+    const int32_t g0 = d * chunk, g1 = min(a.n_gamma, g0 + chunk);
+    for (int32_t i = g0 + tid; i < g1; i += BLK) {
+        const int32_t gi = a.n_int + i;
+        float du[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double dv = a.dg[3 * i + c];
+            if (keep_delta) a.delta[3 * gi + c] = dv;
+            if (apply) {
+                const double xn = a.x[3 * gi + c] + dv;
+                a.x[3 * gi + c] = xn;
+                du[c] = (float)(xn - a.X[3 * gi + c]);
+            }
+        }
+        if (apply) a.u[gi] = make_float4(du[0], du[1], du[2], 0.0f);
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_refine(int32_t n_free, const int32_t* __restrict__ Kp,
+                                                const int32_t* __restrict__ Kc,
+                                                const double* __restrict__ Kv,
+                                                const double* __restrict__ delta,
+                                                double* __restrict__ r) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= n_free) return;
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int32_t k = Kp[i]; k < Kp[i + 1]; ++k) {
+        const double v = Kv[k];
+        const double* dp = delta + 3 * Kc[k];
+        s0 += v * dp[0];
+        s1 += v * dp[1];
+        s2 += v * dp[2];
+    }
+    r[3 * i] -= s0;
+    r[3 * i + 1] -= s1;
+    r[3 * i + 2] -= s2;
+}
+
+__global__ __launch_bounds__(BLK) void k_velocity(int32_t nv, int32_t n_free, double inv_dt,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ xprev,
+                                                  double* __restrict__ v, uint32_t* flags) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= nv) return;
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double xv = x[3 * i + c];
+        bad |= !isfinite(xv);
+        v[3 * i + c] = (i < n_free) ? (xv - xprev[3 * i + c]) * inv_dt : 0.0;
+    }
+    if (bad) atomicOr(&flags[0], 1u);
+}
+
+SolveArgs solve_args(const DevMesh& m) {
+    SolveArgs a;
+    a.n_int = m.n_int;
+    a.n_gamma = m.n_gamma;
+    a.D = m.D;
+    a.sub_off = m.sub_off;
+    a.sub_fwd_ph = m.sub_fwd_ph;
+    a.sub_bwd_ph = m.sub_bwd_ph;
+    a.phases = m.phases;
+    a.tasks = m.tasks;
+    a.segs = m.segs;
+    a.fvals = m.fvals;
+    a.dvals = m.dvals;
+    a.gidx = m.gidx;
+    a.r = m.r;
+    a.zf = m.zf;
+    a.rg = m.rg;
+    a.zg = m.zg;
+    a.dg = m.dg;
+    a.delta = m.delta;
+    a.x = m.x;
+    a.X = m.X;
+    a.u = m.u;
+    return a;
+}
+
+inline int nblk(int64_t n) { return (int)((n + BLK - 1) / BLK); }
+
+}  // namespace
+
+hipError_t launch_predictor(const DevMesh& m, hipStream_t s) {
+    hipLaunchKernelGGL(k_predict, dim3(nblk(m.nv)), dim3(BLK), 0, s, m.nv, m.n_free, m.dt, m.g[0],
+                       m.g[1], m.g[2], m.x, m.v, m.xprev, m.y, m.X, m.u);
+    return hipGetLastError();
+}
+
+hipError_t launch_local(const DevMesh& m, hipStream_t s, bool debug) {
+    if (debug)
+        hipLaunchKernelGGL(k_local<true>, dim3(nblk(m.nt)), dim3(BLK), 0, s, m.nt, m.tet, m.ginv, m.w,
+                           m.u, m.fout, m.flags, m.dbg_T, m.dbg_sig, m.dbg_s);
+    else
+        hipLaunchKernelGGL(k_local<false>, dim3(nblk(m.nt)), dim3(BLK), 0, s, m.nt, m.tet, m.ginv,
+                           m.w, m.u, m.fout, m.flags, nullptr, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const DevMesh& m, hipStream_t s) {
+    hipLaunchKernelGGL(k_residual, dim3(nblk(m.n_free)), dim3(BLK), 0, s, m.n_free, 4 * m.nt,
+                       m.inc_ptr, m.inc_slot, m.fout, m.mass, m.x, m.y, 1.0 / (m.dt * m.dt), m.r);
+    return hipGetLastError();
+}
+
+hipError_t launch_interior_fwd(const DevMesh& m, hipStream_t s) {
+    size_t sh = sizeof(float) * 6 * (size_t)m.max_sub_n;
+    hipLaunchKernelGGL(k_interior_fwd, dim3(m.D), dim3(BLK), sh, s, solve_args(m), m.max_sub_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_interface_phase(const DevMesh& m, const PhaseLaunch& ph, hipStream_t s) {
+    if (ph.ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iface, dim3((ph.ntasks + 3) / 4), dim3(BLK), 0, s, solve_args(m), ph.kind,
+                       ph.task0, ph.ntasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_interior_bwd(const DevMesh& m, hipStream_t s, bool apply, bool keep_delta) {
+    size_t sh = sizeof(float) * 9 * (size_t)m.max_sub_n;
+    hipLaunchKernelGGL(k_interior_bwd, dim3(m.D), dim3(BLK), sh, s, solve_args(m), m.max_sub_n,
+                       (int32_t)apply, (int32_t)keep_delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_residual(const DevMesh& m, hipStream_t s) {
+    hipLaunchKernelGGL(k_refine, dim3(nblk(m.n_free)), dim3(BLK), 0, s, m.n_free, m.K_ptr, m.K_col,
+                       m.K_val, m.delta, m.r);
+    return hipGetLastError();
+}
+
+hipError_t launch_velocity(const DevMesh& m, hipStream_t s) {
+    hipLaunchKernelGGL(k_velocity, dim3(nblk(m.nv)), dim3(BLK), 0, s, m.nv, m.n_free, 1.0 / m.dt, m.x,
+                       m.xprev, m.v, m.flags);
+    return hipGetLastError();
+}
+
+}  // namespace vh
+
+namespace vh {
+namespace {
+__global__ __launch_bounds__(BLK) void k_to_user(int32_t nv, const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ src,
+                                                 double* __restrict__ dst) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= nv) return;
+    const int32_t u = perm[i];
+    dst[3 * u] = src[3 * i];
+    dst[3 * u + 1] = src[3 * i + 1];
+    dst[3 * u + 2] = src[3 * i + 2];
+}
+
+__global__ __launch_bounds__(BLK) void k_from_user(int32_t nv, int32_t n_free,
+                                                   const int32_t* __restrict__ perm,
+                                                   const double* __restrict__ src,
+                                                   const double* __restrict__ X,
+                                                   double* __restrict__ dst) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= nv) return;
+    const int32_t u = perm[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        dst[3 * i + c] = (i < n_free) ? src[3 * u + c] : (X ? X[3 * i + c] : 0.0);
+}
+
+__global__ __launch_bounds__(BLK) void k_refresh_u(int32_t nv, const double* __restrict__ x,
+                                                   const double* __restrict__ X,
+                                                   float4* __restrict__ u) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= nv) return;
+    u[i] = make_float4((float)(x[3 * i] - X[3 * i]), (float)(x[3 * i + 1] - X[3 * i + 1]),
+                       (float)(x[3 * i + 2] - X[3 * i + 2]), 0.0f);
+}
+}  // namespace
+
+hipError_t launch_to_user(int32_t nv, const int32_t* perm, const double* src_int, double* dst_user,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_to_user, dim3(nblk(nv)), dim3(BLK), 0, s, nv, perm, src_int, dst_user);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_user(int32_t nv, int32_t n_free, const int32_t* perm, const double* src_user,
+                            const double* X_or_null, double* dst_int, hipStream_t s) {
+    hipLaunchKernelGGL(k_from_user, dim3(nblk(nv)), dim3(BLK), 0, s, nv, n_free, perm, src_user,
+                       X_or_null, dst_int);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh_u(const DevMesh& m, hipStream_t s) {
+    hipLaunchKernelGGL(k_refresh_u, dim3(nblk(m.nv)), dim3(BLK), 0, s, m.nv, m.x, m.X, m.u);
+    return hipGetLastError();
+}
+}  // namespace vh

@@ -1,0 +1,242 @@
+"""Python binding of libvhpd (ctypes; argument marshalling only).
+
+Every step of the simulation runs in the HIP library; this module converts
+numpy arrays and torch streams/tensors into the plain pointers and sizes of
+the C ABI in ``include/vhpd.h`` and raises ``VHError`` on a nonzero return.
+It fails loudly when the library has not been built: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvhpd.so")
+
+VH_OK, VH_EINVAL, VH_ENOMEM, VH_ENOTSPD, VH_ESTATE, VH_ENUMERIC, VH_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {-1: "VH_EINVAL", -2: "VH_ENOMEM", -3: "VH_ENOTSPD", -4: "VH_ESTATE", -5: "VH_ENUMERIC",
+          -6: "VH_EDEVICE"}
+
+# Every symbol the header declares, with (restype, argtypes).
+_vp, _i32, _dbl, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+_P = ctypes.POINTER
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int32), ("nt", ctypes.c_int32), ("n_free", ctypes.c_int32),
+                ("n_interior", ctypes.c_int32), ("n_interface", ctypes.c_int32),
+                ("n_subdomains", ctypes.c_int32), ("n_supernodes", ctypes.c_int32),
+                ("n_coarse_levels", ctypes.c_int32), ("max_interior_phases", ctypes.c_int32),
+                ("nnz_interior", ctypes.c_int64), ("nnz_coarse", ctypes.c_int64),
+                ("device_bytes", ctypes.c_size_t), ("prefactor_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SIGNATURES = {
+    "vh_last_error": (ctypes.c_char_p, []),
+    "vh_ctx_create": (ctypes.c_int, [_P(_vp), ctypes.c_int, _sz]),
+    "vh_ctx_destroy": (ctypes.c_int, [_vp]),
+    "vh_ctx_hbm_in_use": (ctypes.c_int, [_vp, _P(_sz)]),
+    "vh_mesh_create": (ctypes.c_int, [_vp, _P(_vp), _vp, _i32, _vp, _i32]),
+    "vh_mesh_destroy": (ctypes.c_int, [_vp]),
+    "vh_mesh_set_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32]),
+    "vh_mesh_prefactor": (ctypes.c_int, [_vp, _i32, _i32]),
+    "vh_mesh_step": (ctypes.c_int, [_vp, _i32, _vp]),
+    "vh_mesh_read_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "vh_mesh_write_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "vh_mesh_read_state_device": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "vh_mesh_write_state_device": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "vh_mesh_get_info": (ctypes.c_int, [_vp, _P(MeshInfo)]),
+    "vh_mesh_profile": (ctypes.c_int, [_vp, ctypes.c_uint32]),
+    "vh_mesh_profile_read": (ctypes.c_int, [_vp, _vp, _vp]),
+    "vh_debug_local_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "vh_debug_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "vh_debug_solve": (ctypes.c_int, [_vp, _vp, _vp]),
+}
+
+
+class VHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libvhpd.so (built by paper_2405_12484_amd/build.py); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python paper_2405_12484_amd/build.py`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != VH_OK:
+        raise VHError(rc, _lib.vh_last_error().decode())
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One GPU; ``hbm_budget`` bytes bound the device memory of all meshes (0 = none)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        load()
+        h = ctypes.c_void_p()
+        _check(_lib.vh_ctx_create(ctypes.byref(h), device, hbm_budget))
+        self.h = h
+
+    def hbm_in_use(self) -> int:
+        b = ctypes.c_size_t()
+        _check(_lib.vh_ctx_hbm_in_use(self.h, ctypes.byref(b)))
+        return b.value
+
+    def close(self):
+        if self.h:
+            _lib.vh_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """One garment: rest mesh, materials, factorization and device state."""
+
+    def __init__(self, ctx: Context, X, tets):
+        self.ctx = ctx
+        self.X = np.ascontiguousarray(X, dtype=np.float64)
+        self.tets = np.ascontiguousarray(tets, dtype=np.int32)
+        self.nv, self.nt = self.X.shape[0], self.tets.shape[0]
+        h = ctypes.c_void_p()
+        _check(_lib.vh_mesh_create(ctx.h, ctypes.byref(h), _ptr(self.X), self.nv, _ptr(self.tets), self.nt))
+        self.h = h
+
+    def set_params(self, gamma_s, gamma_v, mass, pinned, gravity, dt, pd_iters=10):
+        gs = np.ascontiguousarray(gamma_s, dtype=np.float64)
+        gv = np.ascontiguousarray(gamma_v, dtype=np.float64)
+        m = np.ascontiguousarray(mass, dtype=np.float64)
+        pin = np.ascontiguousarray(pinned, dtype=np.uint8)
+        g = np.ascontiguousarray(gravity, dtype=np.float64)
+        if gs.shape != (self.nt,) or gv.shape != (self.nt,) or m.shape != (self.nv,) or pin.shape != (self.nv,) \
+                or g.shape != (3,):
+            raise ValueError("parameter array shapes do not match the mesh")
+        _check(_lib.vh_mesh_set_params(self.h, _ptr(gs), _ptr(gv), _ptr(m), _ptr(pin), _ptr(g), float(dt),
+                                       int(pd_iters)))
+
+    def prefactor(self, n_subdomains: int, refine_steps: int = 0):
+        _check(_lib.vh_mesh_prefactor(self.h, int(n_subdomains), int(refine_steps)))
+
+    def step(self, n_frames: int = 1, stream=None):
+        _check(_lib.vh_mesh_step(self.h, int(n_frames), _stream_ptr(stream)))
+
+    def read_state(self, stream=None):
+        x = np.empty((self.nv, 3))
+        v = np.empty((self.nv, 3))
+        _check(_lib.vh_mesh_read_state(self.h, _ptr(x), _ptr(v), _stream_ptr(stream)))
+        return x, v
+
+    def write_state(self, x, v, stream=None):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        if x.shape != (self.nv, 3) or v.shape != (self.nv, 3):
+            raise ValueError("state arrays must be [nv, 3]")
+        _check(_lib.vh_mesh_write_state(self.h, _ptr(x), _ptr(v), _stream_ptr(stream)))
+
+    def read_state_device(self, x_t, v_t, stream=None):
+        """Copy the state into float64 [nv, 3] device tensors (asynchronous)."""
+        for t in (x_t, v_t):
+            if t.dtype.__str__() != "torch.float64" or tuple(t.shape) != (self.nv, 3) or not t.is_contiguous():
+                raise ValueError("state tensors must be contiguous float64 [nv, 3]")
+        _check(_lib.vh_mesh_read_state_device(self.h, ctypes.c_void_p(x_t.data_ptr()),
+                                              ctypes.c_void_p(v_t.data_ptr()), _stream_ptr(stream)))
+
+    def write_state_device(self, x_t, v_t, stream=None):
+        for t in (x_t, v_t):
+            if t.dtype.__str__() != "torch.float64" or tuple(t.shape) != (self.nv, 3) or not t.is_contiguous():
+                raise ValueError("state tensors must be contiguous float64 [nv, 3]")
+        _check(_lib.vh_mesh_write_state_device(self.h, ctypes.c_void_p(x_t.data_ptr()),
+                                               ctypes.c_void_p(v_t.data_ptr()), _stream_ptr(stream)))
+
+    def info(self) -> dict:
+        i = MeshInfo()
+        _check(_lib.vh_mesh_get_info(self.h, ctypes.byref(i)))
+        return i.as_dict()
+
+    PROFILE_CLASSES = ("predictor", "local", "residual", "interior_fwd", "interface", "interior_bwd",
+                       "refine", "velocity")
+
+    def profile(self, classes=()):
+        """Enable HIP-event timing for the named kernel classes (empty = off)."""
+        mask = 0
+        for c in classes:
+            mask |= 1 << self.PROFILE_CLASSES.index(c)
+        _check(_lib.vh_mesh_profile(self.h, mask))
+
+    def profile_read(self):
+        """{class: (milliseconds, timed launch groups)} since profile() or the last read."""
+        ms = np.zeros(8)
+        n = np.zeros(8, dtype=np.int64)
+        _check(_lib.vh_mesh_profile_read(self.h, _ptr(ms), _ptr(n)))
+        return {c: (float(ms[i]), int(n[i])) for i, c in enumerate(self.PROFILE_CLASSES) if n[i]}
+
+    # -- per-kernel entry points (clobber the state) --
+    def debug_local_step(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        T = np.empty((self.nt, 9))
+        sig = np.empty((self.nt, 3))
+        s = np.empty((self.nt, 3))
+        _check(_lib.vh_debug_local_step(self.h, _ptr(x), _ptr(T), _ptr(sig), _ptr(s)))
+        return T.reshape(self.nt, 3, 3), sig, s
+
+    def debug_residual(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        r = np.empty((self.nv, 3))
+        _check(_lib.vh_debug_residual(self.h, _ptr(x), _ptr(y), _ptr(r)))
+        return r
+
+    def debug_solve(self, rhs):
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        d = np.empty((self.nv, 3))
+        _check(_lib.vh_debug_solve(self.h, _ptr(rhs), _ptr(d)))
+        return d
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.vh_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,29 @@
+"""Build the test-only host library tests/host/_plan_host.so (g++, no GPU):
+the library's host plan plus a CPU emulation of its device solve programs."""
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+OUT = os.path.join(HERE, "_plan_host.so")
+SRCS = [os.path.join(HERE, "plan_emulate.cpp"),
+        os.path.join(ROOT, "paper_2405_12484_amd", "csrc", "host_plan.cpp")]
+
+
+def build():
+    cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", *SRCS, "-o", OUT + ".tmp"]
+    print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(OUT + ".tmp", OUT)
+    return OUT
+
+
+def ensure():
+    if not os.path.exists(OUT) or any(os.path.getmtime(s) > os.path.getmtime(OUT) for s in SRCS):
+        build()
+    return OUT
+
+
+if __name__ == "__main__":
+    build()

@@ -1,0 +1,244 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: positions within 1e-5 relative L2 per step (FP32 bulk arithmetic);
+per-kernel tolerances follow from FP32 rounding of O(1) quantities (the
+deformation gradient, singular values) scaled by the element weights."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import deformed, make_mesh, rel_disp, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vh():
+    from paper_2405_12484_amd import vhpd
+    vhpd.load()
+    return vhpd
+
+
+@pytest.fixture(scope="module")
+def ctx(vh):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = vh.Context(0)
+    yield c
+    c.close()
+
+
+# --- local step ----------------------------------------------------------------
+@pytest.mark.parametrize("name", ["box", "shell_small"])
+def test_local_step_matches_oracle(vh, ctx, name):
+    say(f"[local] {name}")
+    p = synth.problem_by_name(name)
+    m = make_mesh(vh, ctx, p)
+    sim = oracle.OracleSim.from_problem(p)
+    for amp in (0.0, 1e-3, 5e-3):
+        x = deformed(p, amp=amp, seed=1)
+        T, sig, s = m.debug_local_step(x)
+        loc = oracle.local_step(x, sim.tets, sim.grads, sim.w_s, sim.w_v)
+        Tref = loc["P"] - (sim.w_s + sim.w_v)[:, None, None] * loc["F"]
+        w = (sim.w_s + sim.w_v)[:, None, None]
+        err = np.abs(T - Tref) / w
+        assert err.max() < 2e-5, (amp, err.max())
+        assert np.abs(sig - loc["sigma"]).max() < 2e-6
+        assert np.abs(s - loc["s"]).max() < 2e-6
+        if amp == 0.0:
+            assert np.abs(T).max() == 0.0          # F = I exactly at rest
+    m.close()
+
+
+def test_local_step_rigid_rotation_zero_stress(vh, ctx):
+    say("[local] rigid rotation")
+    p = synth.problem_by_name("box")
+    pins = np.zeros(p.nv, dtype=np.uint8)
+    m = make_mesh(vh, ctx, p, pinned=pins)
+    th = 0.7
+    Q = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1.0]])
+    x = p.X @ Q.T + np.array([0.01, 0.02, -0.03])
+    T, sig, s = m.debug_local_step(x)
+    w = (p.gamma_s + p.gamma_v)[:, None, None]
+    assert np.abs(T / w).max() < 1e-5 * 1e-6 / 1e-6   # FP32 rounding of |F| ~ 1
+    assert np.abs(sig - 1).max() < 2e-6 and np.abs(s - 1).max() < 2e-6
+    m.close()
+
+
+# --- residual (local step + scatter) ------------------------------------------------
+@pytest.mark.parametrize("name", ["box", "shell_small"])
+def test_residual_matches_oracle(vh, ctx, name):
+    say(f"[residual] {name}")
+    p = synth.problem_by_name(name)
+    m = make_mesh(vh, ctx, p)
+    sim = oracle.OracleSim.from_problem(p)
+    x = deformed(p, amp=2e-3, seed=2)
+    y = deformed(p, amp=1e-3, seed=3)
+    r = m.debug_residual(x, y)
+    loc = oracle.local_step(x, sim.tets, sim.grads, sim.w_s, sim.w_v)
+    rref = sim.rhs(y, loc["P"]) - sim.L_ff @ x[sim.free]
+    assert np.linalg.norm(r[sim.free] - rref) <= 1e-5 * np.linalg.norm(rref)
+    assert np.all(r[sim.fixed] == 0)
+    m.close()
+
+
+# --- decomposed solve ---------------------------------------------------------------
+@pytest.mark.parametrize("name,D", [("box", 4), ("box", 1), ("shell_small", 8), ("slab", 8)])
+def test_solve_matches_exact(vh, ctx, name, D):
+    say(f"[solve] {name} D={D}")
+    p = synth.problem_by_name(name)
+    m = make_mesh(vh, ctx, p, n_subdomains=D)
+    sim = oracle.OracleSim.from_problem(p)
+    rng = np.random.default_rng(4)
+    rhs = rng.standard_normal((p.nv, 3))
+    d = m.debug_solve(rhs)
+    xe = sim._solve(rhs[sim.free])
+    assert np.linalg.norm(d[sim.free] - xe) <= 5e-7 * np.linalg.norm(xe)
+    assert np.all(d[sim.fixed] == 0)
+    m.close()
+
+
+# --- whole steps ---------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["box", "shell_small"])
+def test_trajectory_matches_oracle(vh, ctx, name):
+    """Free-running frames; every frame within 1e-5 relative L2 of the oracle,
+    and lock-step (GPU started from the oracle's state) within 1e-5 too."""
+    say(f"[trajectory] {name}")
+    p = synth.problem_by_name(name)
+    m = make_mesh(vh, ctx, p)
+    sim = oracle.OracleSim.from_problem(p)
+    x, v = p.initial_state()
+    worst = 0.0
+    for f in range(p.frames):
+        xo, vo = sim.step(x, v)
+        m.step(1)
+        xg, vg = m.read_state()
+        e = rel_l2(xg, xo)
+        worst = max(worst, e)
+        assert e <= 1e-5, (f, e)
+        # lock-step from the oracle state
+        m.write_state(x, v)
+        m.step(1)
+        xl, _ = m.read_state()
+        assert rel_l2(xl, xo) <= 1e-5
+        m.write_state(xg, vg)
+        x, v = xo, vo
+    say(f"   worst rel L2 {worst:.3e}, displacement-relative {rel_disp(xg, xo, p.X):.3e}")
+    m.close()
+
+
+def test_free_fall_without_stiffness(vh, ctx):
+    say("[free fall]")
+    p = synth.problem_by_name("box")
+    z = np.zeros(p.nt)
+    m = make_mesh(vh, ctx, p, gamma_s=z, gamma_v=z)
+    rng = np.random.default_rng(5)
+    v0 = 0.1 * rng.standard_normal(p.X.shape)
+    v0[p.pinned.astype(bool)] = 0
+    m.write_state(p.X, v0)
+    m.step(1)
+    x1, v1 = m.read_state()
+    free = ~p.pinned.astype(bool)
+    want = p.X + p.dt * (v0 + p.dt * p.gravity)
+    assert np.abs(x1[free] - want[free]).max() < 1e-15
+    m.close()
+
+
+def test_rest_fixed_point(vh, ctx):
+    say("[rest]")
+    p = synth.problem_by_name("shell_small")
+    m = make_mesh(vh, ctx, p, gravity=np.zeros(3))
+    m.step(3)
+    x, v = m.read_state()
+    assert np.abs(x - p.X).max() == 0.0 and np.abs(v).max() == 0.0
+    m.close()
+
+
+def test_deterministic_and_resume(vh, ctx):
+    """Two runs are bitwise equal; a run resumed from a read/written state equals
+    the uninterrupted one bitwise."""
+    say("[determinism]")
+    p = synth.problem_by_name("shell_small")
+    a = make_mesh(vh, ctx, p)
+    b = make_mesh(vh, ctx, p)
+    a.step(6)
+    b.step(3)
+    xs, vs = b.read_state()
+    b.write_state(xs, vs)
+    b.step(3)
+    xa, va = a.read_state()
+    xb, vb = b.read_state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    a.close()
+    b.close()
+
+
+def test_device_state_roundtrip(vh, ctx):
+    import torch
+    say("[device state]")
+    p = synth.problem_by_name("box")
+    m = make_mesh(vh, ctx, p)
+    m.step(2)
+    xh, vh_ = m.read_state()
+    xt = torch.empty((p.nv, 3), dtype=torch.float64, device="cuda")
+    vt = torch.empty_like(xt)
+    s = torch.cuda.current_stream()
+    m.read_state_device(xt, vt, s)
+    torch.cuda.synchronize()
+    assert np.array_equal(xt.cpu().numpy(), xh) and np.array_equal(vt.cpu().numpy(), vh_)
+    m.write_state_device(xt, vt * 0, s)
+    torch.cuda.synchronize()
+    x2, v2 = m.read_state()
+    assert np.array_equal(x2, xh) and np.abs(v2).max() == 0.0
+    m.close()
+
+
+def test_errors_are_reported(vh, ctx):
+    say("[errors]")
+    p = synth.problem_by_name("box")
+    bad = p.tets.copy()
+    bad[0, [1, 2]] = bad[0, [2, 1]]                        # inverted rest tet
+    with pytest.raises(vh.VHError) as ei:
+        vh.Mesh(ctx, p.X, bad)
+    assert ei.value.code == vh.VH_EINVAL
+    m = vh.Mesh(ctx, p.X, p.tets)
+    with pytest.raises(vh.VHError) as ei:
+        m.prefactor(4)
+    assert ei.value.code == vh.VH_ESTATE
+    g = p.gamma_s.copy()
+    g[3] = -1.0
+    with pytest.raises(vh.VHError) as ei:
+        m.set_params(g, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, 10)
+    assert ei.value.code == vh.VH_EINVAL
+    m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, 10)
+    with pytest.raises(vh.VHError) as ei:
+        m.step(1)
+    assert ei.value.code == vh.VH_ESTATE
+    with pytest.raises(vh.VHError) as ei:
+        m.prefactor(3)
+    assert ei.value.code == vh.VH_EINVAL
+    m.prefactor(4)
+    x = p.X.copy()
+    x[5, 0] = np.nan
+    m.write_state(x, np.zeros_like(x))
+    m.step(1)
+    with pytest.raises(vh.VHError) as ei:
+        m.read_state()
+    assert ei.value.code == vh.VH_ENUMERIC
+    m.close()
+
+
+def test_budget_refuses(vh):
+    say("[budget]")
+    p = synth.problem_by_name("box")
+    c = vh.Context(0, hbm_budget=4096)
+    m = vh.Mesh(c, p.X, p.tets)
+    m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, 10)
+    with pytest.raises(vh.VHError) as ei:
+        m.prefactor(4)
+    assert ei.value.code == vh.VH_ENOMEM
+    assert c.hbm_in_use() == 0
+    m.close()
+    c.close()

@@ -1,0 +1,93 @@
+"""CPU checks of the library's host prefactor (partition, orderings, FP64
+multifrontal factorization, solve programs) through a host emulation of the
+device solve programs, against the oracle's exact sparse solve."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.host import build as hbuild
+
+_vp, _ci, _cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+
+
+@pytest.fixture(scope="module")
+def hl():
+    lib = ctypes.CDLL(hbuild.ensure())
+    lib.vhp_build.restype = _vp
+    lib.vhp_build.argtypes = [_vp, _ci, _vp, _ci, _vp, _vp, _vp, _vp, _vp, _cd, _ci, _ci, _ci, _ci, _vp, _vp, _ci]
+    lib.vhp_info.argtypes = [_vp, _vp]
+    lib.vhp_solve.argtypes = [_vp, _vp, _vp]
+    lib.vhp_free.argtypes = [_vp]
+    lib.vhp_perm.argtypes = [_vp, _vp]
+    return lib
+
+
+def _build(hl, p, D, leaf=32, pinned=None):
+    a = lambda x, t: np.ascontiguousarray(x, dtype=t)
+    keep = [a(p.X, np.float64), a(p.tets, np.int32), a(p.gamma_s, np.float64), a(p.gamma_v, np.float64),
+            a(p.mass, np.float64), a(p.pinned if pinned is None else pinned, np.uint8), a(p.gravity, np.float64)]
+    rc = ctypes.c_int(0)
+    msg = ctypes.create_string_buffer(256)
+    h = hl.vhp_build(keep[0].ctypes.data, p.nv, keep[1].ctypes.data, p.nt, keep[2].ctypes.data,
+                     keep[3].ctypes.data, keep[4].ctypes.data, keep[5].ctypes.data, keep[6].ctypes.data,
+                     p.dt, p.pd_iters, D, 0, leaf, ctypes.byref(rc), msg, 256)
+    info = np.zeros(13, dtype=np.int64)
+    if h:
+        hl.vhp_info(h, info.ctypes.data)
+    keys = "n_free n_int n_gamma D n_sn n_clevels nnz_int nnz_coarse max_sub_phases n_phases n_tasks n_segs max_sub_n"
+    return h, rc.value, msg.value.decode(), dict(zip(keys.split(), info.tolist()))
+
+
+@pytest.mark.parametrize("name,D,leaf", [("box", 4, 32), ("box", 1, 32), ("box", 2, 8), ("box", 8, 1000),
+                                         ("shell_small", 8, 32), ("shell_small", 16, 16), ("slab", 8, 32)])
+def test_emulated_solve_matches_exact(hl, name, D, leaf):
+    p = synth.problem_by_name(name)
+    h, rc, msg, info = _build(hl, p, D, leaf)
+    assert rc == 0, msg
+    try:
+        sim = oracle.OracleSim.from_problem(p)
+        assert info["n_free"] == sim.free.size
+        assert info["n_int"] + info["n_gamma"] == info["n_free"]
+        if D == 1:
+            assert info["n_gamma"] == 0
+        rng = np.random.default_rng(D)
+        rhs = rng.standard_normal((p.nv, 3))
+        d = np.zeros((p.nv, 3))
+        hl.vhp_solve(h, rhs.ctypes.data, d.ctypes.data)
+        xe = sim._solve(rhs[sim.free])
+        # interior factor blocks are stored in FP32
+        assert np.linalg.norm(d[sim.free] - xe) <= 2e-7 * np.linalg.norm(xe)
+        assert np.all(d[sim.fixed] == 0)
+    finally:
+        hl.vhp_free(h)
+
+
+def test_permutation_is_bijection_free_first(hl):
+    p = synth.problem_by_name("shell_small")
+    h, rc, msg, info = _build(hl, p, 8)
+    assert rc == 0, msg
+    perm = np.zeros(p.nv, dtype=np.int32)
+    hl.vhp_perm(h, perm.ctypes.data)
+    hl.vhp_free(h)
+    assert sorted(perm.tolist()) == list(range(p.nv))
+    nf = info["n_free"]
+    assert np.all(p.pinned[perm[:nf]] == 0) and np.all(p.pinned[perm[nf:]] == 1)
+
+
+def test_non_power_of_two_rejected(hl):
+    p = synth.problem_by_name("box")
+    h, rc, msg, info = _build(hl, p, 3)
+    assert h is None and rc == -1 and "power of two" in msg
+
+
+def test_unpinned_mesh(hl):
+    p = synth.problem_by_name("box")
+    pins = np.zeros(p.nv, dtype=np.uint8)
+    h, rc, msg, info = _build(hl, p, 4, pinned=pins)
+    assert rc == 0, msg
+    assert info["n_free"] == p.nv
+    hl.vhp_free(h)
