@@ -3,7 +3,9 @@
 Host prefactor code is plain C++ (g++ with OpenMP); kernels and the C ABI are
 HIP, compiled by hipcc for gfx950 only.  Packed FP32 instructions are disabled
 for device code (they are known to misbehave on this hardware generation in
-some forms; hipcc's host pass warns that it ignores the feature).
+some forms; hipcc's host pass warns that it ignores the feature).  Code object
+version 5 keeps the kernels loadable by the HIP runtime that PyTorch ships,
+which is the runtime the library shares with it in one process.
 """
 
 from __future__ import annotations
@@ -21,7 +23,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HIP_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",
+    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-mcode-object-version=5",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
@@ -44,7 +46,7 @@ def build(verbose: bool = True) -> str:
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lgomp"])
+    _run([HIPCC, f"--offload-arch={ARCH}", "-mcode-object-version=5", "-shared", "-fPIC", "-o", tmp, *objs, "-lgomp"])
     os.replace(tmp, LIB)
     return LIB
 

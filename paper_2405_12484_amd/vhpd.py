@@ -76,6 +76,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python paper_2405_12484_amd/build.py`")
+    # PyTorch's HIP runtime must be the one in the process (the library shares
+    # its streams and device memory); loading torch first makes the library's
+    # libamdhip64.so.7 dependency resolve to it.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
