@@ -141,21 +141,20 @@ def _plus_branch(sig, logc=0.0):
     # below zero: a root exists only if h(lo) < 0
     hlo = h(lo)
     ok &= grow | (hlo < 0)
-    for _ in range(60):
+    for _ in range(24):
         mid = 0.5 * (lo + hi)
         hm = h(mid)
         up = hm > 0
         hi = np.where(up, mid, hi)
         lo = np.where(up, lo, mid)
     mu = 0.5 * (lo + hi)
-    for _ in range(4):                     # Newton polish, kept inside [lo, hi]
+    for _ in range(6):                     # Newton polish, clipped to [lo, hi]
         s, d = _plus_root(sig, mu[:, None])
         with np.errstate(divide="ignore", invalid="ignore"):
             dh = (1.0 / (d * s)).sum(axis=1)
             f = np.log(s).sum(axis=1) - logc
             step = np.where(np.isfinite(dh) & (dh > 0), f / dh, 0.0)
-        cand = mu - step
-        mu = np.where((cand >= lo) & (cand <= hi), cand, mu)
+        mu = np.clip(mu - step, lo, hi)
     s, _ = _plus_root(sig, mu[:, None])
     return s, mu, ok
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -66,6 +67,10 @@ struct vh_mesh {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<size_t, int>> ev_pairs;   // start event index, class
+    // one frame captured as a HIP graph (replayed per frame on the caller's stream)
+    bool use_graph = true;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -109,6 +114,10 @@ struct ProfScope {
 };
 
 void free_device(vh_mesh* m) {
+    if (m->gexec) {
+        (void)hipGraphExecDestroy(m->gexec);
+        m->gexec = nullptr;
+    }
     for (void* p : m->allocs) (void)hipFree(p);
     m->allocs.clear();
     if (m->ctx) m->ctx->in_use -= std::min(m->ctx->in_use, m->bytes);
@@ -181,6 +190,45 @@ int pd_iteration(vh_mesh* m, hipStream_t s) {
             VH_HIP(vh::launch_refine_residual(d, s));
         }
         VH_TRY(solve(m, s, true, k + 1 < m->refine));
+    }
+    return VH_OK;
+}
+
+int frame_direct(vh_mesh* m, hipStream_t s) {
+    {
+        ProfScope ps(m, s, 0);
+        VH_HIP(vh::launch_predictor(m->dm, s));
+    }
+    for (int32_t k = 0; k < m->plan.pd_iters; ++k) VH_TRY(pd_iteration(m, s));
+    {
+        ProfScope ps(m, s, 7);
+        VH_HIP(vh::launch_velocity(m->dm, s));
+    }
+    return VH_OK;
+}
+
+// Capture one frame (predictor, pd_iters x [local, residual, solve], velocity)
+// into an executable graph on a private stream.
+int ensure_graph(vh_mesh* m) {
+    if (m->gexec) return VH_OK;
+    if (!m->cap) VH_HIP(hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking));
+    const uint32_t mask = m->prof_mask;
+    m->prof_mask = 0;
+    VH_HIP(hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal));
+    int rc = frame_direct(m, m->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(m->cap, &g);
+    m->prof_mask = mask;
+    if (rc != VH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(VH_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&m->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        m->gexec = nullptr;
+        return fail(VH_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
     return VH_OK;
 }
@@ -276,6 +324,7 @@ int vh_mesh_destroy(vh_mesh* m) {
         (void)hipSetDevice(m->ctx->device);
         release_events(m);
         free_device(m);
+        if (m->cap) (void)hipStreamDestroy(m->cap);
         auto& v = m->ctx->meshes;
         v.erase(std::remove(v.begin(), v.end(), m), v.end());
     }
@@ -319,16 +368,18 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     if (refine_steps < 0) return fail(VH_EINVAL, "refine_steps must be >= 0");
     VH_TRY(set_device(m));
     free_device(m);
+    // LDS per workgroup decides the chunk size of the interior programs:
+    // two chunk buffers of nv4 * 4 * 256 floats next to the subdomain vectors
+    int lds_limit = 0;
+    VH_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                 m->ctx->device));
+    const int nv4 = (lds_limit >= 160 * 1024) ? 8 : 4;
     std::string msg;
     int rc = vh::build_plan(m->X.data(), m->nv, m->tets.data(), m->nt, m->gs.data(), m->gv.data(),
                             m->mass.data(), m->pinned.data(), m->g, m->dt, m->iters, n_subdomains,
-                            refine_steps, 32, m->plan, msg);
+                            refine_steps, 32, nv4 * 4 * 256, m->plan, msg);
     if (rc != 0) return fail(rc, msg);
     const vh::Plan& P = m->plan;
-    // the interior kernels keep three 3-column FP32 vectors of a subdomain in LDS
-    if ((size_t)P.max_sub_n * 9 * sizeof(float) > 65536)
-        return fail(VH_EINVAL, "a subdomain interior has " + std::to_string(P.max_sub_n) +
-                                   " vertices (LDS holds at most 1820); use more subdomains");
     vh::DevMesh& d = m->dm;
     d.nv = P.nv;
     d.nt = P.nt;
@@ -337,6 +388,14 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     d.n_gamma = P.n_gamma;
     d.D = P.D;
     d.max_sub_n = std::max(P.max_sub_n, 1);
+    d.max_nb = P.max_nb;
+    d.chunk_nv4 = nv4;
+    const size_t lds_need = std::max(vh::interior_fwd_lds(d), vh::interior_bwd_lds(d));
+    if (lds_need > (size_t)lds_limit)
+        return fail(VH_EINVAL, "a subdomain needs " + std::to_string(lds_need) +
+                                   " bytes of LDS (limit " + std::to_string(lds_limit) +
+                                   "); use more subdomains");
+    if (lds_need > 65536) VH_HIP(vh::interior_set_lds_limit(nv4, lds_need));
     d.dt = P.dt;
     for (int c = 0; c < 3; ++c) d.g[c] = P.gravity[c];
     const size_t nv3 = (size_t)P.nv * 3;
@@ -373,6 +432,12 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     chk(upload(m, &d.sub_off, P.sub_off));
     chk(upload(m, &d.sub_fwd_ph, P.sub_fwd_ph));
     chk(upload(m, &d.sub_bwd_ph, P.sub_bwd_ph));
+    chk(upload(m, &d.chunks, P.chunks));
+    chk(upload(m, &d.sub_fwd_ch, P.sub_fwd_ch));
+    chk(upload(m, &d.sub_bwd_ch, P.sub_bwd_ch));
+    chk(upload(m, &d.ivals, P.ivals));
+    chk(upload(m, &d.bnd, P.bnd));
+    chk(upload(m, &d.bnd_off, P.bnd_off));
     chk(upload(m, &d.K_ptr, P.K_ptr));
     chk(upload(m, &d.K_col, P.K_col));
     chk(upload(m, &d.K_val, P.K_val));
@@ -386,11 +451,21 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     VH_HIP(hipMemset(d.delta, 0, (size_t)P.n_free * 3 * sizeof(double)));
     m->fwd.clear();
     m->bwd.clear();
-    for (int32_t ph : P.coarse_fwd_ph)
-        m->fwd.push_back({P.phases[ph].kind, P.phases[ph].task0, P.phases[ph].task1 - P.phases[ph].task0});
-    for (int32_t ph : P.coarse_bwd_ph)
-        m->bwd.push_back({P.phases[ph].kind, P.phases[ph].task0, P.phases[ph].task1 - P.phases[ph].task0});
+    // lanes per task: a full wave for long dot products, 16 lanes for short ones
+    auto launch_of = [&](int32_t ph) {
+        const vh::Phase& Ph = P.phases[ph];
+        int64_t len = 0;
+        for (int32_t t = Ph.task0; t < Ph.task1; ++t)
+            for (int32_t g = P.tasks[t].seg0; g < P.tasks[t].seg1; ++g) len += P.segs[g].len;
+        const int32_t nt = Ph.task1 - Ph.task0;
+        const int32_t group = (nt > 0 && len / nt >= 96) ? 64 : 16;
+        return vh::PhaseLaunch{Ph.kind, Ph.task0, nt, group};
+    };
+    for (int32_t ph : P.coarse_fwd_ph) m->fwd.push_back(launch_of(ph));
+    for (int32_t ph : P.coarse_bwd_ph) m->bwd.push_back(launch_of(ph));
     m->refine = refine_steps;
+    const char* ng = std::getenv("VHPD_NO_GRAPH");
+    m->use_graph = !(ng && ng[0] == '1');
     VH_HIP(vh::launch_refresh_u(d, nullptr));
     VH_HIP(hipDeviceSynchronize());
     m->factored = true;
@@ -402,17 +477,12 @@ int vh_mesh_step(vh_mesh* m, int32_t n_frames, void* stream) {
     if (n_frames < 0) return fail(VH_EINVAL, "n_frames must be >= 0");
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int32_t f = 0; f < n_frames; ++f) {
-        {
-            ProfScope ps(m, s, 0);
-            VH_HIP(vh::launch_predictor(m->dm, s));
-        }
-        for (int32_t k = 0; k < m->plan.pd_iters; ++k) VH_TRY(pd_iteration(m, s));
-        {
-            ProfScope ps(m, s, 7);
-            VH_HIP(vh::launch_velocity(m->dm, s));
-        }
+    if (m->prof_mask || !m->use_graph) {
+        for (int32_t f = 0; f < n_frames; ++f) VH_TRY(frame_direct(m, s));
+        return VH_OK;
     }
+    if (n_frames > 0) VH_TRY(ensure_graph(m));
+    for (int32_t f = 0; f < n_frames; ++f) VH_HIP(hipGraphLaunch(m->gexec, s));
     return VH_OK;
 }
 

@@ -345,7 +345,8 @@ int check_mesh(const double* X, int32_t nv, const int32_t* tets, int32_t nt, std
 int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                const double* gamma_s, const double* gamma_v, const double* mass,
                const uint8_t* pinned, const double* gravity, double dt, int32_t pd_iters,
-               int32_t D, int32_t refine_steps, int32_t leaf_max, Plan& P, std::string& msg) {
+               int32_t D, int32_t refine_steps, int32_t leaf_max, int32_t chunk_floats, Plan& P,
+               std::string& msg) {
     auto t_start = std::chrono::steady_clock::now();
     if (D < 1 || (D & (D - 1))) {
         msg = "n_subdomains must be a power of two >= 1";
@@ -995,6 +996,105 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             }
         close_into(P.coarse_bwd_ph);
     }
+    // ---- interior programs as LDS chunks ---------------------------------------------
+    // Every subdomain's phases are cut into chunks of at most chunk_floats
+    // values; a chunk holds the values of its tasks' segments, and for
+    // backward pulls also the gather list (as int bit patterns) of each
+    // supernode, so a workgroup never reads the factor outside LDS.  Gather
+    // indices are local: [0, n_loc) interior rows, [n_loc, n_loc + nb) the
+    // subdomain's boundary rows staged from the interface solution.
+    P.chunk_floats = chunk_floats;
+    P.bnd_off.assign(D + 1, 0);
+    P.bnd.clear();
+    std::vector<int32_t> bpos(nf, -1);
+    for (int32_t d = 0; d < D; ++d) {
+        P.bnd_off[d] = (int32_t)P.bnd.size();
+        std::vector<int32_t> b;
+        for (int32_t t : sub_sn[d])
+            for (int32_t r : SN[t].rows)
+                if (r >= P.n_int) b.push_back(r);
+        std::sort(b.begin(), b.end());
+        b.erase(std::unique(b.begin(), b.end()), b.end());
+        P.bnd.insert(P.bnd.end(), b.begin(), b.end());
+        P.max_nb = std::max(P.max_nb, (int32_t)b.size());
+    }
+    P.bnd_off[D] = (int32_t)P.bnd.size();
+    P.ivals.clear();
+    P.chunks.clear();
+    P.sub_fwd_ch.assign(D + 1, 0);
+    P.sub_bwd_ch.assign(D + 1, 0);
+    std::vector<Seg> newsegs = P.segs;      // interior segs get chunk-relative offsets
+    auto pack_range = [&](int32_t d, int32_t ph0, int32_t ph1) {
+        const int32_t base = P.sub_off[d];
+        const int32_t nloc = P.sub_off[d + 1] - base;
+        // local ids of this subdomain's boundary rows
+        for (int32_t k = P.bnd_off[d]; k < P.bnd_off[d + 1]; ++k) bpos[P.bnd[k]] = nloc + (k - P.bnd_off[d]);
+        for (int32_t ph = ph0; ph < ph1; ++ph) {
+            const Phase& Ph = P.phases[ph];
+            int32_t t = Ph.task0;
+            while (t < Ph.task1) {
+                Chunk c;
+                c.kind = Ph.kind;
+                c.task0 = t;
+                while (P.ivals.size() % 4) P.ivals.push_back(0.0f);
+                c.v0 = (int32_t)P.ivals.size();
+                int32_t used = 0;
+                int32_t last_rows_off = -1, rows_local = 0;   // shared gather list of one supernode
+                while (t < Ph.task1) {
+                    const Task& T = P.tasks[t];
+                    int32_t need = 0;
+                    for (int32_t g = T.seg0; g < T.seg1; ++g) {
+                        need += P.segs[g].len;
+                        if (Ph.kind == BWD_PULL && P.segs[g].xoff != last_rows_off) need += P.segs[g].len;
+                    }
+                    if (used > 0 && used + need > chunk_floats) break;
+                    for (int32_t g = T.seg0; g < T.seg1; ++g) {
+                        const Seg& S = P.segs[g];
+                        Seg& NS = newsegs[g];
+                        if (Ph.kind == BWD_PULL && S.xoff != last_rows_off) {
+                            rows_local = (int32_t)P.ivals.size() - c.v0;
+                            for (int32_t k = 0; k < S.len; ++k) {
+                                int32_t gi = P.gidx[S.xoff + k];
+                                int32_t li = (gi < P.n_int) ? gi - base : bpos[gi];
+                                float f;
+                                std::memcpy(&f, &li, 4);
+                                P.ivals.push_back(f);
+                            }
+                            last_rows_off = S.xoff;
+                            used += S.len;
+                        }
+                        NS.voff = (int32_t)P.ivals.size() - c.v0;
+                        for (int32_t k = 0; k < S.len; ++k) P.ivals.push_back(P.fvals[S.voff + k]);
+                        if (Ph.kind == BWD_PULL) NS.xoff = rows_local;
+                        used += S.len;
+                    }
+                    ++t;
+                }
+                c.task1 = t;
+                c.nv = (int32_t)P.ivals.size() - c.v0;
+                c.pad[0] = c.pad[1] = c.pad[2] = 0;
+                if (c.nv > chunk_floats) {
+                    msg = "a solve task does not fit one LDS chunk";
+                    return false;
+                }
+                P.chunks.push_back(c);
+            }
+        }
+        return true;
+    };
+    for (int32_t d = 0; d < D; ++d) {
+        P.sub_fwd_ch[d] = (int32_t)P.chunks.size();
+        if (!pack_range(d, P.sub_fwd_ph[d], P.sub_fwd_ph[d + 1])) return EINVAL_;
+    }
+    P.sub_fwd_ch[D] = (int32_t)P.chunks.size();
+    for (int32_t d = 0; d < D; ++d) {
+        P.sub_bwd_ch[d] = (int32_t)P.chunks.size();
+        if (!pack_range(d, P.sub_bwd_ph[d], P.sub_bwd_ph[d + 1])) return EINVAL_;
+    }
+    P.sub_bwd_ch[D] = (int32_t)P.chunks.size();
+    while (P.ivals.size() % 4) P.ivals.push_back(0.0f);
+    P.segs.swap(newsegs);   // interface phases keep their fvals/dvals offsets
+
     P.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return OK;
 }

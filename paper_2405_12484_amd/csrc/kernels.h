@@ -38,6 +38,11 @@ struct DevMesh {
     Task* tasks = nullptr;
     Phase* phases = nullptr;
     int32_t *sub_off = nullptr, *sub_fwd_ph = nullptr, *sub_bwd_ph = nullptr;
+    Chunk* chunks = nullptr;
+    int32_t *sub_fwd_ch = nullptr, *sub_bwd_ch = nullptr;
+    float* ivals = nullptr;
+    int32_t *bnd = nullptr, *bnd_off = nullptr;
+    int32_t max_nb = 0, chunk_nv4 = 4;     // chunk capacity = chunk_nv4 * 4 * 256 floats
     int32_t *K_ptr = nullptr, *K_col = nullptr;
     double* K_val = nullptr;
     uint32_t* flags = nullptr;      // [0] non-finite seen, [1] out-of-regime projections, [2] inverted
@@ -47,8 +52,14 @@ struct DevMesh {
 
 // Host copies of the interface phase launch shapes.
 struct PhaseLaunch {
-    int32_t kind, task0, ntasks;
+    int32_t kind, task0, ntasks, group;   // group: lanes per task (16 or 64)
 };
+
+// LDS bytes of the interior kernels for a mesh (two chunk buffers + vectors)
+size_t interior_fwd_lds(const DevMesh& m);
+size_t interior_bwd_lds(const DevMesh& m);
+// allow the interior kernels to use up to `bytes` of LDS per workgroup
+hipError_t interior_set_lds_limit(int chunk_nv4, size_t bytes);
 
 hipError_t launch_predictor(const DevMesh& m, hipStream_t s);
 hipError_t launch_local(const DevMesh& m, hipStream_t s, bool debug);

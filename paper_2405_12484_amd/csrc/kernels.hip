@@ -20,6 +20,12 @@ namespace {
 
 constexpr int BLK = 256;
 
+// Hardware reciprocal / square root / reciprocal square root (about 1 ulp);
+// every quantity they feed is FP32 and later compared at FP32 tolerance.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // ---------------------------------------------------------------------------
 // 3x3 signed SVD in FP32: cyclic Jacobi eigen-decomposition of F^T F for W,
 // then Givens QR of F W for U and the (signed) singular values; McAdams et al.
@@ -30,9 +36,9 @@ constexpr int BLK = 256;
 __device__ __forceinline__ void jacobi_pair(float& app, float& aqq, float& apq, float& arp,
                                             float& arq, float* W, int p, int q) {
     if (apq == 0.0f) return;
-    float tau = (aqq - app) / (2.0f * apq);
-    float t = copysignf(1.0f, tau) / (fabsf(tau) + sqrtf(1.0f + tau * tau));
-    float c = rsqrtf(1.0f + t * t);
+    float tau = (aqq - app) * frcp(2.0f * apq);
+    float t = copysignf(frcp(fabsf(tau) + fsqrt(1.0f + tau * tau)), tau);
+    float c = frsq(1.0f + t * t);
     float s = t * c;
     app -= t * apq;
     aqq += t * apq;
@@ -64,7 +70,7 @@ __device__ __forceinline__ void givens_rows(float* B, float* U, int p, int q, in
     float r2 = a * a + b * b;
     float c = 1.0f, s = 0.0f;
     if (r2 > 1e-37f) {
-        float ir = rsqrtf(r2);
+        float ir = frsq(r2);
         c = a * ir;
         s = b * ir;
     }
@@ -98,7 +104,7 @@ __device__ __forceinline__ void svd3(const float* F, float* U, float* sig, float
 #pragma unroll
     for (int i = 0; i < 9; ++i) W[i] = (i % 4 == 0) ? 1.0f : 0.0f;
 #pragma unroll
-    for (int sweep = 0; sweep < 5; ++sweep) {
+    for (int sweep = 0; sweep < 4; ++sweep) {
         jacobi_pair(a00, a11, a01, a02, a12, W, 0, 1);   // r = 2
         jacobi_pair(a00, a22, a02, a01, a12, W, 0, 2);   // r = 1: a10 = a01, a12 -> a21
         jacobi_pair(a11, a22, a12, a01, a02, W, 1, 2);   // r = 0: a01, a02
@@ -128,16 +134,17 @@ __device__ __forceinline__ void svd3(const float* F, float* U, float* sig, float
 // s - sigma on the + branch s(mu) = (sigma + sqrt(sigma^2 + 4 mu)) / 2, written
 // without cancellation; returns the root distance q = sqrt(sigma^2 + 4 mu).
 __device__ __forceinline__ float plus_delta(float sg, float mu, float& q) {
-    q = sqrtf(fmaxf(sg * sg + 4.0f * mu, 0.0f));
-    if (sg >= 0.0f) return 2.0f * mu / (q + sg);
-    float s = 2.0f * mu / (q - sg);
+    q = fsqrt(fmaxf(sg * sg + 4.0f * mu, 0.0f));
+    if (sg >= 0.0f) return 2.0f * mu * frcp(q + sg);
+    float s = 2.0f * mu * frcp(q - sg);
     return s - sg;
 }
 
 // Nearest volume-preserving singular values (Eq. vol_pre): the Lagrange
 // condition gives s_i (s_i - sigma_i) = mu for all i; Newton on
-// h(mu) = sum ln s_i(mu) from mu = 0, at most 8 steps, stop when
-// |s1 s2 s3 - 1| < 1e-7.  Returns ds_i = s_i - sigma_i.
+// h(mu) = ln(s1 s2 s3)(mu) from mu = 0, at most 8 steps, stop when
+// |s1 s2 s3 - 1| is within 2 ulp of 1.  Near the root ln p is replaced by
+// (p - 1)/p, which has the same root and slope.  Returns ds_i = s_i - sigma_i.
 __device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_of_regime) {
     const float lo = (sg[2] > 0.0f) ? -0.25f * sg[2] * sg[2] : 0.0f;
     float mu = (sg[2] > 0.0f) ? 0.0f : 0.25f;
@@ -150,10 +157,10 @@ __device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_o
             s[i] = sg[i] + ds[i];
         }
         float p = s[0] * s[1] * s[2];
-        if (fabsf(p - 1.0f) < 1e-7f) break;
-        float h = logf(p);
-        float hp = 1.0f / (q[0] * s[0]) + 1.0f / (q[1] * s[1]) + 1.0f / (q[2] * s[2]);
-        float mun = mu - h / hp;
+        if (fabsf(p - 1.0f) < 2.4e-7f) break;
+        float h = (fabsf(p - 1.0f) < 0.25f) ? (p - 1.0f) * frcp(p) : logf(p);
+        float hp = frcp(q[0] * s[0]) + frcp(q[1] * s[1]) + frcp(q[2] * s[2]);
+        float mun = mu - h * frcp(hp);
         if (!(mun > lo)) mun = 0.5f * (mu + lo);
         mu = mun;
         if (it == 7) {
@@ -282,7 +289,8 @@ __global__ __launch_bounds__(BLK) void k_predict(int32_t nv, int32_t n_free, dou
 }
 
 // r_a = m_a (y_a - x_a) / dt^2 + sum over incident (corner, element) slots of
-// the element forces (fixed summation order: slots ascending).
+// the element forces.  Four lanes per vertex take every fourth slot and are
+// combined by a fixed butterfly, so the sum order is fixed (deterministic).
 __global__ __launch_bounds__(BLK) void k_residual(int32_t n_free, int32_t nt4,
                                                   const int32_t* __restrict__ inc_ptr,
                                                   const int32_t* __restrict__ inc_slot,
@@ -291,20 +299,29 @@ __global__ __launch_bounds__(BLK) void k_residual(int32_t n_free, int32_t nt4,
                                                   const double* __restrict__ x,
                                                   const double* __restrict__ y, double inv_dt2,
                                                   double* __restrict__ r) {
-    const int32_t a = blockIdx.x * BLK + threadIdx.x;
-    if (a >= n_free) return;
+    const int32_t gt = blockIdx.x * BLK + threadIdx.x;
+    const int32_t a = gt >> 2, sub = gt & 3;
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    const int32_t j1 = inc_ptr[a + 1];
-    for (int32_t j = inc_ptr[a]; j < j1; ++j) {
-        const int32_t s = inc_slot[j];
-        fx += fout[s];
-        fy += fout[nt4 + s];
-        fz += fout[2 * nt4 + s];
+    if (a < n_free) {
+        const int32_t j1 = inc_ptr[a + 1];
+        for (int32_t j = inc_ptr[a] + sub; j < j1; j += 4) {
+            const int32_t sl = inc_slot[j];
+            fx += fout[sl];
+            fy += fout[nt4 + sl];
+            fz += fout[2 * nt4 + sl];
+        }
     }
-    const double m = mass[a] * inv_dt2;
-    r[3 * a + 0] = m * (y[3 * a + 0] - x[3 * a + 0]) + (double)fx;
-    r[3 * a + 1] = m * (y[3 * a + 1] - x[3 * a + 1]) + (double)fy;
-    r[3 * a + 2] = m * (y[3 * a + 2] - x[3 * a + 2]) + (double)fz;
+    fx += __shfl_xor(fx, 1, 4);
+    fy += __shfl_xor(fy, 1, 4);
+    fz += __shfl_xor(fz, 1, 4);
+    fx += __shfl_xor(fx, 2, 4);
+    fy += __shfl_xor(fy, 2, 4);
+    fz += __shfl_xor(fz, 2, 4);
+    if (a < n_free && sub < 3) {
+        const double f = (sub == 0) ? (double)fx : (sub == 1) ? (double)fy : (double)fz;
+        const double m = mass[a] * inv_dt2;
+        r[3 * a + sub] = m * (y[3 * a + sub] - x[3 * a + sub]) + f;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -320,12 +337,13 @@ __device__ __forceinline__ T group_sum(T v) {
 }
 
 struct SolveArgs {
-    int32_t n_int, n_gamma, D;
-    const int32_t *sub_off, *sub_fwd_ph, *sub_bwd_ph;
-    const Phase* phases;
+    int32_t n_int, n_gamma, D, max_n, max_nb;
+    const int32_t *sub_off, *sub_fwd_ch, *sub_bwd_ch, *bnd, *bnd_off;
+    const Chunk* chunks;
     const Task* tasks;
     const Seg* segs;
-    const float* fvals;
+    const float* ivals;      // packed interior chunks
+    const float* fvals;      // interior factor blocks (interface condensation rows)
     const double* dvals;
     const int32_t* gidx;
     const double* r;
@@ -335,10 +353,36 @@ struct SolveArgs {
     float4* u;
 };
 
-__global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a, int32_t max_n) {
-    extern __shared__ float sm[];
-    float* R = sm;
-    float* Z = sm + 3 * max_n;
+// Coalesced copy of one chunk (nv4 float4) into registers / LDS.
+template <int NV4>
+__device__ __forceinline__ void chunk_load(const float4* __restrict__ src, int32_t nv4, float4 (&reg)[NV4]) {
+#pragma unroll
+    for (int i = 0; i < NV4; ++i) {
+        const int32_t j = threadIdx.x + i * BLK;
+        if (j < nv4) reg[i] = src[j];
+    }
+}
+template <int NV4>
+__device__ __forceinline__ void chunk_store(float4* dst, int32_t nv4, const float4 (&reg)[NV4]) {
+#pragma unroll
+    for (int i = 0; i < NV4; ++i) {
+        const int32_t j = threadIdx.x + i * BLK;
+        if (j < nv4) dst[j] = reg[i];
+    }
+}
+
+// Interior forward solve, one workgroup per subdomain.  The subdomain's
+// chunk program runs phase by phase; each chunk's values are staged in LDS
+// (double-buffered: the next chunk is read into registers while the current
+// one is computed).  FWD_PULL: R[o] -= sum vals * Z; FWD_TINV: Z[o] = sum vals * R.
+template <int NV4>
+__global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a) {
+    constexpr int32_t CH = NV4 * 4 * BLK;
+    extern __shared__ float4 sm4[];
+    float* sm = reinterpret_cast<float*>(sm4);
+    float* bufs[2] = {sm, sm + CH};
+    float* R = sm + 2 * CH;
+    float* Z = R + 3 * a.max_n;
     const int32_t d = blockIdx.x;
     const int32_t base = a.sub_off[d];
     const int32_t n = a.sub_off[d + 1] - base;
@@ -351,20 +395,35 @@ __global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a, int32_t max_n
     const int32_t chunk = (a.n_gamma + a.D - 1) / a.D;
     const int32_t g0 = d * chunk, g1 = min(a.n_gamma, g0 + chunk);
     for (int32_t i = 3 * g0 + tid; i < 3 * g1; i += BLK) a.rg[i] = a.r[3 * a.n_int + i];
+    const int32_t c0 = a.sub_fwd_ch[d], c1 = a.sub_fwd_ch[d + 1];
+    const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
+    float4 reg[NV4];
+    if (c0 < c1) {
+        const Chunk C = a.chunks[c0];
+        chunk_load<NV4>(iv4 + C.v0 / 4, (C.nv + 3) / 4, reg);
+        chunk_store<NV4>(reinterpret_cast<float4*>(bufs[0]), (C.nv + 3) / 4, reg);
+    }
     __syncthreads();
     const int grp = tid / IG, lane = tid % IG;
     constexpr int NGRP = BLK / IG;
-    const int32_t ph1 = a.sub_fwd_ph[d + 1];
-    for (int32_t ph = a.sub_fwd_ph[d]; ph < ph1; ++ph) {
-        const Phase P = a.phases[ph];
-        const float* Xv = (P.kind == FWD_PULL) ? Z : R;
-        for (int32_t t = P.task0 + grp; t < P.task1; t += NGRP) {
+    for (int32_t c = c0; c < c1; ++c) {
+        const Chunk C = a.chunks[c];
+        const float* cur = bufs[(c - c0) & 1];
+        const bool more = c + 1 < c1;
+        int32_t nxt4 = 0;
+        if (more) {
+            const Chunk Cn = a.chunks[c + 1];
+            nxt4 = (Cn.nv + 3) / 4;
+            chunk_load<NV4>(iv4 + Cn.v0 / 4, nxt4, reg);
+        }
+        const float* Xv = (C.kind == FWD_PULL) ? Z : R;
+        for (int32_t t = C.task0 + grp; t < C.task1; t += NGRP) {
             const Task T = a.tasks[t];
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
             for (int32_t g = T.seg0; g < T.seg1; ++g) {
                 const Seg S = a.segs[g];
                 for (int32_t k = lane; k < S.len; k += IG) {
-                    const float v = a.fvals[S.voff + k];
+                    const float v = cur[S.voff + k];
                     const float* xp = Xv + 3 * (S.xoff + k);
                     s0 += v * xp[0];
                     s1 += v * xp[1];
@@ -375,7 +434,7 @@ __global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a, int32_t max_n
             s1 = group_sum<IG>(s1);
             s2 = group_sum<IG>(s2);
             if (lane == 0) {
-                if (P.kind == FWD_PULL) {
+                if (C.kind == FWD_PULL) {
                     R[3 * T.out + 0] -= s0;
                     R[3 * T.out + 1] -= s1;
                     R[3 * T.out + 2] -= s2;
@@ -386,52 +445,88 @@ __global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a, int32_t max_n
                 }
             }
         }
+        if (more) chunk_store<NV4>(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
         __syncthreads();
     }
     for (int32_t i = tid; i < 3 * n; i += BLK) a.zf[3 * base + i] = Z[i];
 }
 
-// One wave per task.  FWD_PULL: rg[o] -= sum; FWD_TINV: zg[o] = sum;
+// One group of G lanes per task.  FWD_PULL: rg[o] -= sum; FWD_TINV: zg[o] = sum;
 // BWD_PULL: rg[o] = zg[o] - sum (gathered dg); BWD_TINV: dg[o] = sum.
+template <int G>
 __global__ __launch_bounds__(BLK) void k_iface(SolveArgs a, int32_t kind, int32_t task0,
                                                int32_t ntasks) {
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int32_t t = blockIdx.x * (BLK / 64) + wave;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int32_t t = blockIdx.x * (BLK / G) + grp;
     if (t >= ntasks) return;
     const Task T = a.tasks[task0 + t];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int32_t g = T.seg0; g < T.seg1; ++g) {
         const Seg S = a.segs[g];
         if (kind == FWD_PULL && S.kind == 1) {
-            for (int32_t k = lane; k < S.len; k += 64) {
-                const double v = (double)a.fvals[S.voff + k];
-                const float* xp = a.zf + 3 * (S.xoff + k);
+            const float* vp = a.fvals + S.voff;
+            const float* xb = a.zf + 3 * S.xoff;
+            int32_t k = lane;
+            for (; k + G < S.len; k += 2 * G) {
+                const double v0 = (double)vp[k], v1 = (double)vp[k + G];
+                const float* x0 = xb + 3 * k;
+                const float* x1 = xb + 3 * (k + G);
+                s0 += v0 * (double)x0[0] + v1 * (double)x1[0];
+                s1 += v0 * (double)x0[1] + v1 * (double)x1[1];
+                s2 += v0 * (double)x0[2] + v1 * (double)x1[2];
+            }
+            if (k < S.len) {
+                const double v = (double)vp[k];
+                const float* xp = xb + 3 * k;
                 s0 += v * (double)xp[0];
                 s1 += v * (double)xp[1];
                 s2 += v * (double)xp[2];
             }
         } else if (kind == BWD_PULL) {
-            for (int32_t k = lane; k < S.len; k += 64) {
-                const double v = a.dvals[S.voff + k];
-                const double* xp = a.dg + 3 * (a.gidx[S.xoff + k] - a.n_int);
+            const double* vp = a.dvals + S.voff;
+            const int32_t* ip = a.gidx + S.xoff;
+            int32_t k = lane;
+            for (; k + G < S.len; k += 2 * G) {
+                const double v0 = vp[k], v1 = vp[k + G];
+                const double* x0 = a.dg + 3 * (ip[k] - a.n_int);
+                const double* x1 = a.dg + 3 * (ip[k + G] - a.n_int);
+                s0 += v0 * x0[0] + v1 * x1[0];
+                s1 += v0 * x0[1] + v1 * x1[1];
+                s2 += v0 * x0[2] + v1 * x1[2];
+            }
+            if (k < S.len) {
+                const double v = vp[k];
+                const double* xp = a.dg + 3 * (ip[k] - a.n_int);
                 s0 += v * xp[0];
                 s1 += v * xp[1];
                 s2 += v * xp[2];
             }
         } else {
-            const double* xv = (kind == FWD_PULL) ? a.zg : a.rg;
-            for (int32_t k = lane; k < S.len; k += 64) {
-                const double v = a.dvals[S.voff + k];
-                const double* xp = xv + 3 * (S.xoff + k);
+            const double* vp = a.dvals + S.voff;
+            const double* xb = ((kind == FWD_PULL) ? a.zg : a.rg) + 3 * S.xoff;
+            int32_t k = lane;
+            for (; k + 3 * G < S.len; k += 4 * G) {
+                const double v0 = vp[k], v1 = vp[k + G], v2 = vp[k + 2 * G], v3 = vp[k + 3 * G];
+                const double* x0 = xb + 3 * k;
+                const double* x1 = xb + 3 * (k + G);
+                const double* x2 = xb + 3 * (k + 2 * G);
+                const double* x3 = xb + 3 * (k + 3 * G);
+                s0 += v0 * x0[0] + v1 * x1[0] + v2 * x2[0] + v3 * x3[0];
+                s1 += v0 * x0[1] + v1 * x1[1] + v2 * x2[1] + v3 * x3[1];
+                s2 += v0 * x0[2] + v1 * x1[2] + v2 * x2[2] + v3 * x3[2];
+            }
+            for (; k < S.len; k += G) {
+                const double v = vp[k];
+                const double* xp = xb + 3 * k;
                 s0 += v * xp[0];
                 s1 += v * xp[1];
                 s2 += v * xp[2];
             }
         }
     }
-    s0 = group_sum<64>(s0);
-    s1 = group_sum<64>(s1);
-    s2 = group_sum<64>(s2);
+    s0 = group_sum<G>(s0);
+    s1 = group_sum<G>(s1);
+    s2 = group_sum<G>(s2);
     if (lane == 0) {
         const int32_t o = 3 * T.out;
         if (kind == FWD_PULL) {
@@ -454,56 +549,71 @@ __global__ __launch_bounds__(BLK) void k_iface(SolveArgs a, int32_t kind, int32_
     }
 }
 
-__global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t max_n, int32_t apply,
-                                                      int32_t keep_delta) {
-    extern __shared__ float sm[];
-    float* Zl = sm;
-    float* Q = sm + 3 * max_n;
-    float* Dl = sm + 6 * max_n;
+// Interior backward solve and update, one workgroup per subdomain.  The
+// subdomain's boundary values of the interface solution are staged in LDS
+// after its interior rows, so every gather of a backward pull hits LDS.
+// BWD_PULL: ZQ[o] = ZQ[o] - sum vals * DL[gather] (in place, z -> q);
+// BWD_TINV: DL[o] = sum vals * ZQ.
+template <int NV4>
+__global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t apply, int32_t keep_delta) {
+    constexpr int32_t CH = NV4 * 4 * BLK;
+    extern __shared__ float4 sm4[];
+    float* sm = reinterpret_cast<float*>(sm4);
+    float* bufs[2] = {sm, sm + CH};
+    float* ZQ = sm + 2 * CH;
+    float* DL = ZQ + 3 * a.max_n;
     const int32_t d = blockIdx.x;
     const int32_t base = a.sub_off[d];
     const int32_t n = a.sub_off[d + 1] - base;
+    const int32_t b0 = a.bnd_off[d], nb = a.bnd_off[d + 1] - b0;
     const int tid = threadIdx.x;
     for (int32_t i = tid; i < 3 * n; i += BLK) {
-        Zl[i] = a.zf[3 * base + i];
-        Q[i] = 0.0f;
-        Dl[i] = 0.0f;
+        ZQ[i] = a.zf[3 * base + i];
+        DL[i] = 0.0f;
+    }
+    for (int32_t i = tid; i < 3 * nb; i += BLK) {
+        const int32_t k = i / 3, c = i - 3 * k;
+        DL[3 * n + i] = (float)a.dg[3 * (a.bnd[b0 + k] - a.n_int) + c];
+    }
+    const int32_t c0 = a.sub_bwd_ch[d], c1 = a.sub_bwd_ch[d + 1];
+    const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
+    float4 reg[NV4];
+    if (c0 < c1) {
+        const Chunk C = a.chunks[c0];
+        chunk_load<NV4>(iv4 + C.v0 / 4, (C.nv + 3) / 4, reg);
+        chunk_store<NV4>(reinterpret_cast<float4*>(bufs[0]), (C.nv + 3) / 4, reg);
     }
     __syncthreads();
     const int grp = tid / IG, lane = tid % IG;
     constexpr int NGRP = BLK / IG;
-    const int32_t ph1 = a.sub_bwd_ph[d + 1];
-    for (int32_t ph = a.sub_bwd_ph[d]; ph < ph1; ++ph) {
-        const Phase P = a.phases[ph];
-        for (int32_t t = P.task0 + grp; t < P.task1; t += NGRP) {
+    for (int32_t c = c0; c < c1; ++c) {
+        const Chunk C = a.chunks[c];
+        const float* cur = bufs[(c - c0) & 1];
+        const bool more = c + 1 < c1;
+        int32_t nxt4 = 0;
+        if (more) {
+            const Chunk Cn = a.chunks[c + 1];
+            nxt4 = (Cn.nv + 3) / 4;
+            chunk_load<NV4>(iv4 + Cn.v0 / 4, nxt4, reg);
+        }
+        for (int32_t t = C.task0 + grp; t < C.task1; t += NGRP) {
             const Task T = a.tasks[t];
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
             for (int32_t g = T.seg0; g < T.seg1; ++g) {
                 const Seg S = a.segs[g];
-                if (P.kind == BWD_PULL) {
+                if (C.kind == BWD_PULL) {
                     for (int32_t k = lane; k < S.len; k += IG) {
-                        const float v = a.fvals[S.voff + k];
-                        const int32_t gi = a.gidx[S.xoff + k];
-                        float x0, x1, x2;
-                        if (gi < a.n_int) {
-                            const float* xp = Dl + 3 * (gi - base);
-                            x0 = xp[0];
-                            x1 = xp[1];
-                            x2 = xp[2];
-                        } else {
-                            const double* xp = a.dg + 3 * (gi - a.n_int);
-                            x0 = (float)xp[0];
-                            x1 = (float)xp[1];
-                            x2 = (float)xp[2];
-                        }
-                        s0 += v * x0;
-                        s1 += v * x1;
-                        s2 += v * x2;
+                        const float v = cur[S.voff + k];
+                        const int32_t li = __float_as_int(cur[S.xoff + k]);
+                        const float* xp = DL + 3 * li;
+                        s0 += v * xp[0];
+                        s1 += v * xp[1];
+                        s2 += v * xp[2];
                     }
                 } else {
                     for (int32_t k = lane; k < S.len; k += IG) {
-                        const float v = a.fvals[S.voff + k];
-                        const float* xp = Q + 3 * (S.xoff + k);
+                        const float v = cur[S.voff + k];
+                        const float* xp = ZQ + 3 * (S.xoff + k);
                         s0 += v * xp[0];
                         s1 += v * xp[1];
                         s2 += v * xp[2];
@@ -515,17 +625,18 @@ __global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t max_n
             s2 = group_sum<IG>(s2);
             if (lane == 0) {
                 const int32_t o = 3 * T.out;
-                if (P.kind == BWD_PULL) {
-                    Q[o] = Zl[o] - s0;
-                    Q[o + 1] = Zl[o + 1] - s1;
-                    Q[o + 2] = Zl[o + 2] - s2;
+                if (C.kind == BWD_PULL) {
+                    ZQ[o] -= s0;
+                    ZQ[o + 1] -= s1;
+                    ZQ[o + 2] -= s2;
                 } else {
-                    Dl[o] = s0;
-                    Dl[o + 1] = s1;
-                    Dl[o + 2] = s2;
+                    DL[o] = s0;
+                    DL[o + 1] = s1;
+                    DL[o + 2] = s2;
                 }
             }
         }
+        if (more) chunk_store<NV4>(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
         __syncthreads();
     }
     // interior rows of this subdomain
@@ -534,7 +645,7 @@ __global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t max_n
         float du[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double dv = (double)Dl[3 * i + c];
+            const double dv = (double)DL[3 * i + c];
             if (keep_delta) a.delta[3 * gi + c] = dv;
             if (apply) {
                 const double xn = a.x[3 * gi + c] + dv;
@@ -605,12 +716,17 @@ SolveArgs solve_args(const DevMesh& m) {
     a.n_int = m.n_int;
     a.n_gamma = m.n_gamma;
     a.D = m.D;
+    a.max_n = m.max_sub_n;
+    a.max_nb = m.max_nb;
     a.sub_off = m.sub_off;
-    a.sub_fwd_ph = m.sub_fwd_ph;
-    a.sub_bwd_ph = m.sub_bwd_ph;
-    a.phases = m.phases;
+    a.sub_fwd_ch = m.sub_fwd_ch;
+    a.sub_bwd_ch = m.sub_bwd_ch;
+    a.bnd = m.bnd;
+    a.bnd_off = m.bnd_off;
+    a.chunks = m.chunks;
     a.tasks = m.tasks;
     a.segs = m.segs;
+    a.ivals = m.ivals;
     a.fvals = m.fvals;
     a.dvals = m.dvals;
     a.gidx = m.gidx;
@@ -647,28 +763,66 @@ hipError_t launch_local(const DevMesh& m, hipStream_t s, bool debug) {
 }
 
 hipError_t launch_residual(const DevMesh& m, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual, dim3(nblk(m.n_free)), dim3(BLK), 0, s, m.n_free, 4 * m.nt,
+    hipLaunchKernelGGL(k_residual, dim3(nblk(4 * (int64_t)m.n_free)), dim3(BLK), 0, s, m.n_free, 4 * m.nt,
                        m.inc_ptr, m.inc_slot, m.fout, m.mass, m.x, m.y, 1.0 / (m.dt * m.dt), m.r);
     return hipGetLastError();
 }
 
+size_t interior_fwd_lds(const DevMesh& m) {
+    return sizeof(float) * (2 * (size_t)m.chunk_nv4 * 4 * BLK + 6 * (size_t)m.max_sub_n);
+}
+
+size_t interior_bwd_lds(const DevMesh& m) {
+    return sizeof(float) *
+           (2 * (size_t)m.chunk_nv4 * 4 * BLK + 6 * (size_t)m.max_sub_n + 3 * (size_t)m.max_nb);
+}
+
+hipError_t interior_set_lds_limit(int chunk_nv4, size_t bytes) {
+    hipError_t e = hipSuccess;
+    if (chunk_nv4 == 8) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_fwd<8>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_bwd<8>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    } else {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_fwd<4>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_bwd<4>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    }
+    return e;
+}
+
 hipError_t launch_interior_fwd(const DevMesh& m, hipStream_t s) {
-    size_t sh = sizeof(float) * 6 * (size_t)m.max_sub_n;
-    hipLaunchKernelGGL(k_interior_fwd, dim3(m.D), dim3(BLK), sh, s, solve_args(m), m.max_sub_n);
+    const size_t sh = interior_fwd_lds(m);
+    if (m.chunk_nv4 == 8)
+        hipLaunchKernelGGL(k_interior_fwd<8>, dim3(m.D), dim3(BLK), sh, s, solve_args(m));
+    else
+        hipLaunchKernelGGL(k_interior_fwd<4>, dim3(m.D), dim3(BLK), sh, s, solve_args(m));
     return hipGetLastError();
 }
 
 hipError_t launch_interface_phase(const DevMesh& m, const PhaseLaunch& ph, hipStream_t s) {
     if (ph.ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_iface, dim3((ph.ntasks + 3) / 4), dim3(BLK), 0, s, solve_args(m), ph.kind,
-                       ph.task0, ph.ntasks);
+    if (ph.group == 64)
+        hipLaunchKernelGGL(k_iface<64>, dim3((ph.ntasks + 3) / 4), dim3(BLK), 0, s, solve_args(m),
+                           ph.kind, ph.task0, ph.ntasks);
+    else
+        hipLaunchKernelGGL(k_iface<16>, dim3((ph.ntasks + 15) / 16), dim3(BLK), 0, s, solve_args(m),
+                           ph.kind, ph.task0, ph.ntasks);
     return hipGetLastError();
 }
 
 hipError_t launch_interior_bwd(const DevMesh& m, hipStream_t s, bool apply, bool keep_delta) {
-    size_t sh = sizeof(float) * 9 * (size_t)m.max_sub_n;
-    hipLaunchKernelGGL(k_interior_bwd, dim3(m.D), dim3(BLK), sh, s, solve_args(m), m.max_sub_n,
-                       (int32_t)apply, (int32_t)keep_delta);
+    const size_t sh = interior_bwd_lds(m);
+    if (m.chunk_nv4 == 8)
+        hipLaunchKernelGGL(k_interior_bwd<8>, dim3(m.D), dim3(BLK), sh, s, solve_args(m),
+                           (int32_t)apply, (int32_t)keep_delta);
+    else
+        hipLaunchKernelGGL(k_interior_bwd<4>, dim3(m.D), dim3(BLK), sh, s, solve_args(m),
+                           (int32_t)apply, (int32_t)keep_delta);
     return hipGetLastError();
 }
 

@@ -45,6 +45,16 @@ struct Phase {
 
 enum PhaseKind { FWD_PULL = 0, FWD_TINV = 1, BWD_PULL = 2, BWD_TINV = 3 };
 
+// A piece of an interior phase whose values (and gather indices) are
+// contiguous in Plan::ivals, so one workgroup can stage it in LDS with one
+// coalesced copy.  Segment voff/xoff of its tasks are relative to v0.
+struct Chunk {
+    int32_t kind;
+    int32_t task0, task1;
+    int32_t v0, nv;       // [v0, v0 + nv) in ivals, v0 % 4 == 0
+    int32_t pad[3];
+};
+
 struct Plan {
     // sizes
     int32_t nv = 0, nt = 0, n_free = 0, n_int = 0, n_gamma = 0, D = 1;
@@ -85,6 +95,12 @@ struct Plan {
     std::vector<Task> tasks;
     std::vector<Phase> phases;
     std::vector<int32_t> sub_fwd_ph, sub_bwd_ph;   // D+1 ranges into phases (per subdomain)
+    // interior programs as LDS chunks (values and gather indices packed)
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> sub_fwd_ch, sub_bwd_ch;   // D+1 ranges into chunks
+    std::vector<float> ivals;                      // packed interior values
+    std::vector<int32_t> bnd, bnd_off;             // per subdomain: interface rows it touches
+    int32_t max_nb = 0, chunk_floats = 0;
     std::vector<int32_t> coarse_fwd_ph, coarse_bwd_ph;  // ranges of phases, one launch each
     int32_t max_sub_phases = 0, max_sub_n = 0, n_clevels = 0;
 
@@ -95,8 +111,8 @@ struct Plan {
 int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                const double* gamma_s, const double* gamma_v, const double* mass,
                const uint8_t* pinned, const double* gravity, double dt, int32_t pd_iters,
-               int32_t n_subdomains, int32_t refine_steps, int32_t leaf_max, Plan& plan,
-               std::string& msg);
+               int32_t n_subdomains, int32_t refine_steps, int32_t leaf_max,
+               int32_t chunk_floats, Plan& plan, std::string& msg);
 
 // Rest-shape checks used at mesh creation: every tet has positive volume.
 int check_mesh(const double* X, int32_t nv, const int32_t* tets, int32_t nt, std::string& msg);

@@ -32,7 +32,7 @@ void* vhp_build(const double* X, int nv, const int* tets, int nt, const double* 
                 int D, int refine, int leaf_max, int* rc, char* msg, int msglen) {
     Plan* P = new Plan();
     std::string m;
-    *rc = build_plan(X, nv, tets, nt, gs, gv, mass, pinned, g, dt, iters, D, refine, leaf_max, *P, m);
+    *rc = build_plan(X, nv, tets, nt, gs, gv, mass, pinned, g, dt, iters, D, refine, leaf_max, 4096, *P, m);
     std::snprintf(msg, msglen, "%s", m.c_str());
     if (*rc != 0) {
         delete P;
@@ -68,24 +68,23 @@ void vhp_solve(void* h, const double* rhs, double* d) {
     for (int c = 0; c < 3; ++c) {
         std::vector<double> Rc(P.n_free), Zc(P.n_free, 0.0), Dc(P.n_free, 0.0);
         for (int i = 0; i < P.n_free; ++i) Rc[i] = R[3 * i + c];
-        // interior forward
+        // interior forward (chunk programs, values from ivals)
         for (int s = 0; s < P.D; ++s) {
             const int base = P.sub_off[s], nloc = P.sub_off[s + 1] - base;
             std::vector<double> r(Rc.begin() + base, Rc.begin() + base + nloc), z(nloc, 0.0);
-            for (int ph = P.sub_fwd_ph[s]; ph < P.sub_fwd_ph[s + 1]; ++ph) {
-                const Phase& Ph = P.phases[ph];
-                std::vector<double> outv(Ph.task1 - Ph.task0);
-                for (int t = Ph.task0; t < Ph.task1; ++t) {
+            for (int ch = P.sub_fwd_ch[s]; ch < P.sub_fwd_ch[s + 1]; ++ch) {
+                const Chunk& C = P.chunks[ch];
+                const float* cur = P.ivals.data() + C.v0;
+                for (int t = C.task0; t < C.task1; ++t) {
                     const Task& T = P.tasks[t];
                     double acc = 0.0;
-                    for (int g = T.seg0; g < T.seg1; ++g)
-                        acc += seg_dot(P, P.segs[g], Ph.kind == FWD_PULL ? z.data() : r.data());
-                    outv[t - Ph.task0] = (Ph.kind == FWD_PULL) ? r[T.out] - acc : acc;
-                }
-                for (int t = Ph.task0; t < Ph.task1; ++t) {
-                    const Task& T = P.tasks[t];
-                    if (Ph.kind == FWD_PULL) r[T.out] = outv[t - Ph.task0];
-                    else z[T.out] = outv[t - Ph.task0];
+                    for (int g = T.seg0; g < T.seg1; ++g) {
+                        const Seg& S = P.segs[g];
+                        const std::vector<double>& xv = (C.kind == FWD_PULL) ? z : r;
+                        for (int k = 0; k < S.len; ++k) acc += (double)cur[S.voff + k] * xv[S.xoff + k];
+                    }
+                    if (C.kind == FWD_PULL) r[T.out] -= acc;
+                    else z[T.out] = acc;
                 }
             }
             for (int i = 0; i < nloc; ++i) Zc[base + i] = z[i];
@@ -136,34 +135,32 @@ void vhp_solve(void* h, const double* rhs, double* d) {
             }
         }
         for (int i = 0; i < ng; ++i) Dc[nint + i] = D64[i];
-        // interior backward
+        // interior backward (chunk programs, gathers through the staged boundary rows)
         for (int s = 0; s < P.D; ++s) {
             const int base = P.sub_off[s], nloc = P.sub_off[s + 1] - base;
-            std::vector<double> q(nloc, 0.0), z(Zc.begin() + base, Zc.begin() + base + nloc), dl(nloc, 0.0);
-            for (int ph = P.sub_bwd_ph[s]; ph < P.sub_bwd_ph[s + 1]; ++ph) {
-                const Phase& Ph = P.phases[ph];
-                std::vector<double> outv(Ph.task1 - Ph.task0);
-                for (int t = Ph.task0; t < Ph.task1; ++t) {
+            const int b0 = P.bnd_off[s], nb = P.bnd_off[s + 1] - b0;
+            std::vector<double> zq(Zc.begin() + base, Zc.begin() + base + nloc), dl(nloc + nb, 0.0);
+            for (int k = 0; k < nb; ++k) dl[nloc + k] = (double)(float)D64[P.bnd[b0 + k] - nint];
+            for (int ch = P.sub_bwd_ch[s]; ch < P.sub_bwd_ch[s + 1]; ++ch) {
+                const Chunk& C = P.chunks[ch];
+                const float* cur = P.ivals.data() + C.v0;
+                for (int t = C.task0; t < C.task1; ++t) {
                     const Task& T = P.tasks[t];
                     double acc = 0.0;
                     for (int g = T.seg0; g < T.seg1; ++g) {
                         const Seg& S = P.segs[g];
-                        if (Ph.kind == BWD_PULL) {
-                            for (int k = 0; k < S.len; ++k) {
-                                int gi = P.gidx[S.xoff + k];
-                                double xv = gi < nint ? dl[gi - base] : D64[gi - nint];
-                                acc += (double)P.fvals[S.voff + k] * xv;
+                        for (int k = 0; k < S.len; ++k) {
+                            if (C.kind == BWD_PULL) {
+                                int li;
+                                std::memcpy(&li, cur + S.xoff + k, 4);
+                                acc += (double)cur[S.voff + k] * dl[li];
+                            } else {
+                                acc += (double)cur[S.voff + k] * zq[S.xoff + k];
                             }
-                        } else {
-                            acc += seg_dot(P, S, q.data());
                         }
                     }
-                    outv[t - Ph.task0] = (Ph.kind == BWD_PULL) ? z[T.out] - acc : acc;
-                }
-                for (int t = Ph.task0; t < Ph.task1; ++t) {
-                    const Task& T = P.tasks[t];
-                    if (Ph.kind == BWD_PULL) q[T.out] = outv[t - Ph.task0];
-                    else dl[T.out] = outv[t - Ph.task0];
+                    if (C.kind == BWD_PULL) zq[T.out] -= acc;
+                    else dl[T.out] = acc;
                 }
             }
             for (int i = 0; i < nloc; ++i) Dc[base + i] = dl[i];
@@ -173,5 +170,20 @@ void vhp_solve(void* h, const double* rhs, double* d) {
     for (int u = 0; u < P.nv * 3; ++u) d[u] = 0.0;
     for (int i = 0; i < P.n_free; ++i)
         for (int c = 0; c < 3; ++c) d[3 * P.perm[i] + c] = Dv[3 * i + c];
+}
+}
+
+extern "C" {
+// per supernode: sub, n, m (rows below), m_interface (rows below in the interface), height, clevel
+int vhp_sn_stats(void* h, int* out) {
+    const Plan& P = *static_cast<Plan*>(h);
+    int k = 0;
+    for (const auto& s : P.sn) {
+        int mg = 0;
+        for (int r : s.rows) mg += (r >= P.n_int);
+        out[k++] = s.sub; out[k++] = s.n; out[k++] = (int)s.rows.size(); out[k++] = mg;
+        out[k++] = s.height; out[k++] = s.clevel;
+    }
+    return (int)P.sn.size();
 }
 }

@@ -242,3 +242,53 @@ def test_budget_refuses(vh):
     assert c.hbm_in_use() == 0
     m.close()
     c.close()
+
+
+def test_graph_replay_equals_direct_launches(vh, ctx):
+    """The frame replayed as a HIP graph is bitwise equal to direct launches,
+    on every replay."""
+    import os
+    say("[graph vs direct]")
+    p = synth.problem_by_name("shell_small")
+    a = make_mesh(vh, ctx, p)
+    os.environ["VHPD_NO_GRAPH"] = "1"
+    try:
+        b = make_mesh(vh, ctx, p)
+    finally:
+        del os.environ["VHPD_NO_GRAPH"]
+    for _ in range(4):
+        a.step(1)
+        b.step(1)
+        xa, va = a.read_state()
+        xb, vb = b.read_state()
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    a.close()
+    b.close()
+
+
+def test_full_shell_matches_oracle(vh, ctx):
+    """The 390,400-tet shell with 128 subdomains (the benchmark configuration):
+    the first frame from rest and one lock-step frame from the oracle's state,
+    each within 1e-5 relative L2 of the FP64 oracle."""
+    say("[full shell] building")
+    p = synth.problem_by_name("shell")
+    m = make_mesh(vh, ctx, p)
+    say("[full shell] oracle setup")
+    sim = oracle.OracleSim.from_problem(p)
+    x0, v0 = p.initial_state()
+    m.step(1)
+    xg, _ = m.read_state()
+    say("[full shell] oracle frame 1")
+    x1, v1 = sim.step(x0, v0)
+    e1 = rel_l2(xg, x1)
+    say(f"   frame 1: rel L2 {e1:.3e}, displacement-relative {rel_disp(xg, x1, p.X):.3e}")
+    assert e1 <= 1e-5
+    m.write_state(x1, v1)
+    m.step(1)
+    xg2, _ = m.read_state()
+    say("[full shell] oracle frame 2")
+    x2, _ = sim.step(x1, v1)
+    e2 = rel_l2(xg2, x2)
+    say(f"   frame 2 (lock-step): rel L2 {e2:.3e}, displacement-relative {rel_disp(xg2, x2, p.X):.3e}")
+    assert e2 <= 1e-5
+    m.close()
