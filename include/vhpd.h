@@ -66,6 +66,8 @@ const char* vh_last_error(void);
  * holds for all meshes of this context (0 = unlimited).  The device is made
  * current on the calling thread. */
 int vh_ctx_create(vh_ctx** out, int device, size_t hbm_budget_bytes);
+/* Destroys the context and every mesh still alive on it (their handles become
+ * invalid). */
 int vh_ctx_destroy(vh_ctx* ctx);
 /* Device bytes currently held by the context's meshes. */
 int vh_ctx_hbm_in_use(const vh_ctx* ctx, size_t* bytes);

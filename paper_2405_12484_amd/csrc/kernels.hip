@@ -35,7 +35,9 @@ __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void jacobi_pair(float& app, float& aqq, float& apq, float& arp,
                                             float& arq, float* W, int p, int q) {
-    if (apq == 0.0f) return;
+    // tiny (possibly denormal) off-diagonals: no rotation; the hardware
+    // reciprocal of a denormal is inf and would turn tau into 0 * inf
+    if (!(fabsf(apq) > 1e-30f)) return;
     float tau = (aqq - app) * frcp(2.0f * apq);
     float t = copysignf(frcp(fabsf(tau) + fsqrt(1.0f + tau * tau)), tau);
     float c = frsq(1.0f + t * t);

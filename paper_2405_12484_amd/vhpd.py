@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -114,6 +115,7 @@ class Context:
         h = ctypes.c_void_p()
         _check(_lib.vh_ctx_create(ctypes.byref(h), device, hbm_budget))
         self.h = h
+        self._meshes = weakref.WeakSet()
 
     def hbm_in_use(self) -> int:
         b = ctypes.c_size_t()
@@ -121,7 +123,10 @@ class Context:
         return b.value
 
     def close(self):
+        """Destroy the context and every mesh still open on it."""
         if self.h:
+            for m in list(self._meshes):
+                m.close()
             _lib.vh_ctx_destroy(self.h)
             self.h = None
 
@@ -140,9 +145,12 @@ class Mesh:
         self.X = np.ascontiguousarray(X, dtype=np.float64)
         self.tets = np.ascontiguousarray(tets, dtype=np.int32)
         self.nv, self.nt = self.X.shape[0], self.tets.shape[0]
+        if not ctx.h:
+            raise VHError(VH_ESTATE, "context is closed")
         h = ctypes.c_void_p()
         _check(_lib.vh_mesh_create(ctx.h, ctypes.byref(h), _ptr(self.X), self.nv, _ptr(self.tets), self.nt))
         self.h = h
+        ctx._meshes.add(self)
 
     def set_params(self, gamma_s, gamma_v, mass, pinned, gravity, dt, pd_iters=10):
         gs = np.ascontiguousarray(gamma_s, dtype=np.float64)
@@ -236,7 +244,8 @@ class Mesh:
 
     def close(self):
         if getattr(self, "h", None):
-            _lib.vh_mesh_destroy(self.h)
+            if self.ctx.h:                      # a closed context already destroyed it
+                _lib.vh_mesh_destroy(self.h)
             self.h = None
 
     def __del__(self):
