@@ -389,6 +389,7 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     d.D = P.D;
     d.max_sub_n = std::max(P.max_sub_n, 1);
     d.max_nb = P.max_nb;
+    d.max_cint = P.max_cint;
     d.chunk_nv4 = nv4;
     const size_t lds_need = std::max(vh::interior_fwd_lds(d), vh::interior_bwd_lds(d));
     if (lds_need > (size_t)lds_limit)
@@ -423,21 +424,19 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     chk(dalloc(m, &d.zg, (size_t)P.n_gamma * 3));
     chk(dalloc(m, &d.dg, (size_t)P.n_gamma * 3));
     chk(dalloc(m, &d.delta, (size_t)P.n_free * 3));
-    chk(upload(m, &d.fvals, P.fvals));
-    chk(upload(m, &d.dvals, P.dvals));
-    chk(upload(m, &d.gidx, P.gidx));
-    chk(upload(m, &d.segs, P.segs));
-    chk(upload(m, &d.tasks, P.tasks));
-    chk(upload(m, &d.phases, P.phases));
     chk(upload(m, &d.sub_off, P.sub_off));
-    chk(upload(m, &d.sub_fwd_ph, P.sub_fwd_ph));
-    chk(upload(m, &d.sub_bwd_ph, P.sub_bwd_ph));
     chk(upload(m, &d.chunks, P.chunks));
     chk(upload(m, &d.sub_fwd_ch, P.sub_fwd_ch));
     chk(upload(m, &d.sub_bwd_ch, P.sub_bwd_ch));
     chk(upload(m, &d.ivals, P.ivals));
     chk(upload(m, &d.bnd, P.bnd));
     chk(upload(m, &d.bnd_off, P.bnd_off));
+    chk(upload(m, &d.dvals, P.dvals));
+    chk(upload(m, &d.ctasks, P.ctasks));
+    chk(upload(m, &d.cslots, P.cslots));
+    chk(upload(m, &d.cgidx, P.cgidx));
+    chk(dalloc(m, &d.cgf, (size_t)P.n_cgf * 3));
+    chk(dalloc(m, &d.cgd, (size_t)P.n_cgd * 3));
     chk(upload(m, &d.K_ptr, P.K_ptr));
     chk(upload(m, &d.K_col, P.K_col));
     chk(upload(m, &d.K_val, P.K_val));
@@ -451,18 +450,8 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     VH_HIP(hipMemset(d.delta, 0, (size_t)P.n_free * 3 * sizeof(double)));
     m->fwd.clear();
     m->bwd.clear();
-    // lanes per task: a full wave for long dot products, 16 lanes for short ones
-    auto launch_of = [&](int32_t ph) {
-        const vh::Phase& Ph = P.phases[ph];
-        int64_t len = 0;
-        for (int32_t t = Ph.task0; t < Ph.task1; ++t)
-            for (int32_t g = P.tasks[t].seg0; g < P.tasks[t].seg1; ++g) len += P.segs[g].len;
-        const int32_t nt = Ph.task1 - Ph.task0;
-        const int32_t group = (nt > 0 && len / nt >= 96) ? 64 : 16;
-        return vh::PhaseLaunch{Ph.kind, Ph.task0, nt, group};
-    };
-    for (int32_t ph : P.coarse_fwd_ph) m->fwd.push_back(launch_of(ph));
-    for (int32_t ph : P.coarse_bwd_ph) m->bwd.push_back(launch_of(ph));
+    m->fwd = P.cfwd;
+    m->bwd = P.cbwd;
     m->refine = refine_steps;
     const char* ng = std::getenv("VHPD_NO_GRAPH");
     m->use_graph = !(ng && ng[0] == '1');

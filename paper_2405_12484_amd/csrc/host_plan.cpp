@@ -691,40 +691,37 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             if (SN[t].sub < 0) symbolic(t, buf);
         (void)sub_first;
     }
-    // value offsets
-    int64_t fo = 0, dof = 0, go = 0;
+    // value offsets.  Per supernode t with inverted diagonal block Ti = L_tt^{-1}
+    // and rows below B (m x n), the solve uses W_B = B Ti:
+    //   forward   [z_t; c_t] = [Ti; W_B] r'_t      (c_t: contributions to the rows below)
+    //   backward  d_t = Ti^T z_t - W_B^T d_{R_t}
+    // Wf (row-major rows of [Ti; W_B]) and Wb (columns of [Ti; -W_B], each from its
+    // diagonal down) are stored, tri + m n values each.
+    int64_t fo = 0, dof = 0;
     for (int32_t t = 0; t < nsn; ++t) {
         Supernode& s = SN[t];
         int64_t n = s.n, m = (int64_t)s.rows.size();
-        int64_t tri = n * (n + 1) / 2;
+        int64_t blk = n * (n + 1) / 2 + m * n;
         int64_t& o = (s.sub >= 0) ? fo : dof;
-        s.tinv_off = o;
-        o += tri;
-        s.tinvT_off = o;
-        o += tri;
-        s.b_off = o;
-        o += m * n;
-        s.bT_off = o;
-        o += m * n;
-        s.rows_off = go;
-        go += m;
-        if (s.sub >= 0) P.nnz_int += tri + m * n;
-        else P.nnz_coarse += tri + m * n;
+        s.wf_off = o;
+        o += blk;
+        s.wb_off = o;
+        o += blk;
+        if (s.sub >= 0) P.nnz_int += blk;
+        else P.nnz_coarse += blk;
     }
-    if (fo >= ((int64_t)1 << 31) || dof >= ((int64_t)1 << 31)) {
-        msg = "factor too large for 32-bit offsets";
+    if (dof >= ((int64_t)1 << 31)) {
+        msg = "interface factor too large for 32-bit offsets";
         return ENOMEM_;
     }
+    std::vector<double> ivd;
     try {
-        P.fvals.assign(fo, 0.0f);
+        ivd.assign(fo, 0.0);
         P.dvals.assign(dof, 0.0);
-        P.gidx.resize(go);
     } catch (...) {
         msg = "host allocation of the factor failed";
         return ENOMEM_;
     }
-    for (int32_t t = 0; t < nsn; ++t)
-        std::copy(SN[t].rows.begin(), SN[t].rows.end(), P.gidx.begin() + SN[t].rows_off);
 
     // ---- numeric: multifrontal FP64 --------------------------------------------------
     std::vector<std::vector<double>> upd(nsn);
@@ -758,24 +755,35 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         if (rc != OK) return rc;
         std::vector<double> Ti;
         lower_inverse(F.data(), f, n, Ti, par);
-        auto store = [&](auto* vals) {
-            using T = std::remove_pointer_t<decltype(vals)>;
-            for (int32_t a = 0; a < n; ++a)
-                for (int32_t b = 0; b <= a; ++b)
-                    vals[s.tinv_off + (int64_t)a * (a + 1) / 2 + b] = (T)Ti[(size_t)a * n + b];
-            for (int32_t a = 0; a < n; ++a) {
-                int64_t off = s.tinvT_off + (int64_t)a * n - (int64_t)a * (a - 1) / 2;
-                for (int32_t i = a; i < n; ++i) vals[off + (i - a)] = (T)Ti[(size_t)i * n + a];
+        // W_B[p][a] = sum_{b >= a} B[p][b] Ti[b][a], B[p][b] = F(n + p, b)
+        std::vector<double> WB((size_t)m * n, 0.0);
+        auto wrow = [&](int32_t p) {
+            for (int32_t b = 0; b < n; ++b) {
+                const double bv = F[(size_t)b * f + n + p];
+                if (bv == 0.0) continue;
+                const double* tr = &Ti[(size_t)b * n];
+                double* wr = &WB[(size_t)p * n];
+                for (int32_t a = 0; a <= b; ++a) wr[a] += bv * tr[a];
             }
-            for (int32_t p = 0; p < m; ++p)
-                for (int32_t a = 0; a < n; ++a) {
-                    double v = F[(size_t)a * f + n + p];
-                    vals[s.b_off + (int64_t)p * n + a] = (T)v;
-                    vals[s.bT_off + (int64_t)a * m + p] = (T)v;
-                }
         };
-        if (s.sub >= 0) store(P.fvals.data());
-        else store(P.dvals.data());
+        if (par && (int64_t)m * n * n > 4000000) {
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int32_t p = 0; p < m; ++p) wrow(p);
+        } else {
+            for (int32_t p = 0; p < m; ++p) wrow(p);
+        }
+        double* vals = (s.sub >= 0) ? ivd.data() : P.dvals.data();
+        const int64_t tri = (int64_t)n * (n + 1) / 2;
+        for (int32_t a = 0; a < n; ++a)
+            for (int32_t b = 0; b <= a; ++b) vals[s.wf_off + (int64_t)a * (a + 1) / 2 + b] = Ti[(size_t)a * n + b];
+        for (int32_t p = 0; p < m; ++p)
+            for (int32_t a = 0; a < n; ++a) vals[s.wf_off + tri + (int64_t)p * n + a] = WB[(size_t)p * n + a];
+        for (int32_t k = 0; k < n; ++k) {
+            int64_t off = s.wb_off + (int64_t)k * (n + m) - (int64_t)k * (k - 1) / 2;
+            for (int32_t i = k; i < n; ++i) vals[off + (i - k)] = Ti[(size_t)i * n + k];
+            off += n - k;
+            for (int32_t p = 0; p < m; ++p) vals[off + p] = -WB[(size_t)p * n + k];
+        }
         std::vector<double> U((size_t)m * m);
         for (int32_t b = 0; b < m; ++b)
             for (int32_t a = b; a < m; ++a) U[(size_t)b * m + a] = F[(size_t)(n + b) * f + n + a];
@@ -814,287 +822,281 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         }
     }
 
-    // ---- solve programs ------------------------------------------------------------
-    // forward pull segments per row: for every supernode s and every row p of it
-    std::vector<std::vector<Seg>> pull_int(nf), pull_gam(nf);
-    for (int32_t s = 0; s < nsn; ++s) {
-        const Supernode& S = SN[s];
+    // ---- contribution slots ------------------------------------------------------------
+    // Row p of supernode t contributes c_t[p] to row R_t[p].  Interior rows of an
+    // interior supernode get a slot in its subdomain's LDS buffer, interface rows of
+    // an interior supernode a global FP32 slot, rows of an interface supernode a
+    // global FP64 slot.  Each receiving row sums its slots in (t, p) order.
+    std::vector<std::vector<int32_t>> pull_i(nf), pull_f(nf), pull_d(nf);
+    std::vector<int32_t> cint_used(D, 0);
+    int32_t ncgf = 0, ncgd = 0;
+    for (int32_t t = 0; t < nsn; ++t) {
+        Supernode& S = SN[t];
         const int32_t m = (int32_t)S.rows.size();
-        for (int32_t p = 0; p < m; ++p) {
-            int32_t r = S.rows[p];
-            Seg g;
-            g.voff = (int32_t)(S.b_off + (int64_t)p * S.n);
-            g.len = S.n;
-            g.kind = (S.sub >= 0) ? 1 : 0;
-            if (S.sub >= 0) {
-                // interior source: x offset local to the subdomain for interior rows,
-                // global interior index for interface rows
-                g.xoff = (r < P.n_int) ? S.col0 - P.sub_off[S.sub] : S.col0;
-                pull_int[r].push_back(g);
-            } else {
-                g.xoff = S.col0 - P.n_int;
-                pull_gam[r].push_back(g);
-            }
+        int32_t mi = 0;
+        while (mi < m && S.rows[mi] < P.n_int) ++mi;
+        S.m_int = mi;
+        if (S.sub >= 0) {
+            S.cint0 = cint_used[S.sub];
+            cint_used[S.sub] += mi;
+            S.cg0 = ncgf;
+            ncgf += m - mi;
+            for (int32_t p = 0; p < mi; ++p) pull_i[S.rows[p]].push_back(S.cint0 + p);
+            for (int32_t p = mi; p < m; ++p) pull_f[S.rows[p]].push_back(S.cg0 + p - mi);
+        } else {
+            S.cg0 = ncgd;
+            ncgd += m;
+            for (int32_t p = 0; p < m; ++p) pull_d[S.rows[p]].push_back(S.cg0 + p);
         }
     }
-    auto add_task = [&](int32_t out, const std::vector<Seg>& sg) {
-        Task tk;
-        tk.out = out;
-        tk.seg0 = (int32_t)P.segs.size();
-        P.segs.insert(P.segs.end(), sg.begin(), sg.end());
-        tk.seg1 = (int32_t)P.segs.size();
-        tk.pad = 0;
-        P.tasks.push_back(tk);
-    };
-    auto begin_phase = [&](int32_t kind) {
-        Phase ph;
-        ph.kind = kind;
-        ph.task0 = (int32_t)P.tasks.size();
-        ph.task1 = ph.task0;
-        ph.pad = 0;
-        P.phases.push_back(ph);
-    };
-    auto end_phase = [&]() {
-        P.phases.back().task1 = (int32_t)P.tasks.size();
-        if (P.phases.back().task1 == P.phases.back().task0) P.phases.pop_back();
-    };
-    // interior programs
-    P.sub_fwd_ph.assign(D + 1, 0);
-    P.sub_bwd_ph.assign(D + 1, 0);
-    std::vector<std::vector<int32_t>> sub_sn(D);
-    for (int32_t t = 0; t < nsn; ++t)
-        if (SN[t].sub >= 0) sub_sn[SN[t].sub].push_back(t);
-    std::vector<Seg> one(1);
-    std::vector<int32_t> fwd_begin(D), bwd_begin(D), fwd_end(D), bwd_end(D);
-    for (int32_t d = 0; d < D; ++d) {
-        int32_t H = -1;
-        for (int32_t t : sub_sn[d]) H = std::max(H, SN[t].height);
-        const int32_t base = P.sub_off[d];
-        fwd_begin[d] = (int32_t)P.phases.size();
-        for (int32_t h = 0; h <= H; ++h) {
-            begin_phase(FWD_PULL);
-            for (int32_t t : sub_sn[d])
-                if (SN[t].height == h)
-                    for (int32_t a = 0; a < SN[t].n; ++a) {
-                        int32_t r = SN[t].col0 + a;
-                        if (!pull_int[r].empty()) add_task(r - base, pull_int[r]);
-                    }
-            end_phase();
-            begin_phase(FWD_TINV);
-            for (int32_t t : sub_sn[d])
-                if (SN[t].height == h)
-                    for (int32_t a = 0; a < SN[t].n; ++a) {
-                        one[0] = {(int32_t)(SN[t].tinv_off + (int64_t)a * (a + 1) / 2), a + 1,
-                                  SN[t].col0 - base, 1};
-                        add_task(SN[t].col0 + a - base, one);
-                    }
-            end_phase();
-        }
-        fwd_end[d] = (int32_t)P.phases.size();
-        P.max_sub_phases = std::max(P.max_sub_phases, fwd_end[d] - fwd_begin[d]);
-        P.max_sub_n = std::max(P.max_sub_n, P.sub_off[d + 1] - P.sub_off[d]);
-    }
-    for (int32_t d = 0; d < D; ++d) {
-        int32_t H = -1;
-        for (int32_t t : sub_sn[d]) H = std::max(H, SN[t].height);
-        const int32_t base = P.sub_off[d];
-        bwd_begin[d] = (int32_t)P.phases.size();
-        for (int32_t h = H; h >= 0; --h) {
-            begin_phase(BWD_PULL);
-            for (int32_t t : sub_sn[d])
-                if (SN[t].height == h) {
-                    const int32_t m = (int32_t)SN[t].rows.size();
-                    for (int32_t a = 0; a < SN[t].n; ++a) {
-                        if (m > 0) {
-                            one[0] = {(int32_t)(SN[t].bT_off + (int64_t)a * m), m,
-                                      (int32_t)SN[t].rows_off, 1};
-                            add_task(SN[t].col0 + a - base, one);
-                        } else {
-                            add_task(SN[t].col0 + a - base, std::vector<Seg>());
-                        }
-                    }
-                }
-            end_phase();
-            begin_phase(BWD_TINV);
-            for (int32_t t : sub_sn[d])
-                if (SN[t].height == h) {
-                    const int32_t n = SN[t].n;
-                    for (int32_t a = 0; a < n; ++a) {
-                        one[0] = {(int32_t)(SN[t].tinvT_off + (int64_t)a * n - (int64_t)a * (a - 1) / 2),
-                                  n - a, SN[t].col0 + a - base, 1};
-                        add_task(SN[t].col0 + a - base, one);
-                    }
-                }
-            end_phase();
-        }
-        bwd_end[d] = (int32_t)P.phases.size();
-        P.max_sub_phases = std::max(P.max_sub_phases, bwd_end[d] - bwd_begin[d]);
-    }
-    // per-subdomain phase ranges: [fwd_begin, fwd_end) and [bwd_begin, bwd_end)
-    for (int32_t d = 0; d < D; ++d) {
-        P.sub_fwd_ph[d] = fwd_begin[d];
-        P.sub_bwd_ph[d] = bwd_begin[d];
-    }
-    P.sub_fwd_ph[D] = D > 0 ? fwd_end[D - 1] : 0;
-    P.sub_bwd_ph[D] = D > 0 ? bwd_end[D - 1] : 0;
-    // (ranges are contiguous: subdomain d's forward phases end where d+1's begin)
+    P.n_cgf = ncgf;
+    P.n_cgd = ncgd;
+    P.max_cint = 0;
+    for (int32_t d = 0; d < D; ++d) P.max_cint = std::max(P.max_cint, cint_used[d]);
 
-    // interface program: one launch per phase
-    auto close_into = [&](std::vector<int32_t>& lst) {
-        P.phases.back().task1 = (int32_t)P.tasks.size();
-        if (P.phases.back().task1 == P.phases.back().task0) P.phases.pop_back();
-        else lst.push_back((int32_t)P.phases.size() - 1);
-    };
-    P.coarse_fwd_ph.clear();
-    P.coarse_bwd_ph.clear();
-    for (int32_t l = 0; l < P.n_clevels; ++l) {
-        begin_phase(FWD_PULL);
-        for (int32_t t = 0; t < nsn; ++t)
-            if (SN[t].sub < 0 && SN[t].clevel == l)
-                for (int32_t a = 0; a < SN[t].n; ++a) {
-                    int32_t r = SN[t].col0 + a;
-                    std::vector<Seg> sg = pull_int[r];
-                    sg.insert(sg.end(), pull_gam[r].begin(), pull_gam[r].end());
-                    if (!sg.empty()) add_task(r - P.n_int, sg);
-                }
-        close_into(P.coarse_fwd_ph);
-        begin_phase(FWD_TINV);
-        for (int32_t t = 0; t < nsn; ++t)
-            if (SN[t].sub < 0 && SN[t].clevel == l)
-                for (int32_t a = 0; a < SN[t].n; ++a) {
-                    one[0] = {(int32_t)(SN[t].tinv_off + (int64_t)a * (a + 1) / 2), a + 1,
-                              SN[t].col0 - P.n_int, 0};
-                    add_task(SN[t].col0 + a - P.n_int, one);
-                }
-        close_into(P.coarse_fwd_ph);
-    }
-    for (int32_t l = P.n_clevels - 1; l >= 0; --l) {
-        begin_phase(BWD_PULL);
-        for (int32_t t = 0; t < nsn; ++t)
-            if (SN[t].sub < 0 && SN[t].clevel == l) {
-                const int32_t m = (int32_t)SN[t].rows.size();
-                for (int32_t a = 0; a < SN[t].n; ++a) {
-                    if (m > 0) {
-                        one[0] = {(int32_t)(SN[t].bT_off + (int64_t)a * m), m,
-                                  (int32_t)SN[t].rows_off, 0};
-                        add_task(SN[t].col0 + a - P.n_int, one);
-                    } else {
-                        add_task(SN[t].col0 + a - P.n_int, std::vector<Seg>());
-                    }
-                }
-            }
-        close_into(P.coarse_bwd_ph);
-        begin_phase(BWD_TINV);
-        for (int32_t t = 0; t < nsn; ++t)
-            if (SN[t].sub < 0 && SN[t].clevel == l) {
-                const int32_t n = SN[t].n;
-                for (int32_t a = 0; a < n; ++a) {
-                    one[0] = {(int32_t)(SN[t].tinvT_off + (int64_t)a * n - (int64_t)a * (a - 1) / 2),
-                              n - a, SN[t].col0 + a - P.n_int, 0};
-                    add_task(SN[t].col0 + a - P.n_int, one);
-                }
-            }
-        close_into(P.coarse_bwd_ph);
-    }
-    // ---- interior programs as LDS chunks ---------------------------------------------
-    // Every subdomain's phases are cut into chunks of at most chunk_floats
-    // values; a chunk holds the values of its tasks' segments, and for
-    // backward pulls also the gather list (as int bit patterns) of each
-    // supernode, so a workgroup never reads the factor outside LDS.  Gather
-    // indices are local: [0, n_loc) interior rows, [n_loc, n_loc + nb) the
+    // ---- interior programs: LDS chunks ---------------------------------------------
+    // A chunk is [ntasks x 8 int32 task descriptors][data], all as 32-bit words
+    // (ints bit-cast into the float array); data offsets are relative to the data
+    // start.  Local vector ids: [0, n_loc) interior rows, [n_loc, n_loc + nb) the
     // subdomain's boundary rows staged from the interface solution.
     P.chunk_floats = chunk_floats;
     P.bnd_off.assign(D + 1, 0);
     P.bnd.clear();
-    std::vector<int32_t> bpos(nf, -1);
+    std::vector<std::vector<int32_t>> sub_sn(D);
+    for (int32_t t = 0; t < nsn; ++t)
+        if (SN[t].sub >= 0) sub_sn[SN[t].sub].push_back(t);
     for (int32_t d = 0; d < D; ++d) {
         P.bnd_off[d] = (int32_t)P.bnd.size();
-        std::vector<int32_t> b;
+        std::vector<int32_t> bl;
         for (int32_t t : sub_sn[d])
             for (int32_t r : SN[t].rows)
-                if (r >= P.n_int) b.push_back(r);
-        std::sort(b.begin(), b.end());
-        b.erase(std::unique(b.begin(), b.end()), b.end());
-        P.bnd.insert(P.bnd.end(), b.begin(), b.end());
-        P.max_nb = std::max(P.max_nb, (int32_t)b.size());
+                if (r >= P.n_int) bl.push_back(r);
+        std::sort(bl.begin(), bl.end());
+        bl.erase(std::unique(bl.begin(), bl.end()), bl.end());
+        P.bnd.insert(P.bnd.end(), bl.begin(), bl.end());
+        P.max_nb = std::max(P.max_nb, (int32_t)bl.size());
+        P.max_sub_n = std::max(P.max_sub_n, P.sub_off[d + 1] - P.sub_off[d]);
     }
     P.bnd_off[D] = (int32_t)P.bnd.size();
+    std::vector<int32_t> bpos(nf, -1);
+    auto as_f = [](int32_t v) {
+        float f;
+        std::memcpy(&f, &v, 4);
+        return f;
+    };
+    struct Builder {
+        int32_t kind = 0;
+        std::vector<int32_t> desc;
+        std::vector<float> data;
+        int32_t gather_sn = -1, gather_off = 0;
+    } cb;
+    bool too_big = false;
+    auto flush = [&]() {
+        const int32_t nt_ = (int32_t)cb.desc.size() / 8;
+        if (nt_ == 0) return;
+        while (P.ivals.size() % 4) P.ivals.push_back(0.0f);
+        Chunk c;
+        c.kind = cb.kind;
+        c.ntasks = nt_;
+        c.v0 = (int32_t)P.ivals.size();
+        for (int32_t v : cb.desc) P.ivals.push_back(as_f(v));
+        P.ivals.insert(P.ivals.end(), cb.data.begin(), cb.data.end());
+        c.nv = (int32_t)P.ivals.size() - c.v0;
+        c.pad[0] = c.pad[1] = c.pad[2] = c.pad[3] = 0;
+        if (c.nv > chunk_floats) too_big = true;
+        P.chunks.push_back(c);
+        cb.desc.clear();
+        cb.data.clear();
+        cb.gather_sn = -1;
+    };
+    auto room = [&](int32_t need) {
+        return (int32_t)(cb.desc.size() + cb.data.size()) + need + 8 <= chunk_floats || cb.desc.empty();
+    };
+    auto start_phase = [&](int32_t kind) {
+        flush();
+        cb.kind = kind;
+    };
     P.ivals.clear();
     P.chunks.clear();
     P.sub_fwd_ch.assign(D + 1, 0);
     P.sub_bwd_ch.assign(D + 1, 0);
-    std::vector<Seg> newsegs = P.segs;      // interior segs get chunk-relative offsets
-    auto pack_range = [&](int32_t d, int32_t ph0, int32_t ph1) {
-        const int32_t base = P.sub_off[d];
-        const int32_t nloc = P.sub_off[d + 1] - base;
-        // local ids of this subdomain's boundary rows
-        for (int32_t k = P.bnd_off[d]; k < P.bnd_off[d + 1]; ++k) bpos[P.bnd[k]] = nloc + (k - P.bnd_off[d]);
-        for (int32_t ph = ph0; ph < ph1; ++ph) {
-            const Phase& Ph = P.phases[ph];
-            int32_t t = Ph.task0;
-            while (t < Ph.task1) {
-                Chunk c;
-                c.kind = Ph.kind;
-                c.task0 = t;
-                while (P.ivals.size() % 4) P.ivals.push_back(0.0f);
-                c.v0 = (int32_t)P.ivals.size();
-                int32_t used = 0;
-                int32_t last_rows_off = -1, rows_local = 0;   // shared gather list of one supernode
-                while (t < Ph.task1) {
-                    const Task& T = P.tasks[t];
-                    int32_t need = 0;
-                    for (int32_t g = T.seg0; g < T.seg1; ++g) {
-                        need += P.segs[g].len;
-                        if (Ph.kind == BWD_PULL && P.segs[g].xoff != last_rows_off) need += P.segs[g].len;
-                    }
-                    if (used > 0 && used + need > chunk_floats) break;
-                    for (int32_t g = T.seg0; g < T.seg1; ++g) {
-                        const Seg& S = P.segs[g];
-                        Seg& NS = newsegs[g];
-                        if (Ph.kind == BWD_PULL && S.xoff != last_rows_off) {
-                            rows_local = (int32_t)P.ivals.size() - c.v0;
-                            for (int32_t k = 0; k < S.len; ++k) {
-                                int32_t gi = P.gidx[S.xoff + k];
-                                int32_t li = (gi < P.n_int) ? gi - base : bpos[gi];
-                                float f;
-                                std::memcpy(&f, &li, 4);
-                                P.ivals.push_back(f);
-                            }
-                            last_rows_off = S.xoff;
-                            used += S.len;
-                        }
-                        NS.voff = (int32_t)P.ivals.size() - c.v0;
-                        for (int32_t k = 0; k < S.len; ++k) P.ivals.push_back(P.fvals[S.voff + k]);
-                        if (Ph.kind == BWD_PULL) NS.xoff = rows_local;
-                        used += S.len;
-                    }
-                    ++t;
-                }
-                c.task1 = t;
-                c.nv = (int32_t)P.ivals.size() - c.v0;
-                c.pad[0] = c.pad[1] = c.pad[2] = 0;
-                if (c.nv > chunk_floats) {
-                    msg = "a solve task does not fit one LDS chunk";
-                    return false;
-                }
-                P.chunks.push_back(c);
-            }
-        }
-        return true;
-    };
     for (int32_t d = 0; d < D; ++d) {
         P.sub_fwd_ch[d] = (int32_t)P.chunks.size();
-        if (!pack_range(d, P.sub_fwd_ph[d], P.sub_fwd_ph[d + 1])) return EINVAL_;
+        const int32_t base = P.sub_off[d];
+        int32_t H = -1;
+        for (int32_t t : sub_sn[d]) H = std::max(H, SN[t].height);
+        for (int32_t h = 0; h <= H; ++h) {
+            start_phase(PULLSUM);
+            for (int32_t t : sub_sn[d]) {
+                if (SN[t].height != h) continue;
+                for (int32_t a = 0; a < SN[t].n; ++a) {
+                    const auto& L = pull_i[SN[t].col0 + a];
+                    if (L.empty()) continue;
+                    if (!room((int32_t)L.size())) flush();
+                    int32_t off = (int32_t)cb.data.size();
+                    for (int32_t sl : L) cb.data.push_back(as_f(sl));
+                    int32_t dsc[8] = {SN[t].col0 + a - base, off, (int32_t)L.size(), 0, 0, 0, 0, 0};
+                    cb.desc.insert(cb.desc.end(), dsc, dsc + 8);
+                }
+            }
+            start_phase(GEMV);
+            for (int32_t t : sub_sn[d]) {
+                if (SN[t].height != h) continue;
+                const Supernode& S = SN[t];
+                const int32_t n = S.n, m = (int32_t)S.rows.size();
+                const int64_t tri = (int64_t)n * (n + 1) / 2;
+                for (int32_t i = 0; i < n + m; ++i) {
+                    const int32_t len = (i < n) ? i + 1 : n;
+                    const int64_t vo = S.wf_off + ((i < n) ? (int64_t)i * (i + 1) / 2 : tri + (int64_t)(i - n) * n);
+                    if (!room(len)) flush();
+                    int32_t off = (int32_t)cb.data.size();
+                    for (int32_t k = 0; k < len; ++k) cb.data.push_back((float)ivd[vo + k]);
+                    int32_t dest, idx;
+                    if (i < n) {
+                        dest = 0;
+                        idx = S.col0 + i - base;
+                    } else if (i < n + S.m_int) {
+                        dest = 1;
+                        idx = S.cint0 + (i - n);
+                    } else {
+                        dest = 2;
+                        idx = S.cg0 + (i - n - S.m_int);
+                    }
+                    int32_t dsc[8] = {dest, idx, off, len, S.col0 - base, 0, 0, 0};
+                    cb.desc.insert(cb.desc.end(), dsc, dsc + 8);
+                }
+            }
+            flush();
+        }
+        P.max_sub_phases = std::max(P.max_sub_phases, 2 * (H + 1));
     }
     P.sub_fwd_ch[D] = (int32_t)P.chunks.size();
     for (int32_t d = 0; d < D; ++d) {
         P.sub_bwd_ch[d] = (int32_t)P.chunks.size();
-        if (!pack_range(d, P.sub_bwd_ph[d], P.sub_bwd_ph[d + 1])) return EINVAL_;
+        const int32_t base = P.sub_off[d];
+        const int32_t nloc = P.sub_off[d + 1] - base;
+        for (int32_t k = P.bnd_off[d]; k < P.bnd_off[d + 1]; ++k) bpos[P.bnd[k]] = nloc + (k - P.bnd_off[d]);
+        int32_t H = -1;
+        for (int32_t t : sub_sn[d]) H = std::max(H, SN[t].height);
+        for (int32_t h = H; h >= 0; --h) {
+            start_phase(BGEMV);
+            for (int32_t t : sub_sn[d]) {
+                if (SN[t].height != h) continue;
+                const Supernode& S = SN[t];
+                const int32_t n = S.n, m = (int32_t)S.rows.size();
+                for (int32_t k = 0; k < n; ++k) {
+                    const int32_t len1 = n - k;
+                    const bool need_g = (m > 0 && cb.gather_sn != t);
+                    if (!room(len1 + m + (need_g ? m : 0))) flush();
+                    if (m > 0 && cb.gather_sn != t) {
+                        cb.gather_off = (int32_t)cb.data.size();
+                        for (int32_t r : S.rows) cb.data.push_back(as_f(r < P.n_int ? r - base : bpos[r]));
+                        cb.gather_sn = t;
+                    }
+                    const int64_t vo = S.wb_off + (int64_t)k * (n + m) - (int64_t)k * (k - 1) / 2;
+                    int32_t off = (int32_t)cb.data.size();
+                    for (int32_t q = 0; q < len1 + m; ++q) cb.data.push_back((float)ivd[vo + q]);
+                    int32_t dsc[8] = {S.col0 + k - base, off, len1, S.col0 + k - base, m, cb.gather_off, 0, 0};
+                    cb.desc.insert(cb.desc.end(), dsc, dsc + 8);
+                }
+            }
+            flush();
+        }
     }
     P.sub_bwd_ch[D] = (int32_t)P.chunks.size();
     while (P.ivals.size() % 4) P.ivals.push_back(0.0f);
-    P.segs.swap(newsegs);   // interface phases keep their fvals/dvals offsets
+    if (too_big) {
+        msg = "a solve task does not fit one LDS chunk";
+        return EINVAL_;
+    }
 
+    // ---- interface programs: one launch per phase ------------------------------------
+    P.ctasks.clear();
+    P.cslots.clear();
+    P.cgidx.clear();
+    P.cfwd.clear();
+    P.cbwd.clear();
+    auto open_cphase = [&](int32_t kind) {
+        CPhase ph;
+        ph.kind = kind;
+        ph.task0 = (int32_t)P.ctasks.size();
+        ph.ntasks = 0;
+        ph.group = 16;
+        return ph;
+    };
+    auto close_cphase = [&](CPhase ph, int64_t total_len, std::vector<CPhase>& lst) {
+        ph.ntasks = (int32_t)P.ctasks.size() - ph.task0;
+        if (ph.ntasks == 0) return;
+        ph.group = (total_len / ph.ntasks >= 96) ? 64 : 16;
+        lst.push_back(ph);
+    };
+    std::vector<int32_t> cg_goff(nsn, -1);
+    for (int32_t t = 0; t < nsn; ++t)
+        if (SN[t].sub < 0) {
+            cg_goff[t] = (int32_t)P.cgidx.size();
+            for (int32_t r : SN[t].rows) P.cgidx.push_back(r - P.n_int);
+        }
+    for (int32_t l = 0; l < P.n_clevels; ++l) {
+        CPhase ph = open_cphase(PULLSUM);
+        int64_t tl = 0;
+        for (int32_t t = 0; t < nsn; ++t) {
+            if (SN[t].sub >= 0 || SN[t].clevel != l) continue;
+            for (int32_t a = 0; a < SN[t].n; ++a) {
+                const int32_t r = SN[t].col0 + a;
+                CTask c{};
+                c.a[0] = r - P.n_int;
+                c.a[1] = (int32_t)P.cslots.size();
+                c.a[2] = (int32_t)pull_f[r].size();
+                P.cslots.insert(P.cslots.end(), pull_f[r].begin(), pull_f[r].end());
+                c.a[3] = (int32_t)P.cslots.size();
+                c.a[4] = (int32_t)pull_d[r].size();
+                P.cslots.insert(P.cslots.end(), pull_d[r].begin(), pull_d[r].end());
+                tl += c.a[2] + c.a[4];
+                P.ctasks.push_back(c);
+            }
+        }
+        close_cphase(ph, tl, P.cfwd);
+        ph = open_cphase(GEMV);
+        tl = 0;
+        for (int32_t t = 0; t < nsn; ++t) {
+            if (SN[t].sub >= 0 || SN[t].clevel != l) continue;
+            const Supernode& S = SN[t];
+            const int32_t n = S.n, m = (int32_t)S.rows.size();
+            const int64_t tri = (int64_t)n * (n + 1) / 2;
+            for (int32_t i = 0; i < n + m; ++i) {
+                CTask c{};
+                c.a[0] = (i < n) ? 0 : 1;
+                c.a[1] = (i < n) ? S.col0 - P.n_int + i : S.cg0 + (i - n);
+                c.a[2] = (int32_t)(S.wf_off + ((i < n) ? (int64_t)i * (i + 1) / 2 : tri + (int64_t)(i - n) * n));
+                c.a[3] = (i < n) ? i + 1 : n;
+                c.a[4] = S.col0 - P.n_int;
+                tl += c.a[3];
+                P.ctasks.push_back(c);
+            }
+        }
+        close_cphase(ph, tl, P.cfwd);
+    }
+    for (int32_t l = P.n_clevels - 1; l >= 0; --l) {
+        CPhase ph = open_cphase(BGEMV);
+        int64_t tl = 0;
+        for (int32_t t = 0; t < nsn; ++t) {
+            if (SN[t].sub >= 0 || SN[t].clevel != l) continue;
+            const Supernode& S = SN[t];
+            const int32_t n = S.n, m = (int32_t)S.rows.size();
+            for (int32_t k = 0; k < n; ++k) {
+                CTask c{};
+                c.a[0] = S.col0 - P.n_int + k;
+                c.a[1] = (int32_t)(S.wb_off + (int64_t)k * (n + m) - (int64_t)k * (k - 1) / 2);
+                c.a[2] = n - k;
+                c.a[3] = S.col0 - P.n_int + k;
+                c.a[4] = m;
+                c.a[5] = cg_goff[t];
+                tl += n - k + m;
+                P.ctasks.push_back(c);
+            }
+        }
+        close_cphase(ph, tl, P.cbwd);
+    }
     P.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return OK;
 }

@@ -31,18 +31,17 @@ struct DevMesh {
     float* zf = nullptr;            // [n_int][3] interior forward result
     double *rg = nullptr, *zg = nullptr, *dg = nullptr;   // [n_gamma][3] interface work
     double* delta = nullptr;        // [n_free][3] last correction
-    float* fvals = nullptr;
-    double* dvals = nullptr;
-    int32_t* gidx = nullptr;
-    Seg* segs = nullptr;
-    Task* tasks = nullptr;
-    Phase* phases = nullptr;
-    int32_t *sub_off = nullptr, *sub_fwd_ph = nullptr, *sub_bwd_ph = nullptr;
+    int32_t* sub_off = nullptr;
     Chunk* chunks = nullptr;
     int32_t *sub_fwd_ch = nullptr, *sub_bwd_ch = nullptr;
     float* ivals = nullptr;
     int32_t *bnd = nullptr, *bnd_off = nullptr;
-    int32_t max_nb = 0, chunk_nv4 = 4;     // chunk capacity = chunk_nv4 * 4 * 256 floats
+    int32_t max_nb = 0, max_cint = 0, chunk_nv4 = 4;   // chunk capacity = chunk_nv4 * 4 * 256 floats
+    double* dvals = nullptr;
+    CTask* ctasks = nullptr;
+    int32_t *cslots = nullptr, *cgidx = nullptr;
+    float* cgf = nullptr;           // [n_cgf][3]
+    double* cgd = nullptr;          // [n_cgd][3]
     int32_t *K_ptr = nullptr, *K_col = nullptr;
     double* K_val = nullptr;
     uint32_t* flags = nullptr;      // [0] non-finite seen, [1] out-of-regime projections, [2] inverted
@@ -50,10 +49,8 @@ struct DevMesh {
     float *dbg_T = nullptr, *dbg_sig = nullptr, *dbg_s = nullptr;
 };
 
-// Host copies of the interface phase launch shapes.
-struct PhaseLaunch {
-    int32_t kind, task0, ntasks, group;   // group: lanes per task (16 or 64)
-};
+// Host copy of an interface phase launch shape.
+using PhaseLaunch = CPhase;
 
 // LDS bytes of the interior kernels for a mesh (two chunk buffers + vectors)
 size_t interior_fwd_lds(const DevMesh& m);

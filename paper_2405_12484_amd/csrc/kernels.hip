@@ -5,11 +5,12 @@
 //               volume projection (Eq. vol_pre), residual stress and forces
 //   k_residual  Sec. 7.1 global step right-hand side, as the residual
 //               r = b - K x^(k), gathered per vertex without atomics
-//   k_interior_fwd / k_iface / k_interior_bwd
+//   k_interior_fwd / k_coarse / k_interior_bwd
 //               Sec. 7.2 decomposed solve K d = r: interior triangular
-//               solves (one workgroup per subdomain, vectors in LDS, FP32),
-//               interface solve (FP64, one launch per tree level), interior
-//               back-substitution with the interface values, x += d
+//               solves (one workgroup per subdomain, factor chunks and vectors
+//               in LDS, FP32), interface solve (FP64, one launch per tree level
+//               and task kind), interior back-substitution with the interface
+//               values, x += d
 //   k_refine    r -= K d in FP64 (optional refinement passes)
 //   k_velocity  BDF1 velocity, non-finite check
 #include "kernels.h"
@@ -339,17 +340,17 @@ __device__ __forceinline__ T group_sum(T v) {
 }
 
 struct SolveArgs {
-    int32_t n_int, n_gamma, D, max_n, max_nb;
+    int32_t n_int, n_gamma, D, max_n, max_nb, max_cint;
     const int32_t *sub_off, *sub_fwd_ch, *sub_bwd_ch, *bnd, *bnd_off;
     const Chunk* chunks;
-    const Task* tasks;
-    const Seg* segs;
-    const float* ivals;      // packed interior chunks
-    const float* fvals;      // interior factor blocks (interface condensation rows)
+    const float* ivals;          // packed interior chunks
+    const CTask* ctasks;
+    const int32_t *cslots, *cgidx;
     const double* dvals;
-    const int32_t* gidx;
     const double* r;
-    float* zf;
+    float* zf;                   // [n_int][3] interior z
+    float* cgf;                  // [n_cgf][3] contributions of interior supernodes to interface rows
+    double* cgd;                 // [n_cgd][3] contributions of interface supernodes
     double *rg, *zg, *dg, *delta, *x;
     const double* X;
     float4* u;
@@ -373,10 +374,12 @@ __device__ __forceinline__ void chunk_store(float4* dst, int32_t nv4, const floa
     }
 }
 
-// Interior forward solve, one workgroup per subdomain.  The subdomain's
-// chunk program runs phase by phase; each chunk's values are staged in LDS
-// (double-buffered: the next chunk is read into registers while the current
-// one is computed).  FWD_PULL: R[o] -= sum vals * Z; FWD_TINV: Z[o] = sum vals * R.
+// Interior forward solve, one workgroup per subdomain.  Per supernode level:
+// PULLSUM r'_row = r_row - sum of its LDS contribution slots, then GEMV
+// [z; c] = [Ti; B Ti] r' (z and interior contributions to LDS, interface
+// contributions to the global FP32 slots).  Each chunk (task descriptors,
+// values, slot lists) is staged in LDS; the next chunk is read into registers
+// while the current one is computed.
 template <int NV4>
 __global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a) {
     constexpr int32_t CH = NV4 * 4 * BLK;
@@ -385,48 +388,52 @@ __global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a) {
     float* bufs[2] = {sm, sm + CH};
     float* R = sm + 2 * CH;
     float* Z = R + 3 * a.max_n;
+    float* C = Z + 3 * a.max_n;
     const int32_t d = blockIdx.x;
     const int32_t base = a.sub_off[d];
     const int32_t n = a.sub_off[d + 1] - base;
     const int tid = threadIdx.x;
-    for (int32_t i = tid; i < 3 * n; i += BLK) {
-        R[i] = (float)a.r[3 * base + i];
-        Z[i] = 0.0f;
-    }
-    // this block also copies a slice of the interface residual into the work vector
-    const int32_t chunk = (a.n_gamma + a.D - 1) / a.D;
-    const int32_t g0 = d * chunk, g1 = min(a.n_gamma, g0 + chunk);
-    for (int32_t i = 3 * g0 + tid; i < 3 * g1; i += BLK) a.rg[i] = a.r[3 * a.n_int + i];
+    for (int32_t i = tid; i < 3 * n; i += BLK) R[i] = (float)a.r[3 * base + i];
     const int32_t c0 = a.sub_fwd_ch[d], c1 = a.sub_fwd_ch[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
     float4 reg[NV4];
     if (c0 < c1) {
-        const Chunk C = a.chunks[c0];
-        chunk_load<NV4>(iv4 + C.v0 / 4, (C.nv + 3) / 4, reg);
-        chunk_store<NV4>(reinterpret_cast<float4*>(bufs[0]), (C.nv + 3) / 4, reg);
+        const Chunk K = a.chunks[c0];
+        chunk_load<NV4>(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
+        chunk_store<NV4>(reinterpret_cast<float4*>(bufs[0]), (K.nv + 3) / 4, reg);
     }
     __syncthreads();
     const int grp = tid / IG, lane = tid % IG;
     constexpr int NGRP = BLK / IG;
     for (int32_t c = c0; c < c1; ++c) {
-        const Chunk C = a.chunks[c];
+        const Chunk K = a.chunks[c];
         const float* cur = bufs[(c - c0) & 1];
         const bool more = c + 1 < c1;
         int32_t nxt4 = 0;
         if (more) {
-            const Chunk Cn = a.chunks[c + 1];
-            nxt4 = (Cn.nv + 3) / 4;
-            chunk_load<NV4>(iv4 + Cn.v0 / 4, nxt4, reg);
+            const Chunk Kn = a.chunks[c + 1];
+            nxt4 = (Kn.nv + 3) / 4;
+            chunk_load<NV4>(iv4 + Kn.v0 / 4, nxt4, reg);
         }
-        const float* Xv = (C.kind == FWD_PULL) ? Z : R;
-        for (int32_t t = C.task0 + grp; t < C.task1; t += NGRP) {
-            const Task T = a.tasks[t];
+        const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
+        const float* dat = cur + 8 * K.ntasks;
+        const int32_t* idat = reinterpret_cast<const int32_t*>(dat);
+        for (int32_t t = grp; t < K.ntasks; t += NGRP) {
+            const int32_t* q = desc + 8 * t;
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-            for (int32_t g = T.seg0; g < T.seg1; ++g) {
-                const Seg S = a.segs[g];
-                for (int32_t k = lane; k < S.len; k += IG) {
-                    const float v = cur[S.voff + k];
-                    const float* xp = Xv + 3 * (S.xoff + k);
+            if (K.kind == PULLSUM) {
+                const int32_t off = q[1], cnt = q[2];
+                for (int32_t k = lane; k < cnt; k += IG) {
+                    const float* cp = C + 3 * idat[off + k];
+                    s0 += cp[0];
+                    s1 += cp[1];
+                    s2 += cp[2];
+                }
+            } else {
+                const int32_t off = q[2], len = q[3], xo = q[4];
+                for (int32_t k = lane; k < len; k += IG) {
+                    const float v = dat[off + k];
+                    const float* xp = R + 3 * (xo + k);
                     s0 += v * xp[0];
                     s1 += v * xp[1];
                     s2 += v * xp[2];
@@ -436,14 +443,17 @@ __global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a) {
             s1 = group_sum<IG>(s1);
             s2 = group_sum<IG>(s2);
             if (lane == 0) {
-                if (C.kind == FWD_PULL) {
-                    R[3 * T.out + 0] -= s0;
-                    R[3 * T.out + 1] -= s1;
-                    R[3 * T.out + 2] -= s2;
+                if (K.kind == PULLSUM) {
+                    float* rp = R + 3 * q[0];
+                    rp[0] -= s0;
+                    rp[1] -= s1;
+                    rp[2] -= s2;
                 } else {
-                    Z[3 * T.out + 0] = s0;
-                    Z[3 * T.out + 1] = s1;
-                    Z[3 * T.out + 2] = s2;
+                    const int32_t dest = q[0], idx = q[1];
+                    float* op = (dest == 0) ? Z + 3 * idx : (dest == 1) ? C + 3 * idx : a.cgf + 3 * (size_t)idx;
+                    op[0] = s0;
+                    op[1] = s1;
+                    op[2] = s2;
                 }
             }
         }
@@ -453,126 +463,123 @@ __global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a) {
     for (int32_t i = tid; i < 3 * n; i += BLK) a.zf[3 * base + i] = Z[i];
 }
 
-// One group of G lanes per task.  FWD_PULL: rg[o] -= sum; FWD_TINV: zg[o] = sum;
-// BWD_PULL: rg[o] = zg[o] - sum (gathered dg); BWD_TINV: dg[o] = sum.
+// Interface phases, one group of G lanes per task (FP64).
+//   PULLSUM: rg[row] = r[row] - sum FP32 slots - sum FP64 slots
+//   GEMV:    zg[idx] or cgd[idx] = row of W . rg
+//   BGEMV:   dg[out] = Ti column . zg + (-W_B) column . dg[gather]
 template <int G>
-__global__ __launch_bounds__(BLK) void k_iface(SolveArgs a, int32_t kind, int32_t task0,
-                                               int32_t ntasks) {
+__global__ __launch_bounds__(BLK) void k_coarse(SolveArgs a, int32_t kind, int32_t task0, int32_t ntasks) {
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int32_t t = blockIdx.x * (BLK / G) + grp;
     if (t >= ntasks) return;
-    const Task T = a.tasks[task0 + t];
+    const CTask T = a.ctasks[task0 + t];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int32_t g = T.seg0; g < T.seg1; ++g) {
-        const Seg S = a.segs[g];
-        if (kind == FWD_PULL && S.kind == 1) {
-            const float* vp = a.fvals + S.voff;
-            const float* xb = a.zf + 3 * S.xoff;
-            int32_t k = lane;
-            for (; k + G < S.len; k += 2 * G) {
-                const double v0 = (double)vp[k], v1 = (double)vp[k + G];
-                const float* x0 = xb + 3 * k;
-                const float* x1 = xb + 3 * (k + G);
-                s0 += v0 * (double)x0[0] + v1 * (double)x1[0];
-                s1 += v0 * (double)x0[1] + v1 * (double)x1[1];
-                s2 += v0 * (double)x0[2] + v1 * (double)x1[2];
-            }
-            if (k < S.len) {
-                const double v = (double)vp[k];
-                const float* xp = xb + 3 * k;
-                s0 += v * (double)xp[0];
-                s1 += v * (double)xp[1];
-                s2 += v * (double)xp[2];
-            }
-        } else if (kind == BWD_PULL) {
-            const double* vp = a.dvals + S.voff;
-            const int32_t* ip = a.gidx + S.xoff;
-            int32_t k = lane;
-            for (; k + G < S.len; k += 2 * G) {
-                const double v0 = vp[k], v1 = vp[k + G];
-                const double* x0 = a.dg + 3 * (ip[k] - a.n_int);
-                const double* x1 = a.dg + 3 * (ip[k + G] - a.n_int);
-                s0 += v0 * x0[0] + v1 * x1[0];
-                s1 += v0 * x0[1] + v1 * x1[1];
-                s2 += v0 * x0[2] + v1 * x1[2];
-            }
-            if (k < S.len) {
-                const double v = vp[k];
-                const double* xp = a.dg + 3 * (ip[k] - a.n_int);
-                s0 += v * xp[0];
-                s1 += v * xp[1];
-                s2 += v * xp[2];
-            }
-        } else {
-            const double* vp = a.dvals + S.voff;
-            const double* xb = ((kind == FWD_PULL) ? a.zg : a.rg) + 3 * S.xoff;
-            int32_t k = lane;
-            for (; k + 3 * G < S.len; k += 4 * G) {
-                const double v0 = vp[k], v1 = vp[k + G], v2 = vp[k + 2 * G], v3 = vp[k + 3 * G];
-                const double* x0 = xb + 3 * k;
-                const double* x1 = xb + 3 * (k + G);
-                const double* x2 = xb + 3 * (k + 2 * G);
-                const double* x3 = xb + 3 * (k + 3 * G);
-                s0 += v0 * x0[0] + v1 * x1[0] + v2 * x2[0] + v3 * x3[0];
-                s1 += v0 * x0[1] + v1 * x1[1] + v2 * x2[1] + v3 * x3[1];
-                s2 += v0 * x0[2] + v1 * x1[2] + v2 * x2[2] + v3 * x3[2];
-            }
-            for (; k < S.len; k += G) {
-                const double v = vp[k];
-                const double* xp = xb + 3 * k;
-                s0 += v * xp[0];
-                s1 += v * xp[1];
-                s2 += v * xp[2];
-            }
+    if (kind == PULLSUM) {
+        const int32_t* lf = a.cslots + T.a[1];
+        for (int32_t k = lane; k < T.a[2]; k += G) {
+            const float* cp = a.cgf + 3 * (size_t)lf[k];
+            s0 += (double)cp[0];
+            s1 += (double)cp[1];
+            s2 += (double)cp[2];
+        }
+        const int32_t* ld = a.cslots + T.a[3];
+        for (int32_t k = lane; k < T.a[4]; k += G) {
+            const double* cp = a.cgd + 3 * (size_t)ld[k];
+            s0 += cp[0];
+            s1 += cp[1];
+            s2 += cp[2];
+        }
+    } else if (kind == GEMV) {
+        const double* vp = a.dvals + T.a[2];
+        const double* xb = a.rg + 3 * T.a[4];
+        const int32_t len = T.a[3];
+        int32_t k = lane;
+        for (; k + 3 * G < len; k += 4 * G) {
+            const double v0 = vp[k], v1 = vp[k + G], v2 = vp[k + 2 * G], v3 = vp[k + 3 * G];
+            const double* x0 = xb + 3 * k;
+            const double* x1 = x0 + 3 * G;
+            const double* x2 = x1 + 3 * G;
+            const double* x3 = x2 + 3 * G;
+            s0 += v0 * x0[0] + v1 * x1[0] + v2 * x2[0] + v3 * x3[0];
+            s1 += v0 * x0[1] + v1 * x1[1] + v2 * x2[1] + v3 * x3[1];
+            s2 += v0 * x0[2] + v1 * x1[2] + v2 * x2[2] + v3 * x3[2];
+        }
+        for (; k < len; k += G) {
+            const double v = vp[k];
+            const double* xp = xb + 3 * k;
+            s0 += v * xp[0];
+            s1 += v * xp[1];
+            s2 += v * xp[2];
+        }
+    } else {
+        const double* vp = a.dvals + T.a[1];
+        const int32_t len1 = T.a[2], len2 = T.a[4];
+        const double* zb = a.zg + 3 * T.a[3];
+        for (int32_t k = lane; k < len1; k += G) {
+            const double v = vp[k];
+            const double* xp = zb + 3 * k;
+            s0 += v * xp[0];
+            s1 += v * xp[1];
+            s2 += v * xp[2];
+        }
+        const double* v2p = vp + len1;
+        const int32_t* gi = a.cgidx + T.a[5];
+        int32_t k = lane;
+        for (; k + G < len2; k += 2 * G) {
+            const double va = v2p[k], vb = v2p[k + G];
+            const double* xa = a.dg + 3 * gi[k];
+            const double* xb2 = a.dg + 3 * gi[k + G];
+            s0 += va * xa[0] + vb * xb2[0];
+            s1 += va * xa[1] + vb * xb2[1];
+            s2 += va * xa[2] + vb * xb2[2];
+        }
+        if (k < len2) {
+            const double v = v2p[k];
+            const double* xp = a.dg + 3 * gi[k];
+            s0 += v * xp[0];
+            s1 += v * xp[1];
+            s2 += v * xp[2];
         }
     }
     s0 = group_sum<G>(s0);
     s1 = group_sum<G>(s1);
     s2 = group_sum<G>(s2);
     if (lane == 0) {
-        const int32_t o = 3 * T.out;
-        if (kind == FWD_PULL) {
-            a.rg[o] -= s0;
-            a.rg[o + 1] -= s1;
-            a.rg[o + 2] -= s2;
-        } else if (kind == FWD_TINV) {
-            a.zg[o] = s0;
-            a.zg[o + 1] = s1;
-            a.zg[o + 2] = s2;
-        } else if (kind == BWD_PULL) {
-            a.rg[o] = a.zg[o] - s0;
-            a.rg[o + 1] = a.zg[o + 1] - s1;
-            a.rg[o + 2] = a.zg[o + 2] - s2;
-        } else {
-            a.dg[o] = s0;
-            a.dg[o + 1] = s1;
-            a.dg[o + 2] = s2;
+        double* op;
+        if (kind == PULLSUM) {
+            const double* rp = a.r + 3 * ((size_t)a.n_int + T.a[0]);
+            op = a.rg + 3 * T.a[0];
+            op[0] = rp[0] - s0;
+            op[1] = rp[1] - s1;
+            op[2] = rp[2] - s2;
+            return;
         }
+        if (kind == GEMV) op = (T.a[0] == 0) ? a.zg + 3 * T.a[1] : a.cgd + 3 * (size_t)T.a[1];
+        else op = a.dg + 3 * T.a[0];
+        op[0] = s0;
+        op[1] = s1;
+        op[2] = s2;
     }
 }
 
-// Interior backward solve and update, one workgroup per subdomain.  The
-// subdomain's boundary values of the interface solution are staged in LDS
-// after its interior rows, so every gather of a backward pull hits LDS.
-// BWD_PULL: ZQ[o] = ZQ[o] - sum vals * DL[gather] (in place, z -> q);
-// BWD_TINV: DL[o] = sum vals * ZQ.
+// Interior backward solve and update, one workgroup per subdomain.  Per
+// supernode level, top down: BGEMV d_t[k] = Ti column k . z_t + (-W_B) column k
+// . d[rows], with the subdomain's boundary values of the interface solution
+// staged in LDS after its interior rows, so every gather hits LDS.
 template <int NV4>
 __global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t apply, int32_t keep_delta) {
     constexpr int32_t CH = NV4 * 4 * BLK;
     extern __shared__ float4 sm4[];
     float* sm = reinterpret_cast<float*>(sm4);
     float* bufs[2] = {sm, sm + CH};
-    float* ZQ = sm + 2 * CH;
-    float* DL = ZQ + 3 * a.max_n;
+    float* Z = sm + 2 * CH;
+    float* DL = Z + 3 * a.max_n;
     const int32_t d = blockIdx.x;
     const int32_t base = a.sub_off[d];
     const int32_t n = a.sub_off[d + 1] - base;
     const int32_t b0 = a.bnd_off[d], nb = a.bnd_off[d + 1] - b0;
     const int tid = threadIdx.x;
-    for (int32_t i = tid; i < 3 * n; i += BLK) {
-        ZQ[i] = a.zf[3 * base + i];
-        DL[i] = 0.0f;
-    }
+    for (int32_t i = tid; i < 3 * n; i += BLK) Z[i] = a.zf[3 * base + i];
     for (int32_t i = tid; i < 3 * nb; i += BLK) {
         const int32_t k = i / 3, c = i - 3 * k;
         DL[3 * n + i] = (float)a.dg[3 * (a.bnd[b0 + k] - a.n_int) + c];
@@ -581,61 +588,52 @@ __global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t apply
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
     float4 reg[NV4];
     if (c0 < c1) {
-        const Chunk C = a.chunks[c0];
-        chunk_load<NV4>(iv4 + C.v0 / 4, (C.nv + 3) / 4, reg);
-        chunk_store<NV4>(reinterpret_cast<float4*>(bufs[0]), (C.nv + 3) / 4, reg);
+        const Chunk K = a.chunks[c0];
+        chunk_load<NV4>(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
+        chunk_store<NV4>(reinterpret_cast<float4*>(bufs[0]), (K.nv + 3) / 4, reg);
     }
     __syncthreads();
     const int grp = tid / IG, lane = tid % IG;
     constexpr int NGRP = BLK / IG;
     for (int32_t c = c0; c < c1; ++c) {
-        const Chunk C = a.chunks[c];
+        const Chunk K = a.chunks[c];
         const float* cur = bufs[(c - c0) & 1];
         const bool more = c + 1 < c1;
         int32_t nxt4 = 0;
         if (more) {
-            const Chunk Cn = a.chunks[c + 1];
-            nxt4 = (Cn.nv + 3) / 4;
-            chunk_load<NV4>(iv4 + Cn.v0 / 4, nxt4, reg);
+            const Chunk Kn = a.chunks[c + 1];
+            nxt4 = (Kn.nv + 3) / 4;
+            chunk_load<NV4>(iv4 + Kn.v0 / 4, nxt4, reg);
         }
-        for (int32_t t = C.task0 + grp; t < C.task1; t += NGRP) {
-            const Task T = a.tasks[t];
+        const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
+        const float* dat = cur + 8 * K.ntasks;
+        const int32_t* idat = reinterpret_cast<const int32_t*>(dat);
+        for (int32_t t = grp; t < K.ntasks; t += NGRP) {
+            const int32_t* q = desc + 8 * t;
+            const int32_t off = q[1], len1 = q[2], xo = q[3], len2 = q[4], go = q[5];
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-            for (int32_t g = T.seg0; g < T.seg1; ++g) {
-                const Seg S = a.segs[g];
-                if (C.kind == BWD_PULL) {
-                    for (int32_t k = lane; k < S.len; k += IG) {
-                        const float v = cur[S.voff + k];
-                        const int32_t li = __float_as_int(cur[S.xoff + k]);
-                        const float* xp = DL + 3 * li;
-                        s0 += v * xp[0];
-                        s1 += v * xp[1];
-                        s2 += v * xp[2];
-                    }
-                } else {
-                    for (int32_t k = lane; k < S.len; k += IG) {
-                        const float v = cur[S.voff + k];
-                        const float* xp = ZQ + 3 * (S.xoff + k);
-                        s0 += v * xp[0];
-                        s1 += v * xp[1];
-                        s2 += v * xp[2];
-                    }
-                }
+            for (int32_t k = lane; k < len1; k += IG) {
+                const float v = dat[off + k];
+                const float* xp = Z + 3 * (xo + k);
+                s0 += v * xp[0];
+                s1 += v * xp[1];
+                s2 += v * xp[2];
+            }
+            for (int32_t k = lane; k < len2; k += IG) {
+                const float v = dat[off + len1 + k];
+                const float* xp = DL + 3 * idat[go + k];
+                s0 += v * xp[0];
+                s1 += v * xp[1];
+                s2 += v * xp[2];
             }
             s0 = group_sum<IG>(s0);
             s1 = group_sum<IG>(s1);
             s2 = group_sum<IG>(s2);
             if (lane == 0) {
-                const int32_t o = 3 * T.out;
-                if (C.kind == BWD_PULL) {
-                    ZQ[o] -= s0;
-                    ZQ[o + 1] -= s1;
-                    ZQ[o + 2] -= s2;
-                } else {
-                    DL[o] = s0;
-                    DL[o + 1] = s1;
-                    DL[o + 2] = s2;
-                }
+                float* op = DL + 3 * q[0];
+                op[0] = s0;
+                op[1] = s1;
+                op[2] = s2;
             }
         }
         if (more) chunk_store<NV4>(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
@@ -720,20 +718,22 @@ SolveArgs solve_args(const DevMesh& m) {
     a.D = m.D;
     a.max_n = m.max_sub_n;
     a.max_nb = m.max_nb;
+    a.max_cint = m.max_cint;
     a.sub_off = m.sub_off;
     a.sub_fwd_ch = m.sub_fwd_ch;
     a.sub_bwd_ch = m.sub_bwd_ch;
     a.bnd = m.bnd;
     a.bnd_off = m.bnd_off;
     a.chunks = m.chunks;
-    a.tasks = m.tasks;
-    a.segs = m.segs;
     a.ivals = m.ivals;
-    a.fvals = m.fvals;
+    a.ctasks = m.ctasks;
+    a.cslots = m.cslots;
+    a.cgidx = m.cgidx;
     a.dvals = m.dvals;
-    a.gidx = m.gidx;
     a.r = m.r;
     a.zf = m.zf;
+    a.cgf = m.cgf;
+    a.cgd = m.cgd;
     a.rg = m.rg;
     a.zg = m.zg;
     a.dg = m.dg;
@@ -771,7 +771,8 @@ hipError_t launch_residual(const DevMesh& m, hipStream_t s) {
 }
 
 size_t interior_fwd_lds(const DevMesh& m) {
-    return sizeof(float) * (2 * (size_t)m.chunk_nv4 * 4 * BLK + 6 * (size_t)m.max_sub_n);
+    return sizeof(float) *
+           (2 * (size_t)m.chunk_nv4 * 4 * BLK + 6 * (size_t)m.max_sub_n + 3 * (size_t)m.max_cint);
 }
 
 size_t interior_bwd_lds(const DevMesh& m) {
@@ -809,10 +810,10 @@ hipError_t launch_interior_fwd(const DevMesh& m, hipStream_t s) {
 hipError_t launch_interface_phase(const DevMesh& m, const PhaseLaunch& ph, hipStream_t s) {
     if (ph.ntasks <= 0) return hipSuccess;
     if (ph.group == 64)
-        hipLaunchKernelGGL(k_iface<64>, dim3((ph.ntasks + 3) / 4), dim3(BLK), 0, s, solve_args(m),
+        hipLaunchKernelGGL(k_coarse<64>, dim3((ph.ntasks + 3) / 4), dim3(BLK), 0, s, solve_args(m),
                            ph.kind, ph.task0, ph.ntasks);
     else
-        hipLaunchKernelGGL(k_iface<16>, dim3((ph.ntasks + 15) / 16), dim3(BLK), 0, s, solve_args(m),
+        hipLaunchKernelGGL(k_coarse<16>, dim3((ph.ntasks + 15) / 16), dim3(BLK), 0, s, solve_args(m),
                            ph.kind, ph.task0, ph.ntasks);
     return hipGetLastError();
 }

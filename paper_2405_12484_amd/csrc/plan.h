@@ -20,39 +20,40 @@ struct Supernode {
     int32_t clevel = -1;     // interface supernodes: level in the interface tree
     std::vector<int32_t> children;
     std::vector<int32_t> rows;
-    // offsets into the value arrays (float for interior, double for interface)
-    int64_t tinv_off = 0, tinvT_off = 0, b_off = 0, bT_off = 0, rows_off = 0;
+    int32_t m_int = 0;       // rows below that are interior rows (they come first)
+    int32_t cint0 = 0;       // first LDS contribution slot (interior supernodes)
+    int32_t cg0 = 0;         // first global contribution slot
+    // offsets of the forward / backward value blocks (float staging for interior,
+    // Plan::dvals for interface supernodes)
+    int64_t wf_off = 0, wb_off = 0;
 };
 
-// One dot-product term of a solve task: sum_k vals[voff + k] * x[xoff + k]
-// (contiguous) or x[gidx[xoff + k]] (gathered), k < len.
-struct Seg {
-    int32_t voff;   // offset in the value array (elements); values may exceed 2^31 -> split
-    int32_t len;
-    int32_t xoff;
-    int32_t kind;   // 0: double values / double x (interface), 1: float / float (interior)
-};
-struct Task {
-    int32_t out;      // output slot
-    int32_t seg0, seg1;
-    int32_t pad;
-};
-struct Phase {
-    int32_t kind;     // 0 fwd pull, 1 fwd tinv, 2 bwd pull, 3 bwd tinv
-    int32_t task0, task1;
-    int32_t pad;
-};
+// Solve task kinds.  PULLSUM: r'_row = r_row - sum of contribution slots;
+// GEMV: one row of [z; c] = [Ti; B Ti] r'; BGEMV: one column of
+// d = Ti^T z - (B Ti)^T d_rows.
+enum TaskKind { PULLSUM = 0, GEMV = 1, BGEMV = 2 };
 
-enum PhaseKind { FWD_PULL = 0, FWD_TINV = 1, BWD_PULL = 2, BWD_TINV = 3 };
-
-// A piece of an interior phase whose values (and gather indices) are
-// contiguous in Plan::ivals, so one workgroup can stage it in LDS with one
-// coalesced copy.  Segment voff/xoff of its tasks are relative to v0.
+// A piece of an interior phase stored contiguously in Plan::ivals:
+// [ntasks x 8 int32 descriptors][data], one coalesced copy into LDS.
+//   PULLSUM: {row, data offset of the slot list, count}
+//   GEMV:    {dest (0 z, 1 LDS slot, 2 global FP32 slot), index, data offset, len, x offset}
+//   BGEMV:   {out, data offset, len1, z offset, len2, data offset of the gather list}
 struct Chunk {
     int32_t kind;
-    int32_t task0, task1;
+    int32_t ntasks;
     int32_t v0, nv;       // [v0, v0 + nv) in ivals, v0 % 4 == 0
-    int32_t pad[3];
+    int32_t pad[4];
+};
+
+// Interface task (global memory, FP64 values):
+//   PULLSUM: {row, FP32-slot list offset, count, FP64-slot list offset, count}
+//   GEMV:    {dest (0 z, 1 FP64 slot), index, value offset, len, x offset}
+//   BGEMV:   {out, value offset, len1, z offset, len2, gather list offset}
+struct CTask {
+    int32_t a[8];
+};
+struct CPhase {
+    int32_t kind, task0, ntasks, group;   // group: lanes per task (16 or 64)
 };
 
 struct Plan {
@@ -83,26 +84,22 @@ struct Plan {
     std::vector<int32_t> K_ptr, K_col;
     std::vector<double> K_val;
 
-    // factor
+    // factor and solve programs
     std::vector<Supernode> sn;
-    std::vector<float> fvals;             // interior factor blocks
-    std::vector<double> dvals;            // interface factor blocks
-    std::vector<int32_t> gidx;            // gather indices (rows lists)
     int64_t nnz_int = 0, nnz_coarse = 0;
-
-    // solve programs
-    std::vector<Seg> segs;
-    std::vector<Task> tasks;
-    std::vector<Phase> phases;
-    std::vector<int32_t> sub_fwd_ph, sub_bwd_ph;   // D+1 ranges into phases (per subdomain)
-    // interior programs as LDS chunks (values and gather indices packed)
+    int32_t n_clevels = 0, max_sub_phases = 0, max_sub_n = 0;
+    // interior: LDS chunk programs per subdomain
     std::vector<Chunk> chunks;
     std::vector<int32_t> sub_fwd_ch, sub_bwd_ch;   // D+1 ranges into chunks
-    std::vector<float> ivals;                      // packed interior values
+    std::vector<float> ivals;                      // packed chunks (values and int words)
     std::vector<int32_t> bnd, bnd_off;             // per subdomain: interface rows it touches
-    int32_t max_nb = 0, chunk_floats = 0;
-    std::vector<int32_t> coarse_fwd_ph, coarse_bwd_ph;  // ranges of phases, one launch each
-    int32_t max_sub_phases = 0, max_sub_n = 0, n_clevels = 0;
+    int32_t max_nb = 0, max_cint = 0, chunk_floats = 0;
+    // interface: FP64 values and one launch per phase
+    std::vector<double> dvals;
+    std::vector<CTask> ctasks;
+    std::vector<int32_t> cslots, cgidx;            // contribution slot lists, gather lists
+    std::vector<CPhase> cfwd, cbwd;
+    int32_t n_cgf = 0, n_cgd = 0;                  // global FP32 / FP64 contribution slots
 
     double seconds = 0;
 };

@@ -12,17 +12,11 @@
 using namespace vh;
 
 namespace {
-
-template <class T>
-double seg_dot(const Plan& P, const Seg& g, const T* x) {
-    double acc = 0.0;
-    if (g.kind == 1)
-        for (int k = 0; k < g.len; ++k) acc += (double)P.fvals[g.voff + k] * (double)x[g.xoff + k];
-    else
-        for (int k = 0; k < g.len; ++k) acc += P.dvals[g.voff + k] * (double)x[g.xoff + k];
-    return acc;
+inline int32_t word(const float* p) {
+    int32_t v;
+    std::memcpy(&v, p, 4);
+    return v;
 }
-
 }  // namespace
 
 extern "C" {
@@ -44,13 +38,13 @@ void* vhp_build(const double* X, int nv, const int* tets, int nt, const double* 
 void vhp_free(void* h) { delete static_cast<Plan*>(h); }
 
 // sizes: n_free, n_int, n_gamma, D, n_sn, n_clevels, nnz_int, nnz_coarse, max_sub_phases,
-// n_phases, n_tasks, n_segs, max_sub_n
+// n_chunks, n_ctasks, n_cslots, max_sub_n
 void vhp_info(void* h, long long* out) {
     const Plan& P = *static_cast<Plan*>(h);
     out[0] = P.n_free; out[1] = P.n_int; out[2] = P.n_gamma; out[3] = P.D;
     out[4] = (long long)P.sn.size(); out[5] = P.n_clevels; out[6] = P.nnz_int;
-    out[7] = P.nnz_coarse; out[8] = P.max_sub_phases; out[9] = (long long)P.phases.size();
-    out[10] = (long long)P.tasks.size(); out[11] = (long long)P.segs.size(); out[12] = P.max_sub_n;
+    out[7] = P.nnz_coarse; out[8] = P.max_sub_phases; out[9] = (long long)P.chunks.size();
+    out[10] = (long long)P.ctasks.size(); out[11] = (long long)P.cslots.size(); out[12] = P.max_sub_n;
 }
 
 void vhp_perm(void* h, int* perm) {
@@ -62,114 +56,90 @@ void vhp_perm(void* h, int* perm) {
 void vhp_solve(void* h, const double* rhs, double* d) {
     const Plan& P = *static_cast<Plan*>(h);
     const int nint = P.n_int, ng = P.n_gamma;
-    std::vector<double> R((size_t)P.n_free * 3), Z((size_t)P.n_free * 3), Dv((size_t)P.n_free * 3);
-    for (int i = 0; i < P.n_free; ++i)
-        for (int c = 0; c < 3; ++c) R[3 * i + c] = rhs[3 * P.perm[i] + c];
+    for (int u = 0; u < P.nv * 3; ++u) d[u] = 0.0;
     for (int c = 0; c < 3; ++c) {
         std::vector<double> Rc(P.n_free), Zc(P.n_free, 0.0), Dc(P.n_free, 0.0);
-        for (int i = 0; i < P.n_free; ++i) Rc[i] = R[3 * i + c];
-        // interior forward (chunk programs, values from ivals)
+        for (int i = 0; i < P.n_free; ++i) Rc[i] = rhs[3 * P.perm[i] + c];
+        std::vector<double> CGF(P.n_cgf, 0.0), CGD(P.n_cgd, 0.0);
+        // interior forward
         for (int s = 0; s < P.D; ++s) {
             const int base = P.sub_off[s], nloc = P.sub_off[s + 1] - base;
-            std::vector<double> r(Rc.begin() + base, Rc.begin() + base + nloc), z(nloc, 0.0);
+            std::vector<double> r(Rc.begin() + base, Rc.begin() + base + nloc), z(nloc, 0.0),
+                C(P.max_cint, 0.0);
             for (int ch = P.sub_fwd_ch[s]; ch < P.sub_fwd_ch[s + 1]; ++ch) {
-                const Chunk& C = P.chunks[ch];
-                const float* cur = P.ivals.data() + C.v0;
-                for (int t = C.task0; t < C.task1; ++t) {
-                    const Task& T = P.tasks[t];
-                    double acc = 0.0;
-                    for (int g = T.seg0; g < T.seg1; ++g) {
-                        const Seg& S = P.segs[g];
-                        const std::vector<double>& xv = (C.kind == FWD_PULL) ? z : r;
-                        for (int k = 0; k < S.len; ++k) acc += (double)cur[S.voff + k] * xv[S.xoff + k];
+                const Chunk& K = P.chunks[ch];
+                const float* desc = P.ivals.data() + K.v0;
+                const float* dat = desc + 8 * K.ntasks;
+                for (int t = 0; t < K.ntasks; ++t) {
+                    const float* q = desc + 8 * t;
+                    if (K.kind == PULLSUM) {
+                        double acc = 0.0;
+                        for (int k = 0; k < word(q + 2); ++k) acc += C[word(dat + word(q + 1) + k)];
+                        r[word(q)] -= acc;
+                    } else {
+                        double acc = 0.0;
+                        const int off = word(q + 2), len = word(q + 3), xo = word(q + 4);
+                        for (int k = 0; k < len; ++k) acc += (double)dat[off + k] * r[xo + k];
+                        const int dest = word(q), idx = word(q + 1);
+                        if (dest == 0) z[idx] = acc;
+                        else if (dest == 1) C[idx] = (double)(float)acc;
+                        else CGF[idx] = (double)(float)acc;
                     }
-                    if (C.kind == FWD_PULL) r[T.out] -= acc;
-                    else z[T.out] = acc;
                 }
             }
             for (int i = 0; i < nloc; ++i) Zc[base + i] = z[i];
         }
         // interface forward
-        std::vector<double> R64(Rc.begin() + nint, Rc.end()), Z64(ng, 0.0), D64(ng, 0.0);
-        for (int ph : P.coarse_fwd_ph) {
-            const Phase& Ph = P.phases[ph];
-            std::vector<double> outv(Ph.task1 - Ph.task0);
-            for (int t = Ph.task0; t < Ph.task1; ++t) {
-                const Task& T = P.tasks[t];
-                double acc = 0.0;
-                for (int g = T.seg0; g < T.seg1; ++g) {
-                    const Seg& S = P.segs[g];
-                    if (Ph.kind == FWD_PULL) acc += seg_dot(P, S, S.kind == 1 ? Zc.data() : Z64.data());
-                    else acc += seg_dot(P, S, R64.data());
+        std::vector<double> rg(ng, 0.0), zg(ng, 0.0), dg(ng, 0.0);
+        for (const CPhase& ph : P.cfwd)
+            for (int t = ph.task0; t < ph.task0 + ph.ntasks; ++t) {
+                const int32_t* a = P.ctasks[t].a;
+                if (ph.kind == PULLSUM) {
+                    double acc = 0.0;
+                    for (int k = 0; k < a[2]; ++k) acc += CGF[P.cslots[a[1] + k]];
+                    for (int k = 0; k < a[4]; ++k) acc += CGD[P.cslots[a[3] + k]];
+                    rg[a[0]] = Rc[nint + a[0]] - acc;
+                } else {
+                    double acc = 0.0;
+                    for (int k = 0; k < a[3]; ++k) acc += P.dvals[a[2] + k] * rg[a[4] + k];
+                    if (a[0] == 0) zg[a[1]] = acc;
+                    else CGD[a[1]] = acc;
                 }
-                outv[t - Ph.task0] = (Ph.kind == FWD_PULL) ? R64[T.out] - acc : acc;
             }
-            for (int t = Ph.task0; t < Ph.task1; ++t) {
-                const Task& T = P.tasks[t];
-                if (Ph.kind == FWD_PULL) R64[T.out] = outv[t - Ph.task0];
-                else Z64[T.out] = outv[t - Ph.task0];
-            }
-        }
         // interface backward
-        for (int ph : P.coarse_bwd_ph) {
-            const Phase& Ph = P.phases[ph];
-            std::vector<double> outv(Ph.task1 - Ph.task0);
-            for (int t = Ph.task0; t < Ph.task1; ++t) {
-                const Task& T = P.tasks[t];
+        for (const CPhase& ph : P.cbwd)
+            for (int t = ph.task0; t < ph.task0 + ph.ntasks; ++t) {
+                const int32_t* a = P.ctasks[t].a;
                 double acc = 0.0;
-                for (int g = T.seg0; g < T.seg1; ++g) {
-                    const Seg& S = P.segs[g];
-                    if (Ph.kind == BWD_PULL) {
-                        for (int k = 0; k < S.len; ++k)
-                            acc += P.dvals[S.voff + k] * D64[P.gidx[S.xoff + k] - nint];
-                    } else {
-                        acc += seg_dot(P, S, R64.data());
-                    }
-                }
-                outv[t - Ph.task0] = (Ph.kind == BWD_PULL) ? Z64[T.out] - acc : acc;
+                for (int k = 0; k < a[2]; ++k) acc += P.dvals[a[1] + k] * zg[a[3] + k];
+                for (int k = 0; k < a[4]; ++k) acc += P.dvals[a[1] + a[2] + k] * dg[P.cgidx[a[5] + k]];
+                dg[a[0]] = acc;
             }
-            for (int t = Ph.task0; t < Ph.task1; ++t) {
-                const Task& T = P.tasks[t];
-                if (Ph.kind == BWD_PULL) R64[T.out] = outv[t - Ph.task0];
-                else D64[T.out] = outv[t - Ph.task0];
-            }
-        }
-        for (int i = 0; i < ng; ++i) Dc[nint + i] = D64[i];
-        // interior backward (chunk programs, gathers through the staged boundary rows)
+        for (int i = 0; i < ng; ++i) Dc[nint + i] = dg[i];
+        // interior backward
         for (int s = 0; s < P.D; ++s) {
             const int base = P.sub_off[s], nloc = P.sub_off[s + 1] - base;
             const int b0 = P.bnd_off[s], nb = P.bnd_off[s + 1] - b0;
-            std::vector<double> zq(Zc.begin() + base, Zc.begin() + base + nloc), dl(nloc + nb, 0.0);
-            for (int k = 0; k < nb; ++k) dl[nloc + k] = (double)(float)D64[P.bnd[b0 + k] - nint];
+            std::vector<double> z(Zc.begin() + base, Zc.begin() + base + nloc), dl(nloc + nb, 0.0);
+            for (int k = 0; k < nb; ++k) dl[nloc + k] = (double)(float)dg[P.bnd[b0 + k] - nint];
             for (int ch = P.sub_bwd_ch[s]; ch < P.sub_bwd_ch[s + 1]; ++ch) {
-                const Chunk& C = P.chunks[ch];
-                const float* cur = P.ivals.data() + C.v0;
-                for (int t = C.task0; t < C.task1; ++t) {
-                    const Task& T = P.tasks[t];
+                const Chunk& K = P.chunks[ch];
+                const float* desc = P.ivals.data() + K.v0;
+                const float* dat = desc + 8 * K.ntasks;
+                for (int t = 0; t < K.ntasks; ++t) {
+                    const float* q = desc + 8 * t;
+                    const int out = word(q), off = word(q + 1), len1 = word(q + 2), xo = word(q + 3),
+                              len2 = word(q + 4), go = word(q + 5);
                     double acc = 0.0;
-                    for (int g = T.seg0; g < T.seg1; ++g) {
-                        const Seg& S = P.segs[g];
-                        for (int k = 0; k < S.len; ++k) {
-                            if (C.kind == BWD_PULL) {
-                                int li;
-                                std::memcpy(&li, cur + S.xoff + k, 4);
-                                acc += (double)cur[S.voff + k] * dl[li];
-                            } else {
-                                acc += (double)cur[S.voff + k] * zq[S.xoff + k];
-                            }
-                        }
-                    }
-                    if (C.kind == BWD_PULL) zq[T.out] -= acc;
-                    else dl[T.out] = acc;
+                    for (int k = 0; k < len1; ++k) acc += (double)dat[off + k] * z[xo + k];
+                    for (int k = 0; k < len2; ++k) acc += (double)dat[off + len1 + k] * dl[word(dat + go + k)];
+                    dl[out] = acc;
                 }
             }
             for (int i = 0; i < nloc; ++i) Dc[base + i] = dl[i];
         }
-        for (int i = 0; i < P.n_free; ++i) Dv[3 * i + c] = Dc[i];
+        for (int i = 0; i < P.n_free; ++i) d[3 * P.perm[i] + c] = Dc[i];
     }
-    for (int u = 0; u < P.nv * 3; ++u) d[u] = 0.0;
-    for (int i = 0; i < P.n_free; ++i)
-        for (int c = 0; c < 3; ++c) d[3 * P.perm[i] + c] = Dv[3 * i + c];
 }
 }
 

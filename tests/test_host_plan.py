@@ -38,7 +38,7 @@ def _build(hl, p, D, leaf=32, pinned=None):
     info = np.zeros(13, dtype=np.int64)
     if h:
         hl.vhp_info(h, info.ctypes.data)
-    keys = "n_free n_int n_gamma D n_sn n_clevels nnz_int nnz_coarse max_sub_phases n_phases n_tasks n_segs max_sub_n"
+    keys = "n_free n_int n_gamma D n_sn n_clevels nnz_int nnz_coarse max_sub_phases n_chunks n_ctasks n_cslots max_sub_n"
     return h, rc.value, msg.value.decode(), dict(zip(keys.split(), info.tolist()))
 
 
