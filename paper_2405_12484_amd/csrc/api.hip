@@ -368,16 +368,15 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     if (refine_steps < 0) return fail(VH_EINVAL, "refine_steps must be >= 0");
     VH_TRY(set_device(m));
     free_device(m);
-    // LDS per workgroup decides the chunk size of the interior programs:
-    // two chunk buffers of nv4 * 4 * 256 floats next to the subdomain vectors
+    // the interior kernels hold two LDS chunks (48 KB each) next to the
+    // subdomain's vectors: gfx950 gives a workgroup up to 160 KB
     int lds_limit = 0;
     VH_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                  m->ctx->device));
-    const int nv4 = (lds_limit >= 160 * 1024) ? 8 : 4;
     std::string msg;
     int rc = vh::build_plan(m->X.data(), m->nv, m->tets.data(), m->nt, m->gs.data(), m->gv.data(),
                             m->mass.data(), m->pinned.data(), m->g, m->dt, m->iters, n_subdomains,
-                            refine_steps, 32, nv4 * 4 * 256, m->plan, msg);
+                            refine_steps, 32, vh::interior_chunk_words(), m->plan, msg);
     if (rc != 0) return fail(rc, msg);
     const vh::Plan& P = m->plan;
     vh::DevMesh& d = m->dm;
@@ -390,13 +389,12 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     d.max_sub_n = std::max(P.max_sub_n, 1);
     d.max_nb = P.max_nb;
     d.max_cint = P.max_cint;
-    d.chunk_nv4 = nv4;
     const size_t lds_need = std::max(vh::interior_fwd_lds(d), vh::interior_bwd_lds(d));
     if (lds_need > (size_t)lds_limit)
         return fail(VH_EINVAL, "a subdomain needs " + std::to_string(lds_need) +
                                    " bytes of LDS (limit " + std::to_string(lds_limit) +
                                    "); use more subdomains");
-    if (lds_need > 65536) VH_HIP(vh::interior_set_lds_limit(nv4, lds_need));
+    if (lds_need > 65536) VH_HIP(vh::interior_set_lds_limit(lds_need));
     d.dt = P.dt;
     for (int c = 0; c < 3; ++c) d.g[c] = P.gravity[c];
     const size_t nv3 = (size_t)P.nv * 3;

@@ -35,6 +35,9 @@ namespace vh {
 namespace {
 
 constexpr int OK = 0, EINVAL_ = -1, ENOMEM_ = -2, ENOTSPD_ = -3;
+// Interior supernodes have at most this many columns, so that one supernode's
+// solve block fits an LDS chunk and a wave's lanes cover its columns.
+constexpr int32_t kMaxInteriorCols = 32;
 
 inline void tet_dm(const double* X, const int32_t* t, double Dm[9]) {
     // Dm[r][k] = X[t[k+1]][r] - X[t[0]][r]
@@ -445,7 +448,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         if (ndroot[d] < 0) continue;
         // iterative postorder of the ND tree; returns supernode id of each ND node
         std::vector<NDNode>& T = ndt[d];
-        std::vector<int32_t> snid(T.size(), -1);
+        std::vector<int32_t> snid(T.size(), -1), snid_last(T.size(), -1);
         std::vector<std::pair<int32_t, int>> st;
         st.push_back({ndroot[d], 0});
         while (!st.empty()) {
@@ -460,13 +463,23 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             } else {
                 st.pop_back();
                 if (!T[u].verts.empty()) {
-                    Supernode s;
-                    s.col0 = (int32_t)order.size();
-                    s.n = (int32_t)T[u].verts.size();
-                    s.sub = d;
-                    for (int32_t v : T[u].verts) order.push_back(v);
+                    // pieces of at most kMaxInteriorCols columns, chained: each
+                    // piece's parent is the next one (a separator's diagonal
+                    // block is dense, so every piece's rows include the later ones)
+                    const int32_t nvts = (int32_t)T[u].verts.size();
+                    const int32_t npc = (nvts + kMaxInteriorCols - 1) / kMaxInteriorCols;
                     snid[u] = (int32_t)SN.size();
-                    SN.push_back(std::move(s));
+                    for (int32_t pc = 0; pc < npc; ++pc) {
+                        const int32_t a0 = pc * nvts / npc, a1 = (pc + 1) * nvts / npc;
+                        Supernode s;
+                        s.col0 = (int32_t)order.size();
+                        s.n = a1 - a0;
+                        s.sub = d;
+                        for (int32_t k = a0; k < a1; ++k) order.push_back(T[u].verts[k]);
+                        if (pc + 1 < npc) s.parent = (int32_t)SN.size() + 1;
+                        SN.push_back(std::move(s));
+                    }
+                    snid_last[u] = (int32_t)SN.size() - 1;
                 }
             }
         }
@@ -480,7 +493,8 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             if (snid[u] < 0) continue;
             int32_t a = ndpar[u];
             while (a >= 0 && snid[a] < 0) a = ndpar[a];
-            SN[snid[u]].parent = (a >= 0) ? snid[a] : -2;   // -2: attach to interface later
+            // the last piece hangs below the first piece of the nearest non-empty ancestor
+            SN[snid_last[u]].parent = (a >= 0) ? snid[a] : -2;   // -2: attach to interface later
         }
     }
     P.sub_off[D] = (int32_t)order.size();
@@ -782,7 +796,9 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             int64_t off = s.wb_off + (int64_t)k * (n + m) - (int64_t)k * (k - 1) / 2;
             for (int32_t i = k; i < n; ++i) vals[off + (i - k)] = Ti[(size_t)i * n + k];
             off += n - k;
-            for (int32_t p = 0; p < m; ++p) vals[off + p] = -WB[(size_t)p * n + k];
+            // interface blocks hold -W_B (backward dot products); interior blocks +W_B
+            const double sg = (s.sub >= 0) ? 1.0 : -1.0;
+            for (int32_t p = 0; p < m; ++p) vals[off + p] = sg * WB[(size_t)p * n + k];
         }
         std::vector<double> U((size_t)m * m);
         for (int32_t b = 0; b < m; ++b)
@@ -884,15 +900,23 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         std::memcpy(&f, &v, 4);
         return f;
     };
+    // Chunk layouts (32-bit words; ints bit-cast into the float array):
+    //   PULLSUM: ntasks x {row, list offset, count, 0}, then the slot lists
+    //   GEMV:    ntasks x {col0, n, m, m_int, cint0, cg0, value offset, row0}, then
+    //            the supernodes' column-major blocks (column k: rows k..n+m-1)
+    //   BGEMV:   ntasks x {col0, n, m, value offset, gather offset, col0 of the
+    //            block, 0, 0}, then gather lists and row-major blocks
+    // Descriptors are 8 words (PULLSUM uses 4); data offsets are relative to the
+    // data start, which is desc_words * ntasks.
     struct Builder {
         int32_t kind = 0;
         std::vector<int32_t> desc;
         std::vector<float> data;
-        int32_t gather_sn = -1, gather_off = 0;
     } cb;
     bool too_big = false;
+    auto dwords = [](int32_t kind) { return kind == PULLSUM ? 4 : 8; };
     auto flush = [&]() {
-        const int32_t nt_ = (int32_t)cb.desc.size() / 8;
+        const int32_t nt_ = (int32_t)cb.desc.size() / dwords(cb.kind);
         if (nt_ == 0) return;
         while (P.ivals.size() % 4) P.ivals.push_back(0.0f);
         Chunk c;
@@ -907,10 +931,9 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         P.chunks.push_back(c);
         cb.desc.clear();
         cb.data.clear();
-        cb.gather_sn = -1;
     };
-    auto room = [&](int32_t need) {
-        return (int32_t)(cb.desc.size() + cb.data.size()) + need + 8 <= chunk_floats || cb.desc.empty();
+    auto room = [&](int32_t need_words) {
+        return (int32_t)(cb.desc.size() + cb.data.size()) + need_words <= chunk_floats || cb.desc.empty();
     };
     auto start_phase = [&](int32_t kind) {
         flush();
@@ -932,11 +955,11 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                 for (int32_t a = 0; a < SN[t].n; ++a) {
                     const auto& L = pull_i[SN[t].col0 + a];
                     if (L.empty()) continue;
-                    if (!room((int32_t)L.size())) flush();
+                    if (!room(4 + (int32_t)L.size())) flush();
                     int32_t off = (int32_t)cb.data.size();
                     for (int32_t sl : L) cb.data.push_back(as_f(sl));
-                    int32_t dsc[8] = {SN[t].col0 + a - base, off, (int32_t)L.size(), 0, 0, 0, 0, 0};
-                    cb.desc.insert(cb.desc.end(), dsc, dsc + 8);
+                    int32_t dsc[4] = {SN[t].col0 + a - base, off, (int32_t)L.size(), 0};
+                    cb.desc.insert(cb.desc.end(), dsc, dsc + 4);
                 }
             }
             start_phase(GEMV);
@@ -944,25 +967,13 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                 if (SN[t].height != h) continue;
                 const Supernode& S = SN[t];
                 const int32_t n = S.n, m = (int32_t)S.rows.size();
-                const int64_t tri = (int64_t)n * (n + 1) / 2;
-                for (int32_t i = 0; i < n + m; ++i) {
-                    const int32_t len = (i < n) ? i + 1 : n;
-                    const int64_t vo = S.wf_off + ((i < n) ? (int64_t)i * (i + 1) / 2 : tri + (int64_t)(i - n) * n);
-                    if (!room(len)) flush();
-                    int32_t off = (int32_t)cb.data.size();
-                    for (int32_t k = 0; k < len; ++k) cb.data.push_back((float)ivd[vo + k]);
-                    int32_t dest, idx;
-                    if (i < n) {
-                        dest = 0;
-                        idx = S.col0 + i - base;
-                    } else if (i < n + S.m_int) {
-                        dest = 1;
-                        idx = S.cint0 + (i - n);
-                    } else {
-                        dest = 2;
-                        idx = S.cg0 + (i - n - S.m_int);
-                    }
-                    int32_t dsc[8] = {dest, idx, off, len, S.col0 - base, 0, 0, 0};
+                const int32_t blk = n * (n + 1) / 2 + m * n;
+                const int32_t nblk_rows = (n + m + 63) / 64;
+                if (!room(8 * nblk_rows + blk)) flush();
+                const int32_t off = (int32_t)cb.data.size();
+                for (int32_t q = 0; q < blk; ++q) cb.data.push_back((float)ivd[S.wb_off + q]);
+                for (int32_t rb = 0; rb < nblk_rows; ++rb) {
+                    int32_t dsc[8] = {S.col0 - base, n, m, S.m_int, S.cint0, S.cg0, off, 64 * rb};
                     cb.desc.insert(cb.desc.end(), dsc, dsc + 8);
                 }
             }
@@ -984,19 +995,15 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                 if (SN[t].height != h) continue;
                 const Supernode& S = SN[t];
                 const int32_t n = S.n, m = (int32_t)S.rows.size();
-                for (int32_t k = 0; k < n; ++k) {
-                    const int32_t len1 = n - k;
-                    const bool need_g = (m > 0 && cb.gather_sn != t);
-                    if (!room(len1 + m + (need_g ? m : 0))) flush();
-                    if (m > 0 && cb.gather_sn != t) {
-                        cb.gather_off = (int32_t)cb.data.size();
-                        for (int32_t r : S.rows) cb.data.push_back(as_f(r < P.n_int ? r - base : bpos[r]));
-                        cb.gather_sn = t;
-                    }
-                    const int64_t vo = S.wb_off + (int64_t)k * (n + m) - (int64_t)k * (k - 1) / 2;
-                    int32_t off = (int32_t)cb.data.size();
-                    for (int32_t q = 0; q < len1 + m; ++q) cb.data.push_back((float)ivd[vo + q]);
-                    int32_t dsc[8] = {S.col0 + k - base, off, len1, S.col0 + k - base, m, cb.gather_off, 0, 0};
+                const int32_t blk = n * (n + 1) / 2 + m * n;
+                const int32_t nblk_cols = (n + 63) / 64;
+                if (!room(8 * nblk_cols + m + blk)) flush();
+                const int32_t goff = (int32_t)cb.data.size();
+                for (int32_t r : S.rows) cb.data.push_back(as_f(r < P.n_int ? r - base : bpos[r]));
+                const int32_t off = (int32_t)cb.data.size();
+                for (int32_t q = 0; q < blk; ++q) cb.data.push_back((float)ivd[S.wf_off + q]);
+                for (int32_t cbk = 0; cbk < nblk_cols; ++cbk) {
+                    int32_t dsc[8] = {S.col0 - base, n, m, off, goff, 64 * cbk, 0, 0};
                     cb.desc.insert(cb.desc.end(), dsc, dsc + 8);
                 }
             }
@@ -1006,7 +1013,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
     P.sub_bwd_ch[D] = (int32_t)P.chunks.size();
     while (P.ivals.size() % 4) P.ivals.push_back(0.0f);
     if (too_big) {
-        msg = "a solve task does not fit one LDS chunk";
+        msg = "an interior supernode's solve block does not fit one LDS chunk";
         return EINVAL_;
     }
 

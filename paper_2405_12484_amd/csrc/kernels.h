@@ -36,7 +36,7 @@ struct DevMesh {
     int32_t *sub_fwd_ch = nullptr, *sub_bwd_ch = nullptr;
     float* ivals = nullptr;
     int32_t *bnd = nullptr, *bnd_off = nullptr;
-    int32_t max_nb = 0, max_cint = 0, chunk_nv4 = 4;   // chunk capacity = chunk_nv4 * 4 * 256 floats
+    int32_t max_nb = 0, max_cint = 0;
     double* dvals = nullptr;
     CTask* ctasks = nullptr;
     int32_t *cslots = nullptr, *cgidx = nullptr;
@@ -56,7 +56,9 @@ using PhaseLaunch = CPhase;
 size_t interior_fwd_lds(const DevMesh& m);
 size_t interior_bwd_lds(const DevMesh& m);
 // allow the interior kernels to use up to `bytes` of LDS per workgroup
-hipError_t interior_set_lds_limit(int chunk_nv4, size_t bytes);
+hipError_t interior_set_lds_limit(size_t bytes);
+// capacity of one interior LDS chunk in 32-bit words
+int32_t interior_chunk_words();
 
 hipError_t launch_predictor(const DevMesh& m, hipStream_t s);
 hipError_t launch_local(const DevMesh& m, hipStream_t s, bool debug);

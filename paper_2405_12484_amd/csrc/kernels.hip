@@ -330,7 +330,6 @@ __global__ __launch_bounds__(BLK) void k_residual(int32_t n_free, int32_t nt4,
 // ---------------------------------------------------------------------------
 // Decomposed solve
 // ---------------------------------------------------------------------------
-constexpr int IG = 16;                 // lanes per task in the interior kernels
 
 template <int WIDTH, class T>
 __device__ __forceinline__ T group_sum(T v) {
@@ -356,55 +355,56 @@ struct SolveArgs {
     float4* u;
 };
 
+// Interior kernels: one 1024-thread workgroup (16 waves) per subdomain.
+constexpr int BLKI = 1024;
+constexpr int NV4I = 3;                       // float4 per thread per chunk
+constexpr int32_t CHI = NV4I * 4 * BLKI;      // chunk capacity in 32-bit words (48 KB)
+
 // Coalesced copy of one chunk (nv4 float4) into registers / LDS.
-template <int NV4>
-__device__ __forceinline__ void chunk_load(const float4* __restrict__ src, int32_t nv4, float4 (&reg)[NV4]) {
+__device__ __forceinline__ void chunk_load(const float4* __restrict__ src, int32_t nv4, float4 (&reg)[NV4I]) {
 #pragma unroll
-    for (int i = 0; i < NV4; ++i) {
-        const int32_t j = threadIdx.x + i * BLK;
+    for (int i = 0; i < NV4I; ++i) {
+        const int32_t j = threadIdx.x + i * BLKI;
         if (j < nv4) reg[i] = src[j];
     }
 }
-template <int NV4>
-__device__ __forceinline__ void chunk_store(float4* dst, int32_t nv4, const float4 (&reg)[NV4]) {
+__device__ __forceinline__ void chunk_store(float4* dst, int32_t nv4, const float4 (&reg)[NV4I]) {
 #pragma unroll
-    for (int i = 0; i < NV4; ++i) {
-        const int32_t j = threadIdx.x + i * BLK;
+    for (int i = 0; i < NV4I; ++i) {
+        const int32_t j = threadIdx.x + i * BLKI;
         if (j < nv4) dst[j] = reg[i];
     }
 }
 
-// Interior forward solve, one workgroup per subdomain.  Per supernode level:
-// PULLSUM r'_row = r_row - sum of its LDS contribution slots, then GEMV
-// [z; c] = [Ti; B Ti] r' (z and interior contributions to LDS, interface
-// contributions to the global FP32 slots).  Each chunk (task descriptors,
-// values, slot lists) is staged in LDS; the next chunk is read into registers
-// while the current one is computed.
-template <int NV4>
-__global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a) {
-    constexpr int32_t CH = NV4 * 4 * BLK;
+// Interior forward solve.  Per supernode level: PULLSUM (thread per row)
+// r'_row -= sum of its LDS contribution slots; GEMV (lane per row of
+// [Ti; B Ti], 64 rows per wave item) accumulating column by column of the
+// column-major block against broadcast r' values: z to LDS, contributions to
+// interior rows to LDS slots, to interface rows to global FP32 slots.  The next
+// chunk is read into registers while the current one is computed.
+__global__ __launch_bounds__(BLKI) void k_interior_fwd(SolveArgs a) {
     extern __shared__ float4 sm4[];
     float* sm = reinterpret_cast<float*>(sm4);
-    float* bufs[2] = {sm, sm + CH};
-    float* R = sm + 2 * CH;
+    float* bufs[2] = {sm, sm + CHI};
+    float* R = sm + 2 * CHI;
     float* Z = R + 3 * a.max_n;
     float* C = Z + 3 * a.max_n;
     const int32_t d = blockIdx.x;
     const int32_t base = a.sub_off[d];
-    const int32_t n = a.sub_off[d + 1] - base;
+    const int32_t n_loc = a.sub_off[d + 1] - base;
     const int tid = threadIdx.x;
-    for (int32_t i = tid; i < 3 * n; i += BLK) R[i] = (float)a.r[3 * base + i];
+    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)a.r[3 * base + i];
     const int32_t c0 = a.sub_fwd_ch[d], c1 = a.sub_fwd_ch[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
-    float4 reg[NV4];
+    float4 reg[NV4I];
     if (c0 < c1) {
         const Chunk K = a.chunks[c0];
-        chunk_load<NV4>(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
-        chunk_store<NV4>(reinterpret_cast<float4*>(bufs[0]), (K.nv + 3) / 4, reg);
+        chunk_load(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
+        chunk_store(reinterpret_cast<float4*>(bufs[0]), (K.nv + 3) / 4, reg);
     }
     __syncthreads();
-    const int grp = tid / IG, lane = tid % IG;
-    constexpr int NGRP = BLK / IG;
+    const int wave = tid / 64, lane = tid % 64;
+    constexpr int NW = BLKI / 64;
     for (int32_t c = c0; c < c1; ++c) {
         const Chunk K = a.chunks[c];
         const float* cur = bufs[(c - c0) & 1];
@@ -413,54 +413,59 @@ __global__ __launch_bounds__(BLK) void k_interior_fwd(SolveArgs a) {
         if (more) {
             const Chunk Kn = a.chunks[c + 1];
             nxt4 = (Kn.nv + 3) / 4;
-            chunk_load<NV4>(iv4 + Kn.v0 / 4, nxt4, reg);
+            chunk_load(iv4 + Kn.v0 / 4, nxt4, reg);
         }
         const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
-        const float* dat = cur + 8 * K.ntasks;
-        const int32_t* idat = reinterpret_cast<const int32_t*>(dat);
-        for (int32_t t = grp; t < K.ntasks; t += NGRP) {
-            const int32_t* q = desc + 8 * t;
-            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-            if (K.kind == PULLSUM) {
-                const int32_t off = q[1], cnt = q[2];
-                for (int32_t k = lane; k < cnt; k += IG) {
-                    const float* cp = C + 3 * idat[off + k];
+        if (K.kind == PULLSUM) {
+            const int32_t* idat = desc + 4 * K.ntasks;
+            for (int32_t t = tid; t < K.ntasks; t += BLKI) {
+                const int32_t* q = desc + 4 * t;
+                const int32_t* sl = idat + q[1];
+                const int32_t cnt = q[2];
+                float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+                for (int32_t k = 0; k < cnt; ++k) {
+                    const float* cp = C + 3 * sl[k];
                     s0 += cp[0];
                     s1 += cp[1];
                     s2 += cp[2];
                 }
-            } else {
-                const int32_t off = q[2], len = q[3], xo = q[4];
-                for (int32_t k = lane; k < len; k += IG) {
-                    const float v = dat[off + k];
-                    const float* xp = R + 3 * (xo + k);
-                    s0 += v * xp[0];
-                    s1 += v * xp[1];
-                    s2 += v * xp[2];
-                }
+                float* rp = R + 3 * q[0];
+                rp[0] -= s0;
+                rp[1] -= s1;
+                rp[2] -= s2;
             }
-            s0 = group_sum<IG>(s0);
-            s1 = group_sum<IG>(s1);
-            s2 = group_sum<IG>(s2);
-            if (lane == 0) {
-                if (K.kind == PULLSUM) {
-                    float* rp = R + 3 * q[0];
-                    rp[0] -= s0;
-                    rp[1] -= s1;
-                    rp[2] -= s2;
-                } else {
-                    const int32_t dest = q[0], idx = q[1];
-                    float* op = (dest == 0) ? Z + 3 * idx : (dest == 1) ? C + 3 * idx : a.cgf + 3 * (size_t)idx;
-                    op[0] = s0;
-                    op[1] = s1;
-                    op[2] = s2;
+        } else {
+            const float* dat = cur + 8 * K.ntasks;
+            for (int32_t t = wave; t < K.ntasks; t += NW) {
+                const int32_t* q = desc + 8 * t;
+                const int32_t col0 = q[0], n = q[1], m = q[2], mi = q[3];
+                const int32_t i = q[7] + lane;
+                if (i >= n + m) continue;
+                const float* w = dat + q[6] + i;        // column k element of row i: w[co(k) - k]
+                const float* x = R + 3 * col0;
+                const int32_t kmax = min(i + 1, n), stride0 = n + m;
+                float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+                int32_t co = 0;
+#pragma unroll 4
+                for (int32_t k = 0; k < kmax; ++k) {
+                    const float v = w[co - k];
+                    s0 += v * x[3 * k];
+                    s1 += v * x[3 * k + 1];
+                    s2 += v * x[3 * k + 2];
+                    co += stride0 - k;
                 }
+                float* op = (i < n) ? Z + 3 * (col0 + i)
+                                    : (i < n + mi) ? C + 3 * (q[4] + i - n)
+                                                   : a.cgf + 3 * (size_t)(q[5] + i - n - mi);
+                op[0] = s0;
+                op[1] = s1;
+                op[2] = s2;
             }
         }
-        if (more) chunk_store<NV4>(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
+        if (more) chunk_store(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
         __syncthreads();
     }
-    for (int32_t i = tid; i < 3 * n; i += BLK) a.zf[3 * base + i] = Z[i];
+    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) a.zf[3 * base + i] = Z[i];
 }
 
 // Interface phases, one group of G lanes per task (FP64).
@@ -562,39 +567,38 @@ __global__ __launch_bounds__(BLK) void k_coarse(SolveArgs a, int32_t kind, int32
     }
 }
 
-// Interior backward solve and update, one workgroup per subdomain.  Per
-// supernode level, top down: BGEMV d_t[k] = Ti column k . z_t + (-W_B) column k
-// . d[rows], with the subdomain's boundary values of the interface solution
-// staged in LDS after its interior rows, so every gather hits LDS.
-template <int NV4>
-__global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t apply, int32_t keep_delta) {
-    constexpr int32_t CH = NV4 * 4 * BLK;
+// Interior backward solve and update.  Per supernode level, top down: BGEMV
+// (lane per column k of the row-major block [Ti; B Ti]):
+// d_k = sum_{i>=k} Ti[i][k] z_i - sum_p (B Ti)[p][k] d[rows_p], with the
+// subdomain's boundary values of the interface solution staged in LDS after
+// its interior rows, so every gather hits LDS.
+__global__ __launch_bounds__(BLKI) void k_interior_bwd(SolveArgs a, int32_t apply, int32_t keep_delta) {
     extern __shared__ float4 sm4[];
     float* sm = reinterpret_cast<float*>(sm4);
-    float* bufs[2] = {sm, sm + CH};
-    float* Z = sm + 2 * CH;
+    float* bufs[2] = {sm, sm + CHI};
+    float* Z = sm + 2 * CHI;
     float* DL = Z + 3 * a.max_n;
     const int32_t d = blockIdx.x;
     const int32_t base = a.sub_off[d];
-    const int32_t n = a.sub_off[d + 1] - base;
+    const int32_t n_loc = a.sub_off[d + 1] - base;
     const int32_t b0 = a.bnd_off[d], nb = a.bnd_off[d + 1] - b0;
     const int tid = threadIdx.x;
-    for (int32_t i = tid; i < 3 * n; i += BLK) Z[i] = a.zf[3 * base + i];
-    for (int32_t i = tid; i < 3 * nb; i += BLK) {
+    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) Z[i] = a.zf[3 * base + i];
+    for (int32_t i = tid; i < 3 * nb; i += BLKI) {
         const int32_t k = i / 3, c = i - 3 * k;
-        DL[3 * n + i] = (float)a.dg[3 * (a.bnd[b0 + k] - a.n_int) + c];
+        DL[3 * n_loc + i] = (float)a.dg[3 * (a.bnd[b0 + k] - a.n_int) + c];
     }
     const int32_t c0 = a.sub_bwd_ch[d], c1 = a.sub_bwd_ch[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
-    float4 reg[NV4];
+    float4 reg[NV4I];
     if (c0 < c1) {
         const Chunk K = a.chunks[c0];
-        chunk_load<NV4>(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
-        chunk_store<NV4>(reinterpret_cast<float4*>(bufs[0]), (K.nv + 3) / 4, reg);
+        chunk_load(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
+        chunk_store(reinterpret_cast<float4*>(bufs[0]), (K.nv + 3) / 4, reg);
     }
     __syncthreads();
-    const int grp = tid / IG, lane = tid % IG;
-    constexpr int NGRP = BLK / IG;
+    const int wave = tid / 64, lane = tid % 64;
+    constexpr int NW = BLKI / 64;
     for (int32_t c = c0; c < c1; ++c) {
         const Chunk K = a.chunks[c];
         const float* cur = bufs[(c - c0) & 1];
@@ -603,44 +607,45 @@ __global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t apply
         if (more) {
             const Chunk Kn = a.chunks[c + 1];
             nxt4 = (Kn.nv + 3) / 4;
-            chunk_load<NV4>(iv4 + Kn.v0 / 4, nxt4, reg);
+            chunk_load(iv4 + Kn.v0 / 4, nxt4, reg);
         }
         const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
         const float* dat = cur + 8 * K.ntasks;
         const int32_t* idat = reinterpret_cast<const int32_t*>(dat);
-        for (int32_t t = grp; t < K.ntasks; t += NGRP) {
+        for (int32_t t = wave; t < K.ntasks; t += NW) {
             const int32_t* q = desc + 8 * t;
-            const int32_t off = q[1], len1 = q[2], xo = q[3], len2 = q[4], go = q[5];
+            const int32_t col0 = q[0], n = q[1], m = q[2];
+            const int32_t k = q[5] + lane;
+            if (k >= n) continue;
+            const float* w = dat + q[3] + k;
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-            for (int32_t k = lane; k < len1; k += IG) {
-                const float v = dat[off + k];
-                const float* xp = Z + 3 * (xo + k);
+            for (int32_t i = k; i < n; ++i) {
+                const float v = w[i * (i + 1) / 2];
+                const float* xp = Z + 3 * (col0 + i);
                 s0 += v * xp[0];
                 s1 += v * xp[1];
                 s2 += v * xp[2];
             }
-            for (int32_t k = lane; k < len2; k += IG) {
-                const float v = dat[off + len1 + k];
-                const float* xp = DL + 3 * idat[go + k];
-                s0 += v * xp[0];
-                s1 += v * xp[1];
-                s2 += v * xp[2];
+            const float* wb = w + n * (n + 1) / 2;
+            const int32_t* g = idat + q[4];
+#pragma unroll 4
+            for (int32_t p = 0; p < m; ++p) {
+                const float v = wb[p * n];
+                const float* xp = DL + 3 * g[p];
+                s0 -= v * xp[0];
+                s1 -= v * xp[1];
+                s2 -= v * xp[2];
             }
-            s0 = group_sum<IG>(s0);
-            s1 = group_sum<IG>(s1);
-            s2 = group_sum<IG>(s2);
-            if (lane == 0) {
-                float* op = DL + 3 * q[0];
-                op[0] = s0;
-                op[1] = s1;
-                op[2] = s2;
-            }
+            float* op = DL + 3 * (col0 + k);
+            op[0] = s0;
+            op[1] = s1;
+            op[2] = s2;
         }
-        if (more) chunk_store<NV4>(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
+        if (more) chunk_store(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
         __syncthreads();
     }
     // interior rows of this subdomain
-    for (int32_t i = tid; i < n; i += BLK) {
+    for (int32_t i = tid; i < n_loc; i += BLKI) {
         const int32_t gi = base + i;
         float du[3];
 #pragma unroll
@@ -658,7 +663,7 @@ __global__ __launch_bounds__(BLK) void k_interior_bwd(SolveArgs a, int32_t apply
     // a slice of the interface rows
     const int32_t chunk = (a.n_gamma + a.D - 1) / a.D;
     const int32_t g0 = d * chunk, g1 = min(a.n_gamma, g0 + chunk);
-    for (int32_t i = g0 + tid; i < g1; i += BLK) {
+    for (int32_t i = g0 + tid; i < g1; i += BLKI) {
         const int32_t gi = a.n_int + i;
         float du[3];
 #pragma unroll
@@ -771,39 +776,26 @@ hipError_t launch_residual(const DevMesh& m, hipStream_t s) {
 }
 
 size_t interior_fwd_lds(const DevMesh& m) {
-    return sizeof(float) *
-           (2 * (size_t)m.chunk_nv4 * 4 * BLK + 6 * (size_t)m.max_sub_n + 3 * (size_t)m.max_cint);
+    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)m.max_sub_n + 3 * (size_t)m.max_cint);
 }
 
 size_t interior_bwd_lds(const DevMesh& m) {
-    return sizeof(float) *
-           (2 * (size_t)m.chunk_nv4 * 4 * BLK + 6 * (size_t)m.max_sub_n + 3 * (size_t)m.max_nb);
+    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)m.max_sub_n + 3 * (size_t)m.max_nb);
 }
 
-hipError_t interior_set_lds_limit(int chunk_nv4, size_t bytes) {
-    hipError_t e = hipSuccess;
-    if (chunk_nv4 == 8) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_fwd<8>),
+int32_t interior_chunk_words() { return CHI; }
+
+hipError_t interior_set_lds_limit(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_fwd),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_bwd),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_bwd<8>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    } else {
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_fwd<4>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_bwd<4>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    }
     return e;
 }
 
 hipError_t launch_interior_fwd(const DevMesh& m, hipStream_t s) {
-    const size_t sh = interior_fwd_lds(m);
-    if (m.chunk_nv4 == 8)
-        hipLaunchKernelGGL(k_interior_fwd<8>, dim3(m.D), dim3(BLK), sh, s, solve_args(m));
-    else
-        hipLaunchKernelGGL(k_interior_fwd<4>, dim3(m.D), dim3(BLK), sh, s, solve_args(m));
+    hipLaunchKernelGGL(k_interior_fwd, dim3(m.D), dim3(BLKI), interior_fwd_lds(m), s, solve_args(m));
     return hipGetLastError();
 }
 
@@ -819,13 +811,8 @@ hipError_t launch_interface_phase(const DevMesh& m, const PhaseLaunch& ph, hipSt
 }
 
 hipError_t launch_interior_bwd(const DevMesh& m, hipStream_t s, bool apply, bool keep_delta) {
-    const size_t sh = interior_bwd_lds(m);
-    if (m.chunk_nv4 == 8)
-        hipLaunchKernelGGL(k_interior_bwd<8>, dim3(m.D), dim3(BLK), sh, s, solve_args(m),
-                           (int32_t)apply, (int32_t)keep_delta);
-    else
-        hipLaunchKernelGGL(k_interior_bwd<4>, dim3(m.D), dim3(BLK), sh, s, solve_args(m),
-                           (int32_t)apply, (int32_t)keep_delta);
+    hipLaunchKernelGGL(k_interior_bwd, dim3(m.D), dim3(BLKI), interior_bwd_lds(m), s, solve_args(m),
+                       (int32_t)apply, (int32_t)keep_delta);
     return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // FP64 factorization, solve programs) and runs the solve programs on the CPU
 // with the same semantics as the device kernels, so the plan can be checked
 // against a reference solve without a GPU.  Never part of the product path.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -26,7 +27,7 @@ void* vhp_build(const double* X, int nv, const int* tets, int nt, const double* 
                 int D, int refine, int leaf_max, int* rc, char* msg, int msglen) {
     Plan* P = new Plan();
     std::string m;
-    *rc = build_plan(X, nv, tets, nt, gs, gv, mass, pinned, g, dt, iters, D, refine, leaf_max, 4096, *P, m);
+    *rc = build_plan(X, nv, tets, nt, gs, gv, mass, pinned, g, dt, iters, D, refine, leaf_max, 12288, *P, m);
     std::snprintf(msg, msglen, "%s", m.c_str());
     if (*rc != 0) {
         delete P;
@@ -69,21 +70,29 @@ void vhp_solve(void* h, const double* rhs, double* d) {
             for (int ch = P.sub_fwd_ch[s]; ch < P.sub_fwd_ch[s + 1]; ++ch) {
                 const Chunk& K = P.chunks[ch];
                 const float* desc = P.ivals.data() + K.v0;
-                const float* dat = desc + 8 * K.ntasks;
+                const int dw = (K.kind == PULLSUM) ? 4 : 8;
+                const float* dat = desc + dw * K.ntasks;
                 for (int t = 0; t < K.ntasks; ++t) {
-                    const float* q = desc + 8 * t;
+                    const float* q = desc + dw * t;
                     if (K.kind == PULLSUM) {
                         double acc = 0.0;
                         for (int k = 0; k < word(q + 2); ++k) acc += C[word(dat + word(q + 1) + k)];
                         r[word(q)] -= acc;
                     } else {
-                        double acc = 0.0;
-                        const int off = word(q + 2), len = word(q + 3), xo = word(q + 4);
-                        for (int k = 0; k < len; ++k) acc += (double)dat[off + k] * r[xo + k];
-                        const int dest = word(q), idx = word(q + 1);
-                        if (dest == 0) z[idx] = acc;
-                        else if (dest == 1) C[idx] = (double)(float)acc;
-                        else CGF[idx] = (double)(float)acc;
+                        const int col0 = word(q), n = word(q + 1), m = word(q + 2), mi = word(q + 3),
+                                  ci0 = word(q + 4), cg0 = word(q + 5), off = word(q + 6), row0 = word(q + 7);
+                        for (int i = row0; i < std::min(row0 + 64, n + m); ++i) {
+                            double acc = 0.0;
+                            long co = 0;
+                            const int kmax = std::min(i + 1, n);
+                            for (int k = 0; k < kmax; ++k) {
+                                acc += (double)dat[off + co + (i - k)] * r[col0 + k];
+                                co += n + m - k;
+                            }
+                            if (i < n) z[col0 + i] = acc;
+                            else if (i < n + mi) C[ci0 + i - n] = (double)(float)acc;
+                            else CGF[cg0 + i - n - mi] = (double)(float)acc;
+                        }
                     }
                 }
             }
@@ -128,12 +137,16 @@ void vhp_solve(void* h, const double* rhs, double* d) {
                 const float* dat = desc + 8 * K.ntasks;
                 for (int t = 0; t < K.ntasks; ++t) {
                     const float* q = desc + 8 * t;
-                    const int out = word(q), off = word(q + 1), len1 = word(q + 2), xo = word(q + 3),
-                              len2 = word(q + 4), go = word(q + 5);
-                    double acc = 0.0;
-                    for (int k = 0; k < len1; ++k) acc += (double)dat[off + k] * z[xo + k];
-                    for (int k = 0; k < len2; ++k) acc += (double)dat[off + len1 + k] * dl[word(dat + go + k)];
-                    dl[out] = acc;
+                    const int col0 = word(q), n = word(q + 1), m = word(q + 2), off = word(q + 3),
+                              go = word(q + 4), kc0 = word(q + 5);
+                    const long tri = (long)n * (n + 1) / 2;
+                    for (int k = kc0; k < std::min(kc0 + 64, n); ++k) {
+                        double acc = 0.0;
+                        for (int i = k; i < n; ++i) acc += (double)dat[off + (long)i * (i + 1) / 2 + k] * z[col0 + i];
+                        for (int pp = 0; pp < m; ++pp)
+                            acc -= (double)dat[off + tri + (long)pp * n + k] * dl[word(dat + go + pp)];
+                        dl[col0 + k] = acc;
+                    }
                 }
             }
             for (int i = 0; i < nloc; ++i) Dc[base + i] = dl[i];
