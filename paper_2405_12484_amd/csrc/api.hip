@@ -413,9 +413,9 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     chk(upload(m, &d.tet, P.tet_soa));
     chk(upload(m, &d.ginv, P.ginv_soa));
     chk(upload(m, &d.w, P.w_soa));
-    chk(dalloc(m, &d.fout, (size_t)P.nt * 12));
+    chk(dalloc(m, &d.fout, (size_t)std::max(P.inc_ptr.back(), 1) * 3));
     chk(upload(m, &d.inc_ptr, P.inc_ptr));
-    chk(upload(m, &d.inc_slot, P.inc_slot));
+    chk(upload(m, &d.inc_pos, P.inc_pos));
     chk(dalloc(m, &d.r, (size_t)P.n_free * 3));
     chk(dalloc(m, &d.zf, (size_t)P.n_int * 3));
     chk(dalloc(m, &d.rg, (size_t)P.n_gamma * 3));

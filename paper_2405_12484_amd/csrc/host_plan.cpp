@@ -610,16 +610,14 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             if (a < P.n_free) P.inc_ptr[a + 1]++;
         }
     for (int32_t a = 0; a < P.n_free; ++a) P.inc_ptr[a + 1] += P.inc_ptr[a];
-    P.inc_slot.resize(P.inc_ptr[P.n_free]);
+    P.inc_pos.assign((size_t)4 * nt, -1);
     {
         std::vector<int32_t> fill(P.inc_ptr.begin(), P.inc_ptr.end() - 1);
         for (int32_t c = 0; c < 4; ++c)
             for (int32_t e = 0; e < nt; ++e) {
                 int32_t a = P.tet_soa[(size_t)c * nt + e];
-                if (a < P.n_free) P.inc_slot[fill[a]++] = c * nt + e;
+                if (a < P.n_free) P.inc_pos[(size_t)c * nt + e] = fill[a]++;
             }
-        for (int32_t a = 0; a < P.n_free; ++a)
-            std::sort(P.inc_slot.begin() + P.inc_ptr[a], P.inc_slot.begin() + P.inc_ptr[a + 1]);
     }
 
     // ---- FP64 matrix on free unknowns (internal order) ------------------------------

@@ -24,8 +24,8 @@ struct DevMesh {
     int32_t* tet = nullptr;         // [4][nt]
     float* ginv = nullptr;          // [9][nt]
     float* w = nullptr;             // [2][nt]
-    float* fout = nullptr;          // [3][4 nt] element forces per (corner, element) slot
-    int32_t *inc_ptr = nullptr, *inc_slot = nullptr;
+    float* fout = nullptr;          // [n_inc][3] corner forces in vertex-incidence order
+    int32_t *inc_ptr = nullptr, *inc_pos = nullptr;
     // solver
     double* r = nullptr;            // [n_free][3] residual
     float* zf = nullptr;            // [n_int][3] interior forward result

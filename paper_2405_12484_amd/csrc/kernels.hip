@@ -36,9 +36,9 @@ __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void jacobi_pair(float& app, float& aqq, float& apq, float& arp,
                                             float& arq, float* W, int p, int q) {
-    // tiny (possibly denormal) off-diagonals: no rotation; the hardware
-    // reciprocal of a denormal is inf and would turn tau into 0 * inf
-    if (!(fabsf(apq) > 1e-30f)) return;
+    // negligible off-diagonals (below 2^-24 of the diagonal pair): no rotation.
+    // This also keeps denormals out of the hardware reciprocal (inf, and 0 * inf).
+    if (!(fabsf(apq) > 5.96e-8f * (fabsf(app) + fabsf(aqq)) + 1e-30f)) return;
     float tau = (aqq - app) * frcp(2.0f * apq);
     float t = copysignf(frcp(fabsf(tau) + fsqrt(1.0f + tau * tau)), tau);
     float c = frsq(1.0f + t * t);
@@ -188,6 +188,7 @@ __global__ __launch_bounds__(BLK) void k_local(int32_t nt, const int32_t* __rest
                                                const float* __restrict__ ginv,
                                                const float* __restrict__ w,
                                                const float4* __restrict__ u,
+                                               const int32_t* __restrict__ inc_pos,
                                                float* __restrict__ fout, uint32_t* flags,
                                                float* dT, float* dsig, float* ds_out) {
     const int32_t e = blockIdx.x * BLK + threadIdx.x;
@@ -224,24 +225,34 @@ __global__ __launch_bounds__(BLK) void k_local(int32_t nt, const int32_t* __rest
         for (int j = 0; j < 3; ++j)
             T[i * 3 + j] = U[i * 3 + 0] * d0 * W[j * 3 + 0] + U[i * 3 + 1] * d1 * W[j * 3 + 1] +
                            U[i * 3 + 2] * d2 * W[j * 3 + 2];
-    // corner forces f_c = T gradN_c, gradN_c = row c-1 of Dm^{-1}, f_0 = -(f_1+f_2+f_3)
-    const int32_t nt4 = 4 * nt;
+    // corner forces f_c = T gradN_c, gradN_c = row c-1 of Dm^{-1}, f_0 = -(f_1+f_2+f_3),
+    // each written to its place in its vertex's incidence list (pinned: none)
     float s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
     for (int c = 1; c < 4; ++c) {
         float fx = T[0] * G[(c - 1) * 3 + 0] + T[1] * G[(c - 1) * 3 + 1] + T[2] * G[(c - 1) * 3 + 2];
         float fy = T[3] * G[(c - 1) * 3 + 0] + T[4] * G[(c - 1) * 3 + 1] + T[5] * G[(c - 1) * 3 + 2];
         float fz = T[6] * G[(c - 1) * 3 + 0] + T[7] * G[(c - 1) * 3 + 1] + T[8] * G[(c - 1) * 3 + 2];
-        fout[c * nt + e] = fx;
-        fout[nt4 + c * nt + e] = fy;
-        fout[2 * nt4 + c * nt + e] = fz;
+        const int32_t pos = inc_pos[c * nt + e];
+        if (pos >= 0) {
+            float* fp = fout + 3 * (size_t)pos;
+            fp[0] = fx;
+            fp[1] = fy;
+            fp[2] = fz;
+        }
         s0 += fx;
         s1 += fy;
         s2 += fz;
     }
-    fout[e] = -s0;
-    fout[nt4 + e] = -s1;
-    fout[2 * nt4 + e] = -s2;
+    {
+        const int32_t pos = inc_pos[e];
+        if (pos >= 0) {
+            float* fp = fout + 3 * (size_t)pos;
+            fp[0] = -s0;
+            fp[1] = -s1;
+            fp[2] = -s2;
+        }
+    }
     const bool inv = sg[2] <= 0.0f;
     if (__builtin_expect(oor || inv, 0)) {
         if (oor) atomicAdd(&flags[1], 1u);
@@ -291,40 +302,31 @@ __global__ __launch_bounds__(BLK) void k_predict(int32_t nv, int32_t n_free, dou
     u[i] = make_float4(du[0], du[1], du[2], 0.0f);
 }
 
-// r_a = m_a (y_a - x_a) / dt^2 + sum over incident (corner, element) slots of
-// the element forces.  Four lanes per vertex take every fourth slot and are
-// combined by a fixed butterfly, so the sum order is fixed (deterministic).
-__global__ __launch_bounds__(BLK) void k_residual(int32_t n_free, int32_t nt4,
-                                                  const int32_t* __restrict__ inc_ptr,
-                                                  const int32_t* __restrict__ inc_slot,
+// r_a = m_a (y_a - x_a) / dt^2 + the sum of the corner forces of its incident
+// elements, which the local step wrote contiguously per vertex (ascending
+// (corner, element) order, so the sum order is fixed and the result
+// deterministic).  Thread per vertex: its loads are one contiguous run.
+__global__ __launch_bounds__(BLK) void k_residual(int32_t n_free, const int32_t* __restrict__ inc_ptr,
                                                   const float* __restrict__ fout,
                                                   const double* __restrict__ mass,
                                                   const double* __restrict__ x,
                                                   const double* __restrict__ y, double inv_dt2,
                                                   double* __restrict__ r) {
-    const int32_t gt = blockIdx.x * BLK + threadIdx.x;
-    const int32_t a = gt >> 2, sub = gt & 3;
+    const int32_t a = blockIdx.x * BLK + threadIdx.x;
+    if (a >= n_free) return;
+    const int32_t j0 = inc_ptr[a], j1 = inc_ptr[a + 1];
+    const float* fp = fout + 3 * (size_t)j0;
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    if (a < n_free) {
-        const int32_t j1 = inc_ptr[a + 1];
-        for (int32_t j = inc_ptr[a] + sub; j < j1; j += 4) {
-            const int32_t sl = inc_slot[j];
-            fx += fout[sl];
-            fy += fout[nt4 + sl];
-            fz += fout[2 * nt4 + sl];
-        }
+#pragma unroll 4
+    for (int32_t j = 0; j < j1 - j0; ++j) {
+        fx += fp[3 * j];
+        fy += fp[3 * j + 1];
+        fz += fp[3 * j + 2];
     }
-    fx += __shfl_xor(fx, 1, 4);
-    fy += __shfl_xor(fy, 1, 4);
-    fz += __shfl_xor(fz, 1, 4);
-    fx += __shfl_xor(fx, 2, 4);
-    fy += __shfl_xor(fy, 2, 4);
-    fz += __shfl_xor(fz, 2, 4);
-    if (a < n_free && sub < 3) {
-        const double f = (sub == 0) ? (double)fx : (sub == 1) ? (double)fy : (double)fz;
-        const double m = mass[a] * inv_dt2;
-        r[3 * a + sub] = m * (y[3 * a + sub] - x[3 * a + sub]) + f;
-    }
+    const double m = mass[a] * inv_dt2;
+    r[3 * a + 0] = m * (y[3 * a + 0] - x[3 * a + 0]) + (double)fx;
+    r[3 * a + 1] = m * (y[3 * a + 1] - x[3 * a + 1]) + (double)fy;
+    r[3 * a + 2] = m * (y[3 * a + 2] - x[3 * a + 2]) + (double)fz;
 }
 
 // ---------------------------------------------------------------------------
@@ -762,16 +764,16 @@ hipError_t launch_predictor(const DevMesh& m, hipStream_t s) {
 hipError_t launch_local(const DevMesh& m, hipStream_t s, bool debug) {
     if (debug)
         hipLaunchKernelGGL(k_local<true>, dim3(nblk(m.nt)), dim3(BLK), 0, s, m.nt, m.tet, m.ginv, m.w,
-                           m.u, m.fout, m.flags, m.dbg_T, m.dbg_sig, m.dbg_s);
+                           m.u, m.inc_pos, m.fout, m.flags, m.dbg_T, m.dbg_sig, m.dbg_s);
     else
         hipLaunchKernelGGL(k_local<false>, dim3(nblk(m.nt)), dim3(BLK), 0, s, m.nt, m.tet, m.ginv,
-                           m.w, m.u, m.fout, m.flags, nullptr, nullptr, nullptr);
+                           m.w, m.u, m.inc_pos, m.fout, m.flags, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_residual(const DevMesh& m, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual, dim3(nblk(4 * (int64_t)m.n_free)), dim3(BLK), 0, s, m.n_free, 4 * m.nt,
-                       m.inc_ptr, m.inc_slot, m.fout, m.mass, m.x, m.y, 1.0 / (m.dt * m.dt), m.r);
+    hipLaunchKernelGGL(k_residual, dim3(nblk(m.n_free)), dim3(BLK), 0, s, m.n_free, m.inc_ptr, m.fout,
+                       m.mass, m.x, m.y, 1.0 / (m.dt * m.dt), m.r);
     return hipGetLastError();
 }
 

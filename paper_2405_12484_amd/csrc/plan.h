@@ -77,8 +77,11 @@ struct Plan {
     std::vector<float> ginv_soa;          // 9*nt, Dm^{-1} row-major per tet
     std::vector<float> w_soa;             // 2*nt  (V gs, V gv)
 
-    // scatter: free vertex -> incident (corner, element) slots c*nt + e
-    std::vector<int32_t> inc_ptr, inc_slot;
+    // scatter: the incidences (corner, element) of each free vertex are
+    // contiguous, in ascending (corner, element) order: inc_ptr [n_free+1];
+    // inc_pos [4][nt] is the position of corner c of element e in that list
+    // (-1 for a pinned vertex)
+    std::vector<int32_t> inc_ptr, inc_pos;
 
     // FP64 free-free matrix in internal order (CSR) for refinement residuals
     std::vector<int32_t> K_ptr, K_col;
