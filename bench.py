@@ -30,17 +30,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def local_bytes_per_launch(nt, nv, n_inc):
-    """Algorithmic bytes of one local-step launch: per tet 4 int32 vertex ids,
-    9 FP32 Dm^{-1}, 2 FP32 weights and 4 int32 incidence positions read; per
-    free corner 3 FP32 forces written; per vertex one float4 displacement read."""
-    return nt * (16 + 36 + 8 + 16) + n_inc * 12 + nv * 16
+def local_bytes_per_launch(nt, nv, n_part):
+    """Algorithmic bytes of one local-step launch: per tet a 64-byte record
+    (vertex ids, Dm^{-1}, weights) and 8 bytes of LDS positions; per vertex one
+    float4 displacement; per (workgroup, vertex) partial a packed int32 range
+    read and a float4 force sum written; the per-workgroup partial ranges."""
+    return nt * (64 + 8) + nv * 16 + n_part * (4 + 16) + ((nt + 255) // 256 + 1) * 4
 
 
-def residual_bytes_per_launch(n_inc, n_free):
-    """Residual gather: per incidence 3 FP32 forces read; per free vertex the
-    row pointer, FP64 mass, x and y read and the FP64 residual written."""
-    return n_inc * 12 + n_free * (4 + 8 + 24 + 24 + 24)
+def residual_bytes_per_launch(n_part, n_free):
+    """Residual: per free vertex the partial-list pointer, FP64 mass, x and y
+    read and the FP64 residual written; per partial an int32 index and a
+    float4 force sum read."""
+    return n_free * (4 + 8 + 24 + 24 + 24) + 4 + n_part * (4 + 16)
 
 
 def run(args):
@@ -89,9 +91,9 @@ def run(args):
     breakdown = {k: round(v[0] / 2.0, 4) for k, v in br.items()}   # ms per frame
 
     nt, nv, nf = p.nt, p.nv, info["n_free"]
-    n_inc = int((p.pinned[p.tets] == 0).sum())
-    lb = local_bytes_per_launch(nt, nv, n_inc)
-    rb = residual_bytes_per_launch(n_inc, nf)
+    n_part = info["n_partials"]
+    lb = local_bytes_per_launch(nt, nv, n_part)
+    rb = residual_bytes_per_launch(n_part, nf)
     loc_ms, loc_n = prof["local"]
     res_ms, res_n = prof["residual"]
     loc_gbs = lb / (loc_ms / loc_n * 1e-3) / 1e9

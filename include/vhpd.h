@@ -121,6 +121,7 @@ typedef struct vh_mesh_info {
     int64_t nnz_coarse;     /* stored entries of the FP64 interface factor blocks */
     size_t device_bytes;
     double prefactor_seconds;
+    int64_t n_partials;     /* per-(local-step workgroup, vertex) force partials */
 } vh_mesh_info;
 int vh_mesh_get_info(const vh_mesh* mesh, vh_mesh_info* info);
 

@@ -410,12 +410,19 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     chk(upload(m, &d.mass, P.mass_int));
     chk(upload(m, &d.perm, P.perm));
     chk(dalloc(m, &d.u, (size_t)P.nv));
-    chk(upload(m, &d.tet, P.tet_soa));
-    chk(upload(m, &d.ginv, P.ginv_soa));
-    chk(upload(m, &d.w, P.w_soa));
-    chk(dalloc(m, &d.fout, (size_t)std::max(P.inc_ptr.back(), 1) * 3));
-    chk(upload(m, &d.inc_ptr, P.inc_ptr));
-    chk(upload(m, &d.inc_pos, P.inc_pos));
+    {
+        std::vector<float4> tr((size_t)P.nt * 4);
+        std::memcpy(tr.data(), P.trec.data(), P.trec.size() * sizeof(float));
+        chk(upload(m, &d.trec, tr));
+        std::vector<uint2> lp((size_t)P.nt);
+        std::memcpy(lp.data(), P.lpos.data(), P.lpos.size() * sizeof(uint16_t));
+        chk(upload(m, &d.lpos, lp));
+    }
+    chk(upload(m, &d.blk_part, P.blk_part));
+    chk(upload(m, &d.part_pack, P.part_pack));
+    chk(dalloc(m, &d.part, (size_t)std::max<int32_t>(P.blk_part.back(), 1)));
+    chk(upload(m, &d.vpart_ptr, P.vpart_ptr));
+    chk(upload(m, &d.vpart, P.vpart));
     chk(dalloc(m, &d.r, (size_t)P.n_free * 3));
     chk(dalloc(m, &d.zf, (size_t)P.n_int * 3));
     chk(dalloc(m, &d.rg, (size_t)P.n_gamma * 3));
@@ -536,6 +543,7 @@ int vh_mesh_get_info(const vh_mesh* m, vh_mesh_info* info) {
     info->nnz_coarse = P.nnz_coarse;
     info->device_bytes = m->bytes;
     info->prefactor_seconds = P.seconds;
+    info->n_partials = P.blk_part.empty() ? 0 : P.blk_part.back();
     return VH_OK;
 }
 

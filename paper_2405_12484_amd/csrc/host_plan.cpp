@@ -38,6 +38,8 @@ constexpr int OK = 0, EINVAL_ = -1, ENOMEM_ = -2, ENOTSPD_ = -3;
 // Interior supernodes have at most this many columns, so that one supernode's
 // solve block fits an LDS chunk and a wave's lanes cover its columns.
 constexpr int32_t kMaxInteriorCols = 32;
+// tets per local-step workgroup (one thread per tet)
+constexpr int32_t kLocalBlock = 256;
 
 inline void tet_dm(const double* X, const int32_t* t, double Dm[9]) {
     // Dm[r][k] = X[t[k+1]][r] - X[t[0]][r]
@@ -582,8 +584,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
     std::stable_sort(P.elem_perm.begin(), P.elem_perm.end(),
                      [&](int32_t a, int32_t b) { return part[a] < part[b]; });
     P.tet_soa.resize((size_t)nt * 4);
-    P.ginv_soa.resize((size_t)nt * 9);
-    P.w_soa.resize((size_t)nt * 2);
+    P.trec.assign((size_t)nt * 16, 0.0f);
     std::vector<double> Vol(nt), Gd((size_t)nt * 9);
     for (int32_t e = 0; e < nt; ++e) {
         int32_t u = P.elem_perm[e];
@@ -593,31 +594,58 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         double det = det3(Dm);
         inv3(Dm, det, G);
         Vol[e] = det / 6.0;
-        for (int c = 0; c < 4; ++c) P.tet_soa[(size_t)c * nt + e] = P.iperm[t[c]];
+        float* rec = &P.trec[(size_t)e * 16];
+        for (int c = 0; c < 4; ++c) {
+            P.tet_soa[(size_t)c * nt + e] = P.iperm[t[c]];
+            int32_t id = P.iperm[t[c]];
+            std::memcpy(&rec[c], &id, 4);
+        }
         for (int k = 0; k < 9; ++k) {
-            P.ginv_soa[(size_t)k * nt + e] = (float)G[k];
+            rec[4 + k] = (float)G[k];
             Gd[(size_t)e * 9 + k] = G[k];
         }
-        P.w_soa[e] = (float)(Vol[e] * gamma_s[u]);
-        P.w_soa[(size_t)nt + e] = (float)(Vol[e] * gamma_v[u]);
+        rec[13] = (float)(Vol[e] * gamma_s[u]);
+        rec[14] = (float)(Vol[e] * gamma_v[u]);
     }
 
-    // ---- scatter incidence ---------------------------------------------------------
-    P.inc_ptr.assign(P.n_free + 1, 0);
-    for (int32_t c = 0; c < 4; ++c)
-        for (int32_t e = 0; e < nt; ++e) {
-            int32_t a = P.tet_soa[(size_t)c * nt + e];
-            if (a < P.n_free) P.inc_ptr[a + 1]++;
-        }
-    for (int32_t a = 0; a < P.n_free; ++a) P.inc_ptr[a + 1] += P.inc_ptr[a];
-    P.inc_pos.assign((size_t)4 * nt, -1);
+    // ---- scatter: per-block reduction of corner forces ----------------------------
     {
-        std::vector<int32_t> fill(P.inc_ptr.begin(), P.inc_ptr.end() - 1);
-        for (int32_t c = 0; c < 4; ++c)
-            for (int32_t e = 0; e < nt; ++e) {
-                int32_t a = P.tet_soa[(size_t)c * nt + e];
-                if (a < P.n_free) P.inc_pos[(size_t)c * nt + e] = fill[a]++;
+        const int32_t nblocks = (nt + kLocalBlock - 1) / kLocalBlock;
+        P.lpos.assign((size_t)4 * nt, 0xFFFF);
+        P.blk_part.assign(nblocks + 1, 0);
+        P.part_pack.clear();
+        std::vector<std::vector<int32_t>> vparts(P.n_free);
+        std::vector<std::pair<int32_t, int32_t>> inc;   // (vertex, local corner slot t*4 + c)
+        for (int32_t b = 0; b < nblocks; ++b) {
+            P.blk_part[b] = (int32_t)P.part_pack.size();
+            const int32_t e0 = b * kLocalBlock, e1 = std::min(nt, e0 + kLocalBlock);
+            inc.clear();
+            for (int32_t e = e0; e < e1; ++e)
+                for (int32_t c = 0; c < 4; ++c) {
+                    int32_t a = P.tet_soa[(size_t)c * nt + e];
+                    if (a < P.n_free) inc.push_back({a, (e - e0) * 4 + c});
+                }
+            std::sort(inc.begin(), inc.end());
+            for (size_t k = 0; k < inc.size();) {
+                size_t k1 = k;
+                while (k1 < inc.size() && inc[k1].first == inc[k].first) ++k1;
+                const int32_t pidx = (int32_t)P.part_pack.size();
+                P.part_pack.push_back(((int32_t)k << 16) | (int32_t)(k1 - k));
+                vparts[inc[k].first].push_back(pidx);
+                for (size_t q = k; q < k1; ++q) {
+                    const int32_t slot = inc[q].second;
+                    P.lpos[(size_t)(e0 + slot / 4) * 4 + slot % 4] = (uint16_t)q;
+                }
+                k = k1;
             }
+        }
+        P.blk_part[nblocks] = (int32_t)P.part_pack.size();
+        P.vpart_ptr.assign(P.n_free + 1, 0);
+        P.vpart.clear();
+        for (int32_t a = 0; a < P.n_free; ++a) {
+            P.vpart.insert(P.vpart.end(), vparts[a].begin(), vparts[a].end());
+            P.vpart_ptr[a + 1] = (int32_t)P.vpart.size();
+        }
     }
 
     // ---- FP64 matrix on free unknowns (internal order) ------------------------------

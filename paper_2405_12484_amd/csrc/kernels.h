@@ -21,11 +21,11 @@ struct DevMesh {
     int32_t* perm = nullptr;        // internal vertex -> user vertex
     float4* u = nullptr;            // float(x - X), w unused
     // elements
-    int32_t* tet = nullptr;         // [4][nt]
-    float* ginv = nullptr;          // [9][nt]
-    float* w = nullptr;             // [2][nt]
-    float* fout = nullptr;          // [n_inc][3] corner forces in vertex-incidence order
-    int32_t *inc_ptr = nullptr, *inc_pos = nullptr;
+    float4* trec = nullptr;         // [nt][4]: ids, Dm^{-1}, V gs, V gv
+    uint2* lpos = nullptr;          // [nt]: 4 x uint16 LDS positions of the corner forces
+    int32_t *blk_part = nullptr, *part_pack = nullptr;
+    float4* part = nullptr;         // per (block, vertex) partial force sums
+    int32_t *vpart_ptr = nullptr, *vpart = nullptr;
     // solver
     double* r = nullptr;            // [n_free][3] residual
     float* zf = nullptr;            // [n_int][3] interior forward result

@@ -2,9 +2,11 @@
 //
 //   k_predict   Sec. 7: inertial target y = x* + dt v* + dt^2 g, x^(0) = y
 //   k_local     Sec. 7.1 local step: per tet F, signed SVD, polar rotation R,
-//               volume projection (Eq. vol_pre), residual stress and forces
+//               volume projection (Eq. vol_pre), residual stress and corner
+//               forces, summed per vertex inside each workgroup (LDS, fixed order)
 //   k_residual  Sec. 7.1 global step right-hand side, as the residual
-//               r = b - K x^(k), gathered per vertex without atomics
+//               r = b - K x^(k): per vertex the sum of its workgroup partials,
+//               without atomics
 //   k_interior_fwd / k_coarse / k_interior_bwd
 //               Sec. 7.2 decomposed solve K d = r: interior triangular
 //               solves (one workgroup per subdomain, factor chunks and vectors
@@ -183,89 +185,107 @@ __device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_o
         }
 }
 
+// Local step, one thread per tet, 256 tets per workgroup.  Each tet reads
+// one 64-byte record (vertex ids, Dm^{-1}, weights), gathers the four vertex
+// displacements, and writes its four corner forces into LDS at positions that
+// group them by vertex; the workgroup then sums each of its vertices' runs in
+// a fixed order and stores one partial per (workgroup, vertex), coalesced.
+constexpr int LBLK = 256;
+
 template <bool DBG>
-__global__ __launch_bounds__(BLK) void k_local(int32_t nt, const int32_t* __restrict__ tet,
-                                               const float* __restrict__ ginv,
-                                               const float* __restrict__ w,
-                                               const float4* __restrict__ u,
-                                               const int32_t* __restrict__ inc_pos,
-                                               float* __restrict__ fout, uint32_t* flags,
-                                               float* dT, float* dsig, float* ds_out) {
-    const int32_t e = blockIdx.x * BLK + threadIdx.x;
-    if (e >= nt) return;
-    const int32_t i0 = tet[e], i1 = tet[nt + e], i2 = tet[2 * nt + e], i3 = tet[3 * nt + e];
-    const float4 u0 = u[i0], u1 = u[i1], u2 = u[i2], u3 = u[i3];
-    float G[9];
+__global__ __launch_bounds__(LBLK) void k_local(int32_t nt, const float4* __restrict__ trec,
+                                                const uint2* __restrict__ lpos,
+                                                const float4* __restrict__ u,
+                                                const int32_t* __restrict__ blk_part,
+                                                const int32_t* __restrict__ part_pack,
+                                                float4* __restrict__ part, uint32_t* flags,
+                                                float* dT, float* dsig, float* ds_out) {
+    __shared__ float LF[3][4 * LBLK];
+    const int32_t e = blockIdx.x * LBLK + threadIdx.x;
+    if (e < nt) {
+        const float4 r0 = trec[4 * (size_t)e], r1 = trec[4 * (size_t)e + 1], r2 = trec[4 * (size_t)e + 2],
+                     r3 = trec[4 * (size_t)e + 3];
+        const uint2 lp = lpos[e];
+        const int32_t i0 = __float_as_int(r0.x), i1 = __float_as_int(r0.y), i2 = __float_as_int(r0.z),
+                      i3 = __float_as_int(r0.w);
+        const float4 u0 = u[i0], u1 = u[i1], u2 = u[i2], u3 = u[i3];
+        const float G[9] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
+        const float ws = r3.y, wv = r3.z;
+        // displacement differences, columns k = corners 1..3
+        const float Du[3][3] = {{u1.x - u0.x, u2.x - u0.x, u3.x - u0.x},
+                                {u1.y - u0.y, u2.y - u0.y, u3.y - u0.y},
+                                {u1.z - u0.z, u2.z - u0.z, u3.z - u0.z}};
+        float F[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) G[k] = ginv[k * nt + e];
-    const float ws = w[e], wv = w[nt + e];
-    // displacement differences, columns k = corners 1..3
-    const float Du[3][3] = {{u1.x - u0.x, u2.x - u0.x, u3.x - u0.x},
-                            {u1.y - u0.y, u2.y - u0.y, u3.y - u0.y},
-                            {u1.z - u0.z, u2.z - u0.z, u3.z - u0.z}};
-    float F[9];
+        for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < 3; ++j)
+                F[r * 3 + j] = (r == j ? 1.0f : 0.0f) + Du[r][0] * G[0 * 3 + j] + Du[r][1] * G[1 * 3 + j] +
+                               Du[r][2] * G[2 * 3 + j];
+        float U[9], W[9], sg[3], dsv[3];
+        svd3(F, U, sg, W);
+        bool oor = false;
+        proj_sl3(sg, dsv, oor);
+        // residual stress T = U diag(ws (1 - sigma) + wv (s - sigma)) W^T = P - (ws + wv) F
+        const float d0 = ws * (1.0f - sg[0]) + wv * dsv[0];
+        const float d1 = ws * (1.0f - sg[1]) + wv * dsv[1];
+        const float d2 = ws * (1.0f - sg[2]) + wv * dsv[2];
+        float T[9];
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-            F[r * 3 + j] = (r == j ? 1.0f : 0.0f) + Du[r][0] * G[0 * 3 + j] + Du[r][1] * G[1 * 3 + j] +
-                           Du[r][2] * G[2 * 3 + j];
-    float U[9], W[9], sg[3], dsv[3];
-    svd3(F, U, sg, W);
-    bool oor = false;
-    proj_sl3(sg, dsv, oor);
-    // residual stress T = U diag(ws (1 - sigma) + wv (s - sigma)) W^T = P - (ws + wv) F
-    float d0 = ws * (1.0f - sg[0]) + wv * dsv[0];
-    float d1 = ws * (1.0f - sg[1]) + wv * dsv[1];
-    float d2 = ws * (1.0f - sg[2]) + wv * dsv[2];
-    float T[9];
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                T[i * 3 + j] = U[i * 3 + 0] * d0 * W[j * 3 + 0] + U[i * 3 + 1] * d1 * W[j * 3 + 1] +
+                               U[i * 3 + 2] * d2 * W[j * 3 + 2];
+        // corner forces f_c = T gradN_c, gradN_c = row c-1 of Dm^{-1}, f_0 = -(f_1+f_2+f_3)
+        const uint32_t pos[4] = {lp.x & 0xFFFFu, lp.x >> 16, lp.y & 0xFFFFu, lp.y >> 16};
+        float s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-            T[i * 3 + j] = U[i * 3 + 0] * d0 * W[j * 3 + 0] + U[i * 3 + 1] * d1 * W[j * 3 + 1] +
-                           U[i * 3 + 2] * d2 * W[j * 3 + 2];
-    // corner forces f_c = T gradN_c, gradN_c = row c-1 of Dm^{-1}, f_0 = -(f_1+f_2+f_3),
-    // each written to its place in its vertex's incidence list (pinned: none)
-    float s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-    for (int c = 1; c < 4; ++c) {
-        float fx = T[0] * G[(c - 1) * 3 + 0] + T[1] * G[(c - 1) * 3 + 1] + T[2] * G[(c - 1) * 3 + 2];
-        float fy = T[3] * G[(c - 1) * 3 + 0] + T[4] * G[(c - 1) * 3 + 1] + T[5] * G[(c - 1) * 3 + 2];
-        float fz = T[6] * G[(c - 1) * 3 + 0] + T[7] * G[(c - 1) * 3 + 1] + T[8] * G[(c - 1) * 3 + 2];
-        const int32_t pos = inc_pos[c * nt + e];
-        if (pos >= 0) {
-            float* fp = fout + 3 * (size_t)pos;
-            fp[0] = fx;
-            fp[1] = fy;
-            fp[2] = fz;
+        for (int c = 1; c < 4; ++c) {
+            const float fx = T[0] * G[(c - 1) * 3 + 0] + T[1] * G[(c - 1) * 3 + 1] + T[2] * G[(c - 1) * 3 + 2];
+            const float fy = T[3] * G[(c - 1) * 3 + 0] + T[4] * G[(c - 1) * 3 + 1] + T[5] * G[(c - 1) * 3 + 2];
+            const float fz = T[6] * G[(c - 1) * 3 + 0] + T[7] * G[(c - 1) * 3 + 1] + T[8] * G[(c - 1) * 3 + 2];
+            if (pos[c] != 0xFFFFu) {
+                LF[0][pos[c]] = fx;
+                LF[1][pos[c]] = fy;
+                LF[2][pos[c]] = fz;
+            }
+            s0 += fx;
+            s1 += fy;
+            s2 += fz;
         }
-        s0 += fx;
-        s1 += fy;
-        s2 += fz;
-    }
-    {
-        const int32_t pos = inc_pos[e];
-        if (pos >= 0) {
-            float* fp = fout + 3 * (size_t)pos;
-            fp[0] = -s0;
-            fp[1] = -s1;
-            fp[2] = -s2;
+        if (pos[0] != 0xFFFFu) {
+            LF[0][pos[0]] = -s0;
+            LF[1][pos[0]] = -s1;
+            LF[2][pos[0]] = -s2;
+        }
+        const bool inv = sg[2] <= 0.0f;
+        if (__builtin_expect(oor || inv, 0)) {
+            if (oor) atomicAdd(&flags[1], 1u);
+            if (inv) atomicAdd(&flags[2], 1u);
+        }
+        if (DBG) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) dT[(size_t)e * 9 + k] = T[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                dsig[(size_t)e * 3 + k] = sg[k];
+                ds_out[(size_t)e * 3 + k] = sg[k] + dsv[k];
+            }
         }
     }
-    const bool inv = sg[2] <= 0.0f;
-    if (__builtin_expect(oor || inv, 0)) {
-        if (oor) atomicAdd(&flags[1], 1u);
-        if (inv) atomicAdd(&flags[2], 1u);
-    }
-    if (DBG) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) dT[(size_t)e * 9 + k] = T[k];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            dsig[(size_t)e * 3 + k] = sg[k];
-            ds_out[(size_t)e * 3 + k] = sg[k] + dsv[k];
+    __syncthreads();
+    const int32_t p0 = blk_part[blockIdx.x], np = blk_part[blockIdx.x + 1] - p0;
+    for (int32_t k = threadIdx.x; k < np; k += LBLK) {
+        const int32_t pk = part_pack[p0 + k];
+        const int32_t st = pk >> 16, cnt = pk & 0xFFFF;
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        for (int32_t q = st; q < st + cnt; ++q) {
+            fx += LF[0][q];
+            fy += LF[1][q];
+            fz += LF[2][q];
         }
+        part[p0 + k] = make_float4(fx, fy, fz, 0.0f);
     }
 }
 
@@ -302,26 +322,24 @@ __global__ __launch_bounds__(BLK) void k_predict(int32_t nv, int32_t n_free, dou
     u[i] = make_float4(du[0], du[1], du[2], 0.0f);
 }
 
-// r_a = m_a (y_a - x_a) / dt^2 + the sum of the corner forces of its incident
-// elements, which the local step wrote contiguously per vertex (ascending
-// (corner, element) order, so the sum order is fixed and the result
-// deterministic).  Thread per vertex: its loads are one contiguous run.
-__global__ __launch_bounds__(BLK) void k_residual(int32_t n_free, const int32_t* __restrict__ inc_ptr,
-                                                  const float* __restrict__ fout,
+// r_a = m_a (y_a - x_a) / dt^2 + the sum of the vertex's per-workgroup force
+// partials (ascending workgroup order, so the result is deterministic).
+__global__ __launch_bounds__(BLK) void k_residual(int32_t n_free, const int32_t* __restrict__ vpart_ptr,
+                                                  const int32_t* __restrict__ vpart,
+                                                  const float4* __restrict__ part,
                                                   const double* __restrict__ mass,
                                                   const double* __restrict__ x,
                                                   const double* __restrict__ y, double inv_dt2,
                                                   double* __restrict__ r) {
     const int32_t a = blockIdx.x * BLK + threadIdx.x;
     if (a >= n_free) return;
-    const int32_t j0 = inc_ptr[a], j1 = inc_ptr[a + 1];
-    const float* fp = fout + 3 * (size_t)j0;
+    const int32_t j0 = vpart_ptr[a], j1 = vpart_ptr[a + 1];
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-#pragma unroll 4
-    for (int32_t j = 0; j < j1 - j0; ++j) {
-        fx += fp[3 * j];
-        fy += fp[3 * j + 1];
-        fz += fp[3 * j + 2];
+    for (int32_t j = j0; j < j1; ++j) {
+        const float4 f = part[vpart[j]];
+        fx += f.x;
+        fy += f.y;
+        fz += f.z;
     }
     const double m = mass[a] * inv_dt2;
     r[3 * a + 0] = m * (y[3 * a + 0] - x[3 * a + 0]) + (double)fx;
@@ -762,18 +780,19 @@ hipError_t launch_predictor(const DevMesh& m, hipStream_t s) {
 }
 
 hipError_t launch_local(const DevMesh& m, hipStream_t s, bool debug) {
+    const dim3 g((m.nt + LBLK - 1) / LBLK);
     if (debug)
-        hipLaunchKernelGGL(k_local<true>, dim3(nblk(m.nt)), dim3(BLK), 0, s, m.nt, m.tet, m.ginv, m.w,
-                           m.u, m.inc_pos, m.fout, m.flags, m.dbg_T, m.dbg_sig, m.dbg_s);
+        hipLaunchKernelGGL(k_local<true>, g, dim3(LBLK), 0, s, m.nt, m.trec, m.lpos, m.u, m.blk_part,
+                           m.part_pack, m.part, m.flags, m.dbg_T, m.dbg_sig, m.dbg_s);
     else
-        hipLaunchKernelGGL(k_local<false>, dim3(nblk(m.nt)), dim3(BLK), 0, s, m.nt, m.tet, m.ginv,
-                           m.w, m.u, m.inc_pos, m.fout, m.flags, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL(k_local<false>, g, dim3(LBLK), 0, s, m.nt, m.trec, m.lpos, m.u, m.blk_part,
+                           m.part_pack, m.part, m.flags, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_residual(const DevMesh& m, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual, dim3(nblk(m.n_free)), dim3(BLK), 0, s, m.n_free, m.inc_ptr, m.fout,
-                       m.mass, m.x, m.y, 1.0 / (m.dt * m.dt), m.r);
+    hipLaunchKernelGGL(k_residual, dim3(nblk(m.n_free)), dim3(BLK), 0, s, m.n_free, m.vpart_ptr,
+                       m.vpart, m.part, m.mass, m.x, m.y, 1.0 / (m.dt * m.dt), m.r);
     return hipGetLastError();
 }
 

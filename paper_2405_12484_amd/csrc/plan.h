@@ -71,17 +71,19 @@ struct Plan {
     std::vector<double> mass_int;         // nv
     std::vector<uint8_t> pinned_user;     // nv, user order
 
-    // elements in internal order (sorted by subdomain), SoA
+    // elements in internal order (sorted by subdomain)
     std::vector<int32_t> elem_perm;       // internal element -> user element
-    std::vector<int32_t> tet_soa;         // 4*nt internal vertex ids
-    std::vector<float> ginv_soa;          // 9*nt, Dm^{-1} row-major per tet
-    std::vector<float> w_soa;             // 2*nt  (V gs, V gv)
-
-    // scatter: the incidences (corner, element) of each free vertex are
-    // contiguous, in ascending (corner, element) order: inc_ptr [n_free+1];
-    // inc_pos [4][nt] is the position of corner c of element e in that list
-    // (-1 for a pinned vertex)
-    std::vector<int32_t> inc_ptr, inc_pos;
+    std::vector<int32_t> tet_soa;         // 4*nt internal vertex ids (host use)
+    // one 64-byte record per tet: 4 vertex ids, Dm^{-1} (9, row-major), V gs, V gv, 0
+    std::vector<float> trec;              // 16*nt 32-bit words
+    // scatter, reduced per block of kLocalBlock tets: each corner force goes to
+    // the LDS position lpos (grouped by vertex, ascending (tet, corner)); each
+    // of the block's free vertices sums its run into one partial; partial p
+    // covers LDS positions [start, start + count) packed as start << 16 | count.
+    std::vector<uint16_t> lpos;           // [nt][4], 0xFFFF for a pinned corner
+    std::vector<int32_t> blk_part;        // nblocks+1: partial index ranges per block
+    std::vector<int32_t> part_pack;       // per partial: start << 16 | count
+    std::vector<int32_t> vpart_ptr, vpart;  // per free vertex: its partials (ascending)
 
     // FP64 free-free matrix in internal order (CSR) for refinement residuals
     std::vector<int32_t> K_ptr, K_col;

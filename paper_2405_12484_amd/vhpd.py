@@ -32,7 +32,8 @@ class MeshInfo(ctypes.Structure):
                 ("n_subdomains", ctypes.c_int32), ("n_supernodes", ctypes.c_int32),
                 ("n_coarse_levels", ctypes.c_int32), ("max_interior_phases", ctypes.c_int32),
                 ("nnz_interior", ctypes.c_int64), ("nnz_coarse", ctypes.c_int64),
-                ("device_bytes", ctypes.c_size_t), ("prefactor_seconds", ctypes.c_double)]
+                ("device_bytes", ctypes.c_size_t), ("prefactor_seconds", ctypes.c_double),
+                ("n_partials", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
