@@ -45,6 +45,29 @@ def residual_bytes_per_launch(n_part, n_free):
     return n_free * (4 + 8 + 24 + 24 + 24) + 4 + n_part * (4 + 16)
 
 
+def copy_calibration(torch, mb=512, reps=5):
+    """A plain device copy of `mb` MB (torch's copy kernel): achieved GB/s,
+    counting read + write bytes.  Also the reference dispatch for scaling the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    n = mb * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    del a, b
+    return {"bytes_per_copy": 2 * n * 4, "avg_us": round(ms * 1e3, 2), "GBps": round(gbs, 1)}
+
+
 def run(args):
     import torch
 
@@ -54,6 +77,7 @@ def run(args):
     p = synth.problem_by_name(args.workload)
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    copy_cal = copy_calibration(torch)
     stream = torch.cuda.current_stream(dev)
     ctx = vhpd.Context(0)
     mesh = vhpd.Mesh(ctx, p.X, p.tets)
@@ -138,6 +162,7 @@ def run(args):
         "roofline": roofline,
         "scatter_roofline": scatter,
         "breakdown_ms_per_frame": breakdown,
+        "hbm_copy_calibration": copy_cal,
         "prefactor_s": round(prefactor_s, 3),
     }
 
