@@ -30,21 +30,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def local_bytes_per_launch(nt, nv, n_part):
-    """Algorithmic bytes of one local-step launch: per tet a 64-byte record
-    (vertex ids, Dm^{-1}, weights) and 8 bytes of LDS positions; per vertex one
-    float4 displacement; per (workgroup, vertex) partial a packed int32 range
-    read and a float4 force sum written; the per-workgroup partial ranges."""
-    return nt * (64 + 8) + nv * 16 + n_part * (4 + 16) + ((nt + 255) // 256 + 1) * 4
-
-
-def residual_bytes_per_launch(n_part, n_free):
-    """Residual: per free vertex the partial-list pointer, FP64 mass, x and y
-    read and the FP64 residual written; per partial an int32 index and a
-    float4 force sum read."""
-    return n_free * (4 + 8 + 24 + 24 + 24) + 4 + n_part * (4 + 16)
-
-
 def copy_calibration(torch, mb=512, reps=5):
     """A plain device copy of `mb` MB (torch's copy kernel): achieved GB/s,
     counting read + write bytes.  Also the reference dispatch for scaling the
@@ -94,8 +79,7 @@ def run(args):
     mesh.step(max(0, args.warmup - 1), stream)
     torch.cuda.synchronize()
 
-    # timed region: K frames; HIP events around the local-step and residual launches
-    mesh.profile(["local", "residual"])
+    # timed region: K frames
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -103,11 +87,50 @@ def run(args):
     mesh.step(args.steps, stream)
     ev1.record(stream)
     torch.cuda.synchronize()
-    ms_total = ev0.elapsed_time(ev1)
-    prof = mesh.profile_read()
-    ms_per_frame = ms_total / args.steps
+    ms_per_frame = ev0.elapsed_time(ev1) / args.steps
 
-    # breakdown (separate, untimed pass with every class timed)
+    # per-kernel-class duration: HIP events around `reps` back-to-back launches of
+    # that class on the bench stream, at the state the timed frames left
+    reps = {"local": 40, "residual": 40, "interior_fwd": 10, "interface": 10, "interior_bwd": 10}
+    kt = {}
+    for k, n in reps.items():
+        mesh.time_kernel(k, 2, stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        mesh.time_kernel(k, n, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kt[k] = e0.elapsed_time(e1) / n * 1e3           # us per launch (per solve for the interface)
+    info = mesh.info()
+    nbytes = {"local": info["bytes_local"], "residual": info["bytes_residual"],
+              "interior_fwd": info["bytes_interior_fwd"], "interface": info["bytes_interface"],
+              "interior_bwd": info["bytes_interior_bwd"]}
+    kname = {"local": "k_local", "residual": "k_residual", "interior_fwd": "k_interior_fwd",
+             "interface": "k_coarse", "interior_bwd": "k_interior_bwd"}
+    per_frame_us = {k: kt[k] * p.pd_iters * (1 + args.refine) if k != "local" and k != "residual"
+                    else kt[k] * p.pd_iters for k in kt}
+    rooflines = {}
+    for k in kt:
+        launches = info["interface_launches"] if k == "interface" else 1
+        gbs = nbytes[k] / (kt[k] * 1e-6) / 1e9
+        rooflines[k] = {"kernel": kname[k], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                        "bytes_per_launch": int(nbytes[k] / launches),
+                        "avg_launch_us": round(kt[k] / launches, 3),
+                        "us_per_frame": round(per_frame_us[k], 1)}
+    dominant = max(per_frame_us, key=per_frame_us.get)
+    roofline = dict(rooflines[dominant])
+    local_scatter = {
+        "kernels": "k_local + k_residual",
+        "bytes_per_iteration": nbytes["local"] + nbytes["residual"],
+        "us_per_iteration": round(kt["local"] + kt["residual"], 3),
+        "achieved": round((nbytes["local"] + nbytes["residual"]) / ((kt["local"] + kt["residual"]) * 1e-6) / 1e9, 1),
+    }
+    local_scatter["frac"] = round(local_scatter["achieved"] / HBM_PEAK_GBS, 4)
+
+    # breakdown (separate, untimed pass with every class timed by events around its launch groups)
     mesh.profile(list(vhpd.Mesh.PROFILE_CLASSES))
     mesh.step(2, stream)
     br = mesh.profile_read()
@@ -115,32 +138,6 @@ def run(args):
     breakdown = {k: round(v[0] / 2.0, 4) for k, v in br.items()}   # ms per frame
 
     nt, nv, nf = p.nt, p.nv, info["n_free"]
-    n_part = info["n_partials"]
-    lb = local_bytes_per_launch(nt, nv, n_part)
-    rb = residual_bytes_per_launch(n_part, nf)
-    loc_ms, loc_n = prof["local"]
-    res_ms, res_n = prof["residual"]
-    loc_gbs = lb / (loc_ms / loc_n * 1e-3) / 1e9
-    res_gbs = rb / (res_ms / res_n * 1e-3) / 1e9
-    roofline = {
-        "kernel": "k_local",
-        "bound": "hbm",
-        "achieved": round(loc_gbs, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(loc_gbs / HBM_PEAK_GBS, 4),
-        "traffic": None,
-        "bytes_per_launch": lb,
-        "avg_launch_us": round(loc_ms / loc_n * 1e3, 3),
-    }
-    scatter = {
-        "kernel": "k_residual",
-        "achieved": round(res_gbs, 1),
-        "frac": round(res_gbs / HBM_PEAK_GBS, 4),
-        "bytes_per_launch": rb,
-        "avg_launch_us": round(res_ms / res_n * 1e3, 3),
-    }
-
     out = {
         "metric": "ms/frame on 390K-tet PD; batched frames/s + p99 step latency vs plain",
         "value": round(ms_per_frame, 4),
@@ -160,7 +157,8 @@ def run(args):
                    "free_verts": nf, "interface_verts": info["n_interface"], "subdomains": p.n_subdomains,
                    "dt": p.dt, "pd_iters": p.pd_iters, "refine_steps": args.refine},
         "roofline": roofline,
-        "scatter_roofline": scatter,
+        "local_plus_scatter": local_scatter,
+        "rooflines": rooflines,
         "breakdown_ms_per_frame": breakdown,
         "hbm_copy_calibration": copy_cal,
         "prefactor_s": round(prefactor_s, 3),

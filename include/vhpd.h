@@ -122,6 +122,11 @@ typedef struct vh_mesh_info {
     size_t device_bytes;
     double prefactor_seconds;
     int64_t n_partials;     /* per-(local-step workgroup, vertex) force partials */
+    /* algorithmic bytes moved by one launch of each kernel class (the
+     * interface: one whole solve, all its launches): data each kernel must
+     * read or write once, without re-reads */
+    int64_t bytes_local, bytes_residual, bytes_interior_fwd, bytes_interface, bytes_interior_bwd;
+    int32_t interface_launches;   /* kernel launches per interface solve */
 } vh_mesh_info;
 int vh_mesh_get_info(const vh_mesh* mesh, vh_mesh_info* info);
 
@@ -136,6 +141,13 @@ int vh_mesh_get_info(const vh_mesh* mesh, vh_mesh_info* info);
 #define VH_PROFILE_CLASSES 8
 int vh_mesh_profile(vh_mesh* mesh, uint32_t class_mask);
 int vh_mesh_profile_read(vh_mesh* mesh, double* ms, int64_t* launches);
+
+/* Launch one kernel class (1 local step, 2 residual gather, 3 interior
+ * forward, 4 all interface phases of one solve, 5 interior backward without
+ * update) `reps` times back to back on `stream`, on the mesh's current data,
+ * for timing with events around the call.  The local step and residual
+ * overwrite only their outputs; the solve kernels only their work vectors. */
+int vh_mesh_time_kernel(vh_mesh* mesh, int32_t kernel_class, int32_t reps, void* stream);
 
 /* ---- Entry points that run one part of the step, for testing each kernel
  * against a reference.  All arrays are host arrays in user vertex order. ---- */

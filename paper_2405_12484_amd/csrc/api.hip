@@ -544,6 +544,23 @@ int vh_mesh_get_info(const vh_mesh* m, vh_mesh_info* info) {
     info->device_bytes = m->bytes;
     info->prefactor_seconds = P.seconds;
     info->n_partials = P.blk_part.empty() ? 0 : P.blk_part.back();
+    const int64_t npart = info->n_partials, nblk = (int64_t)P.blk_part.size();
+    info->bytes_local = (int64_t)P.nt * (64 + 8) + (int64_t)P.nv * 16 + npart * (4 + 16) + nblk * 4;
+    info->bytes_residual = (int64_t)P.n_free * (4 + 8 + 24 + 24 + 24) + 4 + npart * (4 + 16);
+    int64_t fw = 0, bw = 0;
+    for (int32_t c = P.sub_fwd_ch[0]; c < P.sub_fwd_ch[P.D]; ++c) fw += 4 * (int64_t)P.chunks[c].nv + 32;
+    for (int32_t c = P.sub_bwd_ch[0]; c < P.sub_bwd_ch[P.D]; ++c) bw += 4 * (int64_t)P.chunks[c].nv + 32;
+    // forward: chunks, r in, z out, interface contributions out
+    info->bytes_interior_fwd = fw + (int64_t)P.n_int * (24 + 12) + (int64_t)P.n_cgf * 12;
+    // backward: chunks, z in, boundary values in, x/X in, x/u out (interior and interface rows)
+    info->bytes_interior_bwd = bw + (int64_t)P.n_int * 12 + (int64_t)P.bnd.size() * 24 +
+                               (int64_t)P.n_free * (24 + 24 + 24 + 16) + (int64_t)P.n_gamma * 24;
+    // interface: every FP64 value once (forward rows, backward columns), task
+    // descriptors, slot and gather lists, contributions in/out, r/z/d vectors
+    info->bytes_interface = 8 * (int64_t)P.dvals.size() + 32 * (int64_t)P.ctasks.size() +
+                            4 * (int64_t)(P.cslots.size() + P.cgidx.size()) + (int64_t)P.n_cgf * 12 +
+                            (int64_t)P.n_cgd * 24 * 2 + (int64_t)P.n_gamma * 24 * 5;
+    info->interface_launches = (int32_t)(P.cfwd.size() + P.cbwd.size());
     return VH_OK;
 }
 
@@ -605,6 +622,27 @@ int vh_debug_solve(vh_mesh* m, const double* rhs, double* out) {
     VH_TRY(solve(m, nullptr, false, true));
     VH_HIP(hipDeviceSynchronize());
     return get_user(m, d.delta, out, d.n_free, nullptr);
+}
+
+int vh_mesh_time_kernel(vh_mesh* m, int32_t kernel_class, int32_t reps, void* stream) {
+    VH_TRY(check_ready(m));
+    if (reps < 1) return fail(VH_EINVAL, "reps must be >= 1");
+    VH_TRY(set_device(m));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int32_t r = 0; r < reps; ++r) {
+        switch (kernel_class) {
+            case 1: VH_HIP(vh::launch_local(m->dm, s, false)); break;
+            case 2: VH_HIP(vh::launch_residual(m->dm, s)); break;
+            case 3: VH_HIP(vh::launch_interior_fwd(m->dm, s)); break;
+            case 4:
+                for (const auto& ph : m->fwd) VH_HIP(vh::launch_interface_phase(m->dm, ph, s));
+                for (const auto& ph : m->bwd) VH_HIP(vh::launch_interface_phase(m->dm, ph, s));
+                break;
+            case 5: VH_HIP(vh::launch_interior_bwd(m->dm, s, false, false)); break;
+            default: return fail(VH_EINVAL, "kernel_class must be 1..5");
+        }
+    }
+    return VH_OK;
 }
 
 int vh_mesh_profile(vh_mesh* m, uint32_t class_mask) {

@@ -588,7 +588,8 @@ __global__ __launch_bounds__(BLK) void k_coarse(SolveArgs a, int32_t kind, int32
 }
 
 // Interior backward solve and update.  Per supernode level, top down: BGEMV
-// (lane per column k of the row-major block [Ti; B Ti]):
+// (lanes per column k of the row-major block [Ti; B Ti], the rows split among
+// them and combined by a fixed butterfly):
 // d_k = sum_{i>=k} Ti[i][k] z_i - sum_p (B Ti)[p][k] d[rows_p], with the
 // subdomain's boundary values of the interface solution staged in LDS after
 // its interior rows, so every gather hits LDS.
@@ -635,31 +636,44 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(SolveArgs a, int32_t appl
         for (int32_t t = wave; t < K.ntasks; t += NW) {
             const int32_t* q = desc + 8 * t;
             const int32_t col0 = q[0], n = q[1], m = q[2];
-            const int32_t k = q[5] + lane;
-            if (k >= n) continue;
+            // lanes per column: the wave's 64 lanes are split into `lpc` groups of
+            // `ncp` columns (ncp >= n, a power of two); group j takes rows j, j+lpc, ...
+            const int32_t ncp = (n <= 8) ? 8 : (n <= 16) ? 16 : (n <= 32) ? 32 : 64;
+            const int32_t lpc = 64 / ncp;
+            const int32_t k = q[5] + (lane & (ncp - 1)), j = lane / ncp;
+            const bool act = k < n;
             const float* w = dat + q[3] + k;
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-            for (int32_t i = k; i < n; ++i) {
-                const float v = w[i * (i + 1) / 2];
-                const float* xp = Z + 3 * (col0 + i);
-                s0 += v * xp[0];
-                s1 += v * xp[1];
-                s2 += v * xp[2];
+            if (act) {
+                for (int32_t i = k + j; i < n; i += lpc) {
+                    const float v = w[i * (i + 1) / 2];
+                    const float* xp = Z + 3 * (col0 + i);
+                    s0 += v * xp[0];
+                    s1 += v * xp[1];
+                    s2 += v * xp[2];
+                }
+                const float* wb = w + n * (n + 1) / 2;
+                const int32_t* g = idat + q[4];
+#pragma unroll 2
+                for (int32_t p = j; p < m; p += lpc) {
+                    const float v = wb[p * n];
+                    const float* xp = DL + 3 * g[p];
+                    s0 -= v * xp[0];
+                    s1 -= v * xp[1];
+                    s2 -= v * xp[2];
+                }
             }
-            const float* wb = w + n * (n + 1) / 2;
-            const int32_t* g = idat + q[4];
-#pragma unroll 4
-            for (int32_t p = 0; p < m; ++p) {
-                const float v = wb[p * n];
-                const float* xp = DL + 3 * g[p];
-                s0 -= v * xp[0];
-                s1 -= v * xp[1];
-                s2 -= v * xp[2];
+            for (int32_t off = ncp; off < 64; off <<= 1) {
+                s0 += __shfl_xor(s0, off, 64);
+                s1 += __shfl_xor(s1, off, 64);
+                s2 += __shfl_xor(s2, off, 64);
             }
-            float* op = DL + 3 * (col0 + k);
-            op[0] = s0;
-            op[1] = s1;
-            op[2] = s2;
+            if (act && j == 0) {
+                float* op = DL + 3 * (col0 + k);
+                op[0] = s0;
+                op[1] = s1;
+                op[2] = s2;
+            }
         }
         if (more) chunk_store(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
         __syncthreads();

@@ -33,7 +33,10 @@ class MeshInfo(ctypes.Structure):
                 ("n_coarse_levels", ctypes.c_int32), ("max_interior_phases", ctypes.c_int32),
                 ("nnz_interior", ctypes.c_int64), ("nnz_coarse", ctypes.c_int64),
                 ("device_bytes", ctypes.c_size_t), ("prefactor_seconds", ctypes.c_double),
-                ("n_partials", ctypes.c_int64)]
+                ("n_partials", ctypes.c_int64),
+                ("bytes_local", ctypes.c_int64), ("bytes_residual", ctypes.c_int64),
+                ("bytes_interior_fwd", ctypes.c_int64), ("bytes_interface", ctypes.c_int64),
+                ("bytes_interior_bwd", ctypes.c_int64), ("interface_launches", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -54,6 +57,7 @@ SIGNATURES = {
     "vh_mesh_read_state_device": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_mesh_write_state_device": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_mesh_get_info": (ctypes.c_int, [_vp, _P(MeshInfo)]),
+    "vh_mesh_time_kernel": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
     "vh_mesh_profile": (ctypes.c_int, [_vp, ctypes.c_uint32]),
     "vh_mesh_profile_read": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_debug_local_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -213,6 +217,11 @@ class Mesh:
         for c in classes:
             mask |= 1 << self.PROFILE_CLASSES.index(c)
         _check(_lib.vh_mesh_profile(self.h, mask))
+
+    def time_kernel(self, kernel_class: str, reps: int, stream=None):
+        """Launch one kernel class `reps` times back to back (for event timing)."""
+        idx = {"local": 1, "residual": 2, "interior_fwd": 3, "interface": 4, "interior_bwd": 5}[kernel_class]
+        _check(_lib.vh_mesh_time_kernel(self.h, idx, int(reps), _stream_ptr(stream)))
 
     def profile_read(self):
         """{class: (milliseconds, timed launch groups)} since profile() or the last read."""
