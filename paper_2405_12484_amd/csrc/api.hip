@@ -37,6 +37,28 @@ int fail(int code, const std::string& msg) {
 
 }  // namespace
 
+namespace {
+
+struct CoarseLaunch {
+    vh::LaunchRef ref;
+    int32_t kind = 0, group = 16;
+};
+
+// The launches of one frame over a set of garments (one mesh, or a batch).
+struct LaunchSet {
+    vh::DevMesh* G = nullptr;       // device [ng]
+    int32_t* tables = nullptr;      // device launch tables
+    int32_t* active = nullptr;      // device [ng]
+    int32_t ng = 0;
+    vh::LaunchRef predict, local, residual, ifwd, ibwd, refine, velocity;
+    std::vector<CoarseLaunch> cfwd, cbwd;
+    size_t lds_fwd = 0, lds_bwd = 0;
+    int32_t pd_iters = 10, refine_steps = 0;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
 struct vh_ctx {
     int device = 0;
     size_t budget = 0;
@@ -59,7 +81,7 @@ struct vh_mesh {
     vh::DevMesh dm;
     std::vector<void*> allocs;
     size_t bytes = 0;
-    std::vector<vh::PhaseLaunch> fwd, bwd;
+    LaunchSet ls;                   // this mesh's own frame (one garment)
     int32_t refine = 0;
     std::vector<double> stage;   // host staging, nv*3
     // optional per-kernel-class timing with HIP events on the step's stream
@@ -74,6 +96,8 @@ struct vh_mesh {
 };
 
 namespace {
+
+void free_launch_set(LaunchSet& L);
 
 void release_events(vh_mesh* m) {
     for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
@@ -100,7 +124,7 @@ struct ProfScope {
         return m->ev_pool[m->ev_used++];
     }
     ProfScope(vh_mesh* m_, hipStream_t s_, int cls_) : m(m_), s(s_), cls(cls_) {
-        on = (m->prof_mask >> cls) & 1u;
+        on = m && ((m->prof_mask >> cls) & 1u);
         if (!on) return;
         start = m->ev_used;
         hipEvent_t e = next();
@@ -118,6 +142,8 @@ void free_device(vh_mesh* m) {
         (void)hipGraphExecDestroy(m->gexec);
         m->gexec = nullptr;
     }
+    if (m->ctx) m->ctx->in_use -= std::min(m->ctx->in_use, m->ls.bytes);
+    free_launch_set(m->ls);
     for (void* p : m->allocs) (void)hipFree(p);
     m->allocs.clear();
     if (m->ctx) m->ctx->in_use -= std::min(m->ctx->in_use, m->bytes);
@@ -149,60 +175,173 @@ int upload(vh_mesh* m, T** p, const std::vector<T>& v) {
     return VH_OK;
 }
 
+void free_launch_set(LaunchSet& L) {
+    if (L.G) (void)hipFree(L.G);
+    if (L.tables) (void)hipFree(L.tables);
+    if (L.active) (void)hipFree(L.active);
+    L = LaunchSet();
+}
+
+// Build the launch tables of one frame over `members` (all prefactored, with
+// equal pd_iters and refine steps).  Device memory is charged to ctx.
+int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSet& L) {
+    free_launch_set(L);
+    const int32_t ng = (int32_t)members.size();
+    if (ng == 0) return fail(VH_EINVAL, "empty launch set");
+    L.ng = ng;
+    L.pd_iters = members[0]->plan.pd_iters;
+    L.refine_steps = members[0]->refine;
+    for (vh_mesh* m : members)
+        if (m->plan.pd_iters != L.pd_iters || m->refine != L.refine_steps)
+            return fail(VH_EINVAL, "garments in one batch need equal pd_iters and refine steps");
+    std::vector<int32_t> tab;
+    std::vector<std::pair<vh::LaunchRef*, size_t>> fix;   // ref -> table offset
+    // per-garment blocks and parameters -> one table
+    auto add = [&](vh::LaunchRef* ref, const std::vector<int32_t>& gids, const std::vector<int32_t>& nb,
+                   const std::vector<int32_t>& x0, const std::vector<int32_t>& x1) {
+        const size_t off = tab.size();
+        const int32_t n = (int32_t)gids.size();
+        tab.push_back(n);
+        int32_t acc = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            tab.push_back(acc);
+            acc += nb[i];
+        }
+        tab.push_back(acc);
+        for (int32_t v : gids) tab.push_back(v);
+        for (int32_t v : x0) tab.push_back(v);
+        for (int32_t v : x1) tab.push_back(v);
+        ref->nblocks = acc;
+        fix.push_back({ref, off});
+    };
+    std::vector<int32_t> all(ng), zero(ng, 0), nb(ng);
+    for (int32_t i = 0; i < ng; ++i) all[i] = i;
+    auto per = [&](auto f) {
+        for (int32_t i = 0; i < ng; ++i) nb[i] = f(members[i]->dm);
+        return nb;
+    };
+    add(&L.predict, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.nv); }), zero, zero);
+    add(&L.local, all, per([](const vh::DevMesh& d) { return vh::blocks_tets(d.nt); }), zero, zero);
+    add(&L.residual, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.n_free); }), zero, zero);
+    add(&L.refine, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.n_free); }), zero, zero);
+    add(&L.velocity, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.nv); }), zero, zero);
+    add(&L.ifwd, all, per([](const vh::DevMesh& d) { return d.D; }), zero, zero);
+    add(&L.ibwd, all, per([](const vh::DevMesh& d) { return d.D; }), zero, zero);
+    // interface phases: phase j of every garment in one launch per lane-group size
+    auto phases = [&](bool fwd, std::vector<CoarseLaunch>& out) {
+        size_t nj = 0;
+        for (vh_mesh* m : members) nj = std::max(nj, (fwd ? m->plan.cfwd : m->plan.cbwd).size());
+        out.reserve(2 * nj);
+        for (size_t j = 0; j < nj; ++j)
+            for (int32_t grp : {16, 64}) {
+                std::vector<int32_t> g, b, x0, x1;
+                int32_t kind = -1;
+                for (int32_t i = 0; i < ng; ++i) {
+                    const auto& ph = fwd ? members[i]->plan.cfwd : members[i]->plan.cbwd;
+                    if (j >= ph.size() || ph[j].group != grp) continue;
+                    kind = ph[j].kind;
+                    g.push_back(i);
+                    b.push_back(vh::coarse_blocks(ph[j].ntasks, grp));
+                    x0.push_back(ph[j].task0);
+                    x1.push_back(ph[j].ntasks);
+                }
+                if (g.empty()) continue;
+                out.push_back(CoarseLaunch{});
+                out.back().kind = kind;
+                out.back().group = grp;
+                add(&out.back().ref, g, b, x0, x1);
+            }
+    };
+    phases(true, L.cfwd);
+    phases(false, L.cbwd);
+    // device copies
+    std::vector<vh::DevMesh> G(ng);
+    int32_t max_n = 1, max_nb = 0, max_cint = 0;
+    for (int32_t i = 0; i < ng; ++i) {
+        G[i] = members[i]->dm;
+        max_n = std::max(max_n, G[i].max_sub_n);
+        max_nb = std::max(max_nb, G[i].max_nb);
+        max_cint = std::max(max_cint, G[i].max_cint);
+    }
+    // every garment of a launch carves LDS with its own sizes inside the batch maximum
+    for (auto& d : G) {
+        d.max_sub_n = max_n;
+        d.max_nb = max_nb;
+        d.max_cint = max_cint;
+    }
+    L.lds_fwd = vh::interior_fwd_lds(max_n, max_cint);
+    L.lds_bwd = vh::interior_bwd_lds(max_n, max_nb);
+    const size_t need = sizeof(vh::DevMesh) * ng + sizeof(int32_t) * (tab.size() + ng);
+    if (ctx->budget && ctx->in_use + need > ctx->budget) return fail(VH_ENOMEM, "HBM budget exceeded");
+    VH_HIP(hipMalloc(&L.G, sizeof(vh::DevMesh) * ng));
+    VH_HIP(hipMalloc(&L.tables, sizeof(int32_t) * tab.size()));
+    VH_HIP(hipMalloc(&L.active, sizeof(int32_t) * ng));
+    L.bytes = need;
+    VH_HIP(hipMemcpy(L.G, G.data(), sizeof(vh::DevMesh) * ng, hipMemcpyHostToDevice));
+    VH_HIP(hipMemcpy(L.tables, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice));
+    std::vector<int32_t> ones(ng, 1);
+    VH_HIP(hipMemcpy(L.active, ones.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice));
+    for (auto& f : fix) {
+        f.first->G = L.G;
+        f.first->L = L.tables + f.second;
+        f.first->active = L.active;
+    }
+    return VH_OK;
+}
+
 int set_device(vh_mesh* m) {
     VH_HIP(hipSetDevice(m->ctx->device));
     return VH_OK;
 }
 
-int solve(vh_mesh* m, hipStream_t s, bool apply, bool keep_delta) {
-    const vh::DevMesh& d = m->dm;
+int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta) {
     {
         ProfScope ps(m, s, 3);
-        VH_HIP(vh::launch_interior_fwd(d, s));
+        VH_HIP(vh::launch_interior_fwd(L.ifwd, L.lds_fwd, s));
     }
     {
         ProfScope ps(m, s, 4);
-        for (const auto& ph : m->fwd) VH_HIP(vh::launch_interface_phase(d, ph, s));
-        for (const auto& ph : m->bwd) VH_HIP(vh::launch_interface_phase(d, ph, s));
+        for (const auto& c : L.cfwd) VH_HIP(vh::launch_coarse(c.ref, c.kind, c.group, s));
+        for (const auto& c : L.cbwd) VH_HIP(vh::launch_coarse(c.ref, c.kind, c.group, s));
     }
     {
         ProfScope ps(m, s, 5);
-        VH_HIP(vh::launch_interior_bwd(d, s, apply, keep_delta));
+        VH_HIP(vh::launch_interior_bwd(L.ibwd, L.lds_bwd, s, apply, keep_delta));
     }
     return VH_OK;
 }
 
-int pd_iteration(vh_mesh* m, hipStream_t s) {
-    const vh::DevMesh& d = m->dm;
+int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s) {
     {
         ProfScope ps(m, s, 1);
-        VH_HIP(vh::launch_local(d, s, false));
+        VH_HIP(vh::launch_local(L.local, s, false));
     }
     {
         ProfScope ps(m, s, 2);
-        VH_HIP(vh::launch_residual(d, s));
+        VH_HIP(vh::launch_residual(L.residual, s));
     }
-    const bool refine = m->refine > 0;
-    VH_TRY(solve(m, s, true, refine));
-    for (int32_t k = 0; k < m->refine; ++k) {
+    const bool refine = L.refine_steps > 0;
+    VH_TRY(solve(m, L, s, true, refine));
+    for (int32_t k = 0; k < L.refine_steps; ++k) {
         {
             ProfScope ps(m, s, 6);
-            VH_HIP(vh::launch_refine_residual(d, s));
+            VH_HIP(vh::launch_refine_residual(L.refine, s));
         }
-        VH_TRY(solve(m, s, true, k + 1 < m->refine));
+        VH_TRY(solve(m, L, s, true, k + 1 < L.refine_steps));
     }
     return VH_OK;
 }
 
-int frame_direct(vh_mesh* m, hipStream_t s) {
+// One frame over the launch set; m (may be null) receives per-class timing.
+int frame_direct(vh_mesh* m, const LaunchSet& L, hipStream_t s) {
     {
         ProfScope ps(m, s, 0);
-        VH_HIP(vh::launch_predictor(m->dm, s));
+        VH_HIP(vh::launch_predictor(L.predict, s));
     }
-    for (int32_t k = 0; k < m->plan.pd_iters; ++k) VH_TRY(pd_iteration(m, s));
+    for (int32_t k = 0; k < L.pd_iters; ++k) VH_TRY(pd_iteration(m, L, s));
     {
         ProfScope ps(m, s, 7);
-        VH_HIP(vh::launch_velocity(m->dm, s));
+        VH_HIP(vh::launch_velocity(L.velocity, s));
     }
     return VH_OK;
 }
@@ -215,7 +354,7 @@ int ensure_graph(vh_mesh* m) {
     const uint32_t mask = m->prof_mask;
     m->prof_mask = 0;
     VH_HIP(hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal));
-    int rc = frame_direct(m, m->cap);
+    int rc = frame_direct(m, m->ls, m->cap);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(m->cap, &g);
     m->prof_mask = mask;
@@ -389,7 +528,8 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     d.max_sub_n = std::max(P.max_sub_n, 1);
     d.max_nb = P.max_nb;
     d.max_cint = P.max_cint;
-    const size_t lds_need = std::max(vh::interior_fwd_lds(d), vh::interior_bwd_lds(d));
+    const size_t lds_need = std::max(vh::interior_fwd_lds(d.max_sub_n, d.max_cint),
+                                     vh::interior_bwd_lds(d.max_sub_n, d.max_nb));
     if (lds_need > (size_t)lds_limit)
         return fail(VH_EINVAL, "a subdomain needs " + std::to_string(lds_need) +
                                    " bytes of LDS (limit " + std::to_string(lds_limit) +
@@ -453,11 +593,16 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     VH_HIP(hipMemset(d.v, 0, nv3 * sizeof(double)));
     VH_HIP(hipMemset(d.flags, 0, 4 * sizeof(uint32_t)));
     VH_HIP(hipMemset(d.delta, 0, (size_t)P.n_free * 3 * sizeof(double)));
-    m->fwd.clear();
-    m->bwd.clear();
-    m->fwd = P.cfwd;
-    m->bwd = P.cbwd;
     m->refine = refine_steps;
+    {
+        std::vector<vh_mesh*> one{m};
+        int lrc = build_launch_set(m->ctx, one, m->ls);
+        if (lrc != VH_OK) {
+            free_device(m);
+            return lrc;
+        }
+        m->ctx->in_use += m->ls.bytes;
+    }
     const char* ng = std::getenv("VHPD_NO_GRAPH");
     m->use_graph = !(ng && ng[0] == '1');
     VH_HIP(vh::launch_refresh_u(d, nullptr));
@@ -472,7 +617,7 @@ int vh_mesh_step(vh_mesh* m, int32_t n_frames, void* stream) {
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (m->prof_mask || !m->use_graph) {
-        for (int32_t f = 0; f < n_frames; ++f) VH_TRY(frame_direct(m, s));
+        for (int32_t f = 0; f < n_frames; ++f) VH_TRY(frame_direct(m, m->ls, s));
         return VH_OK;
     }
     if (n_frames > 0) VH_TRY(ensure_graph(m));
@@ -576,8 +721,9 @@ int vh_debug_local_step(vh_mesh* m, const double* x, double* T, double* sigma, d
         VH_TRY(dalloc(m, &d.dbg_s, (size_t)nt * 3));
     }
     VH_TRY(put_user(m, x, d.x, true, nullptr));
+    VH_HIP(hipMemcpy(&m->ls.G[0].dbg_T, &d.dbg_T, 3 * sizeof(float*), hipMemcpyHostToDevice));
     VH_HIP(vh::launch_refresh_u(d, nullptr));
-    VH_HIP(vh::launch_local(d, nullptr, true));
+    VH_HIP(vh::launch_local(m->ls.local, nullptr, true));
     VH_HIP(hipDeviceSynchronize());
     std::vector<float> hT((size_t)nt * 9), hs((size_t)nt * 3), hss((size_t)nt * 3);
     VH_HIP(hipMemcpy(hT.data(), d.dbg_T, hT.size() * 4, hipMemcpyDeviceToHost));
@@ -603,8 +749,8 @@ int vh_debug_residual(vh_mesh* m, const double* x, const double* y, double* r) {
     VH_TRY(put_user(m, x, d.x, true, nullptr));
     VH_TRY(put_user(m, y, d.y, true, nullptr));
     VH_HIP(vh::launch_refresh_u(d, nullptr));
-    VH_HIP(vh::launch_local(d, nullptr, false));
-    VH_HIP(vh::launch_residual(d, nullptr));
+    VH_HIP(vh::launch_local(m->ls.local, nullptr, false));
+    VH_HIP(vh::launch_residual(m->ls.residual, nullptr));
     VH_HIP(hipDeviceSynchronize());
     return get_user(m, d.r, r, d.n_free, nullptr);
 }
@@ -619,7 +765,7 @@ int vh_debug_solve(vh_mesh* m, const double* rhs, double* out) {
     for (int32_t i = 0; i < P.n_free; ++i)
         for (int c = 0; c < 3; ++c) st[3 * i + c] = rhs[3 * P.perm[i] + c];
     VH_HIP(hipMemcpy(d.r, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice));
-    VH_TRY(solve(m, nullptr, false, true));
+    VH_TRY(solve(m, m->ls, nullptr, false, true));
     VH_HIP(hipDeviceSynchronize());
     return get_user(m, d.delta, out, d.n_free, nullptr);
 }
@@ -631,14 +777,14 @@ int vh_mesh_time_kernel(vh_mesh* m, int32_t kernel_class, int32_t reps, void* st
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int32_t r = 0; r < reps; ++r) {
         switch (kernel_class) {
-            case 1: VH_HIP(vh::launch_local(m->dm, s, false)); break;
-            case 2: VH_HIP(vh::launch_residual(m->dm, s)); break;
-            case 3: VH_HIP(vh::launch_interior_fwd(m->dm, s)); break;
+            case 1: VH_HIP(vh::launch_local(m->ls.local, s, false)); break;
+            case 2: VH_HIP(vh::launch_residual(m->ls.residual, s)); break;
+            case 3: VH_HIP(vh::launch_interior_fwd(m->ls.ifwd, m->ls.lds_fwd, s)); break;
             case 4:
-                for (const auto& ph : m->fwd) VH_HIP(vh::launch_interface_phase(m->dm, ph, s));
-                for (const auto& ph : m->bwd) VH_HIP(vh::launch_interface_phase(m->dm, ph, s));
+                for (const auto& c : m->ls.cfwd) VH_HIP(vh::launch_coarse(c.ref, c.kind, c.group, s));
+                for (const auto& c : m->ls.cbwd) VH_HIP(vh::launch_coarse(c.ref, c.kind, c.group, s));
                 break;
-            case 5: VH_HIP(vh::launch_interior_bwd(m->dm, s, false, false)); break;
+            case 5: VH_HIP(vh::launch_interior_bwd(m->ls.ibwd, m->ls.lds_bwd, s, false, false)); break;
             default: return fail(VH_EINVAL, "kernel_class must be 1..5");
         }
     }

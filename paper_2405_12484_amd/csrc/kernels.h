@@ -49,25 +49,36 @@ struct DevMesh {
     float *dbg_T = nullptr, *dbg_sig = nullptr, *dbg_s = nullptr;
 };
 
-// Host copy of an interface phase launch shape.
-using PhaseLaunch = CPhase;
+// One launch over one or more garments: G is a device array of DevMesh, L the
+// launch table [ng, bstart[0..ng], gid[0..ng-1], x0[0..ng-1], x1[0..ng-1]]
+// (device), active a device array of per-garment flags, nblocks = bstart[ng].
+struct LaunchRef {
+    const DevMesh* G = nullptr;
+    const int32_t* L = nullptr;
+    const int32_t* active = nullptr;
+    int32_t nblocks = 0;
+};
 
-// LDS bytes of the interior kernels for a mesh (two chunk buffers + vectors)
-size_t interior_fwd_lds(const DevMesh& m);
-size_t interior_bwd_lds(const DevMesh& m);
+// LDS bytes of the interior kernels (two chunk buffers + subdomain vectors)
+size_t interior_fwd_lds(int32_t max_n, int32_t max_cint);
+size_t interior_bwd_lds(int32_t max_n, int32_t max_nb);
 // allow the interior kernels to use up to `bytes` of LDS per workgroup
 hipError_t interior_set_lds_limit(size_t bytes);
 // capacity of one interior LDS chunk in 32-bit words
 int32_t interior_chunk_words();
+// blocks per garment of each launch kind
+int32_t blocks_vertices(int32_t n);
+int32_t blocks_tets(int32_t nt);
+int32_t coarse_blocks(int32_t ntasks, int32_t group);
 
-hipError_t launch_predictor(const DevMesh& m, hipStream_t s);
-hipError_t launch_local(const DevMesh& m, hipStream_t s, bool debug);
-hipError_t launch_residual(const DevMesh& m, hipStream_t s);
-hipError_t launch_interior_fwd(const DevMesh& m, hipStream_t s);
-hipError_t launch_interface_phase(const DevMesh& m, const PhaseLaunch& ph, hipStream_t s);
-hipError_t launch_interior_bwd(const DevMesh& m, hipStream_t s, bool apply, bool keep_delta);
-hipError_t launch_refine_residual(const DevMesh& m, hipStream_t s);
-hipError_t launch_velocity(const DevMesh& m, hipStream_t s);
+hipError_t launch_predictor(const LaunchRef& r, hipStream_t s);
+hipError_t launch_local(const LaunchRef& r, hipStream_t s, bool debug);
+hipError_t launch_residual(const LaunchRef& r, hipStream_t s);
+hipError_t launch_interior_fwd(const LaunchRef& r, size_t lds, hipStream_t s);
+hipError_t launch_coarse(const LaunchRef& r, int32_t kind, int32_t group, hipStream_t s);
+hipError_t launch_interior_bwd(const LaunchRef& r, size_t lds, hipStream_t s, bool apply, bool keep_delta);
+hipError_t launch_refine_residual(const LaunchRef& r, hipStream_t s);
+hipError_t launch_velocity(const LaunchRef& r, hipStream_t s);
 
 }  // namespace vh
 

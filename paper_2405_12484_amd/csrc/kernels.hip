@@ -23,6 +23,33 @@ namespace {
 
 constexpr int BLK = 256;
 
+// A launch covers one or more garments.  Its table L is
+//   [ng, bstart[0..ng], gid[0..ng-1], x0[0..ng-1], x1[0..ng-1]]
+// (bstart: block prefix; gid: garment index into the DevMesh array; x0, x1:
+// per-garment launch parameters).  A block finds its garment by binary search
+// and skips the work when the garment is not active in this launch.
+struct Slot {
+    int32_t g, lb, x0, x1;
+};
+
+__device__ __forceinline__ bool slot_of(const int32_t* __restrict__ L, const int32_t* __restrict__ active,
+                                        Slot& s) {
+    const int32_t ng = L[0];
+    const int32_t* bs = L + 1;
+    const int32_t b = blockIdx.x;
+    int32_t lo = 0, hi = ng;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (bs[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    s.g = L[2 + ng + lo];
+    s.lb = b - bs[lo];
+    s.x0 = L[2 + 2 * ng + lo];
+    s.x1 = L[2 + 3 * ng + lo];
+    return active[s.g] != 0;
+}
+
 // Hardware reciprocal / square root / reciprocal square root (about 1 ulp);
 // every quantity they feed is FP32 and later compared at FP32 tolerance.
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -193,15 +220,22 @@ __device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_o
 constexpr int LBLK = 256;
 
 template <bool DBG>
-__global__ __launch_bounds__(LBLK) void k_local(int32_t nt, const float4* __restrict__ trec,
-                                                const uint2* __restrict__ lpos,
-                                                const float4* __restrict__ u,
-                                                const int32_t* __restrict__ blk_part,
-                                                const int32_t* __restrict__ part_pack,
-                                                float4* __restrict__ part, uint32_t* flags,
-                                                float* dT, float* dsig, float* ds_out) {
+__global__ __launch_bounds__(LBLK) void k_local(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                const int32_t* __restrict__ active) {
     __shared__ float LF[3][4 * LBLK];
-    const int32_t e = blockIdx.x * LBLK + threadIdx.x;
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t nt = M.nt;
+    const float4* __restrict__ trec = M.trec;
+    const uint2* __restrict__ lpos = M.lpos;
+    const float4* __restrict__ u = M.u;
+    const int32_t* __restrict__ blk_part = M.blk_part;
+    const int32_t* __restrict__ part_pack = M.part_pack;
+    float4* __restrict__ part = M.part;
+    uint32_t* flags = M.flags;
+    float *dT = M.dbg_T, *dsig = M.dbg_sig, *ds_out = M.dbg_s;
+    const int32_t e = sl.lb * LBLK + threadIdx.x;
     if (e < nt) {
         const float4 r0 = trec[4 * (size_t)e], r1 = trec[4 * (size_t)e + 1], r2 = trec[4 * (size_t)e + 2],
                      r3 = trec[4 * (size_t)e + 3];
@@ -275,7 +309,7 @@ __global__ __launch_bounds__(LBLK) void k_local(int32_t nt, const float4* __rest
         }
     }
     __syncthreads();
-    const int32_t p0 = blk_part[blockIdx.x], np = blk_part[blockIdx.x + 1] - p0;
+    const int32_t p0 = blk_part[sl.lb], np = blk_part[sl.lb + 1] - p0;
     for (int32_t k = threadIdx.x; k < np; k += LBLK) {
         const int32_t pk = part_pack[p0 + k];
         const int32_t st = pk >> 16, cnt = pk & 0xFFFF;
@@ -289,15 +323,22 @@ __global__ __launch_bounds__(LBLK) void k_local(int32_t nt, const float4* __rest
     }
 }
 
-__global__ __launch_bounds__(BLK) void k_predict(int32_t nv, int32_t n_free, double dt, double gx,
-                                                 double gy, double gz, double* __restrict__ x,
-                                                 const double* __restrict__ v,
-                                                 double* __restrict__ xprev, double* __restrict__ y,
-                                                 const double* __restrict__ X,
-                                                 float4* __restrict__ u) {
-    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+__global__ __launch_bounds__(BLK) void k_predict(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                 const int32_t* __restrict__ active) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t nv = M.nv, n_free = M.n_free;
+    const double dt = M.dt;
+    double* __restrict__ x = M.x;
+    const double* __restrict__ v = M.v;
+    double* __restrict__ xprev = M.xprev;
+    double* __restrict__ y = M.y;
+    const double* __restrict__ X = M.X;
+    float4* __restrict__ u = M.u;
+    const int32_t i = sl.lb * BLK + threadIdx.x;
     if (i >= nv) return;
-    const double g[3] = {gx, gy, gz};
+    const double g[3] = {M.g[0], M.g[1], M.g[2]};
     float du[3];
     if (i < n_free) {
 #pragma unroll
@@ -324,14 +365,21 @@ __global__ __launch_bounds__(BLK) void k_predict(int32_t nv, int32_t n_free, dou
 
 // r_a = m_a (y_a - x_a) / dt^2 + the sum of the vertex's per-workgroup force
 // partials (ascending workgroup order, so the result is deterministic).
-__global__ __launch_bounds__(BLK) void k_residual(int32_t n_free, const int32_t* __restrict__ vpart_ptr,
-                                                  const int32_t* __restrict__ vpart,
-                                                  const float4* __restrict__ part,
-                                                  const double* __restrict__ mass,
-                                                  const double* __restrict__ x,
-                                                  const double* __restrict__ y, double inv_dt2,
-                                                  double* __restrict__ r) {
-    const int32_t a = blockIdx.x * BLK + threadIdx.x;
+__global__ __launch_bounds__(BLK) void k_residual(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                  const int32_t* __restrict__ active) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t n_free = M.n_free;
+    const int32_t* __restrict__ vpart_ptr = M.vpart_ptr;
+    const int32_t* __restrict__ vpart = M.vpart;
+    const float4* __restrict__ part = M.part;
+    const double* __restrict__ mass = M.mass;
+    const double* __restrict__ x = M.x;
+    const double* __restrict__ y = M.y;
+    double* __restrict__ r = M.r;
+    const double inv_dt2 = 1.0 / (M.dt * M.dt);
+    const int32_t a = sl.lb * BLK + threadIdx.x;
     if (a >= n_free) return;
     const int32_t j0 = vpart_ptr[a], j1 = vpart_ptr[a + 1];
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
@@ -375,6 +423,39 @@ struct SolveArgs {
     float4* u;
 };
 
+__host__ __device__ __forceinline__ SolveArgs solve_args(const DevMesh& m) {
+    SolveArgs a;
+    a.n_int = m.n_int;
+    a.n_gamma = m.n_gamma;
+    a.D = m.D;
+    a.max_n = m.max_sub_n;
+    a.max_nb = m.max_nb;
+    a.max_cint = m.max_cint;
+    a.sub_off = m.sub_off;
+    a.sub_fwd_ch = m.sub_fwd_ch;
+    a.sub_bwd_ch = m.sub_bwd_ch;
+    a.bnd = m.bnd;
+    a.bnd_off = m.bnd_off;
+    a.chunks = m.chunks;
+    a.ivals = m.ivals;
+    a.ctasks = m.ctasks;
+    a.cslots = m.cslots;
+    a.cgidx = m.cgidx;
+    a.dvals = m.dvals;
+    a.r = m.r;
+    a.zf = m.zf;
+    a.cgf = m.cgf;
+    a.cgd = m.cgd;
+    a.rg = m.rg;
+    a.zg = m.zg;
+    a.dg = m.dg;
+    a.delta = m.delta;
+    a.x = m.x;
+    a.X = m.X;
+    a.u = m.u;
+    return a;
+}
+
 // Interior kernels: one 1024-thread workgroup (16 waves) per subdomain.
 constexpr int BLKI = 1024;
 constexpr int NV4I = 3;                       // float4 per thread per chunk
@@ -402,14 +483,19 @@ __device__ __forceinline__ void chunk_store(float4* dst, int32_t nv4, const floa
 // column-major block against broadcast r' values: z to LDS, contributions to
 // interior rows to LDS slots, to interface rows to global FP32 slots.  The next
 // chunk is read into registers while the current one is computed.
-__global__ __launch_bounds__(BLKI) void k_interior_fwd(SolveArgs a) {
+__global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict__ GM,
+                                                        const int32_t* __restrict__ L,
+                                                        const int32_t* __restrict__ active) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const SolveArgs a = solve_args(GM[sl.g]);
     extern __shared__ float4 sm4[];
     float* sm = reinterpret_cast<float*>(sm4);
     float* bufs[2] = {sm, sm + CHI};
     float* R = sm + 2 * CHI;
     float* Z = R + 3 * a.max_n;
     float* C = Z + 3 * a.max_n;
-    const int32_t d = blockIdx.x;
+    const int32_t d = sl.lb;
     const int32_t base = a.sub_off[d];
     const int32_t n_loc = a.sub_off[d + 1] - base;
     const int tid = threadIdx.x;
@@ -493,9 +579,14 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(SolveArgs a) {
 //   GEMV:    zg[idx] or cgd[idx] = row of W . rg
 //   BGEMV:   dg[out] = Ti column . zg + (-W_B) column . dg[gather]
 template <int G>
-__global__ __launch_bounds__(BLK) void k_coarse(SolveArgs a, int32_t kind, int32_t task0, int32_t ntasks) {
+__global__ __launch_bounds__(BLK) void k_coarse(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                const int32_t* __restrict__ active, int32_t kind) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const SolveArgs a = solve_args(GM[sl.g]);
+    const int32_t task0 = sl.x0, ntasks = sl.x1;
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
-    const int32_t t = blockIdx.x * (BLK / G) + grp;
+    const int32_t t = sl.lb * (BLK / G) + grp;
     if (t >= ntasks) return;
     const CTask T = a.ctasks[task0 + t];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -593,13 +684,19 @@ __global__ __launch_bounds__(BLK) void k_coarse(SolveArgs a, int32_t kind, int32
 // d_k = sum_{i>=k} Ti[i][k] z_i - sum_p (B Ti)[p][k] d[rows_p], with the
 // subdomain's boundary values of the interface solution staged in LDS after
 // its interior rows, so every gather hits LDS.
-__global__ __launch_bounds__(BLKI) void k_interior_bwd(SolveArgs a, int32_t apply, int32_t keep_delta) {
+__global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict__ GM,
+                                                        const int32_t* __restrict__ L,
+                                                        const int32_t* __restrict__ active, int32_t apply,
+                                                        int32_t keep_delta) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const SolveArgs a = solve_args(GM[sl.g]);
     extern __shared__ float4 sm4[];
     float* sm = reinterpret_cast<float*>(sm4);
     float* bufs[2] = {sm, sm + CHI};
     float* Z = sm + 2 * CHI;
     float* DL = Z + 3 * a.max_n;
-    const int32_t d = blockIdx.x;
+    const int32_t d = sl.lb;
     const int32_t base = a.sub_off[d];
     const int32_t n_loc = a.sub_off[d + 1] - base;
     const int32_t b0 = a.bnd_off[d], nb = a.bnd_off[d + 1] - b0;
@@ -714,12 +811,18 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(SolveArgs a, int32_t appl
     }
 }
 
-__global__ __launch_bounds__(BLK) void k_refine(int32_t n_free, const int32_t* __restrict__ Kp,
-                                                const int32_t* __restrict__ Kc,
-                                                const double* __restrict__ Kv,
-                                                const double* __restrict__ delta,
-                                                double* __restrict__ r) {
-    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+__global__ __launch_bounds__(BLK) void k_refine(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                const int32_t* __restrict__ active) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t n_free = M.n_free;
+    const int32_t* __restrict__ Kp = M.K_ptr;
+    const int32_t* __restrict__ Kc = M.K_col;
+    const double* __restrict__ Kv = M.K_val;
+    const double* __restrict__ delta = M.delta;
+    double* __restrict__ r = M.r;
+    const int32_t i = sl.lb * BLK + threadIdx.x;
     if (i >= n_free) return;
     double s0 = 0, s1 = 0, s2 = 0;
     for (int32_t k = Kp[i]; k < Kp[i + 1]; ++k) {
@@ -734,11 +837,18 @@ __global__ __launch_bounds__(BLK) void k_refine(int32_t n_free, const int32_t* _
     r[3 * i + 2] -= s2;
 }
 
-__global__ __launch_bounds__(BLK) void k_velocity(int32_t nv, int32_t n_free, double inv_dt,
-                                                  const double* __restrict__ x,
-                                                  const double* __restrict__ xprev,
-                                                  double* __restrict__ v, uint32_t* flags) {
-    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+__global__ __launch_bounds__(BLK) void k_velocity(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                  const int32_t* __restrict__ active) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t nv = M.nv, n_free = M.n_free;
+    const double inv_dt = 1.0 / M.dt;
+    const double* __restrict__ x = M.x;
+    const double* __restrict__ xprev = M.xprev;
+    double* __restrict__ v = M.v;
+    uint32_t* flags = M.flags;
+    const int32_t i = sl.lb * BLK + threadIdx.x;
     if (i >= nv) return;
     bool bad = false;
 #pragma unroll
@@ -750,72 +860,37 @@ __global__ __launch_bounds__(BLK) void k_velocity(int32_t nv, int32_t n_free, do
     if (bad) atomicOr(&flags[0], 1u);
 }
 
-SolveArgs solve_args(const DevMesh& m) {
-    SolveArgs a;
-    a.n_int = m.n_int;
-    a.n_gamma = m.n_gamma;
-    a.D = m.D;
-    a.max_n = m.max_sub_n;
-    a.max_nb = m.max_nb;
-    a.max_cint = m.max_cint;
-    a.sub_off = m.sub_off;
-    a.sub_fwd_ch = m.sub_fwd_ch;
-    a.sub_bwd_ch = m.sub_bwd_ch;
-    a.bnd = m.bnd;
-    a.bnd_off = m.bnd_off;
-    a.chunks = m.chunks;
-    a.ivals = m.ivals;
-    a.ctasks = m.ctasks;
-    a.cslots = m.cslots;
-    a.cgidx = m.cgidx;
-    a.dvals = m.dvals;
-    a.r = m.r;
-    a.zf = m.zf;
-    a.cgf = m.cgf;
-    a.cgd = m.cgd;
-    a.rg = m.rg;
-    a.zg = m.zg;
-    a.dg = m.dg;
-    a.delta = m.delta;
-    a.x = m.x;
-    a.X = m.X;
-    a.u = m.u;
-    return a;
-}
-
 inline int nblk(int64_t n) { return (int)((n + BLK - 1) / BLK); }
 
 }  // namespace
 
-hipError_t launch_predictor(const DevMesh& m, hipStream_t s) {
-    hipLaunchKernelGGL(k_predict, dim3(nblk(m.nv)), dim3(BLK), 0, s, m.nv, m.n_free, m.dt, m.g[0],
-                       m.g[1], m.g[2], m.x, m.v, m.xprev, m.y, m.X, m.u);
+hipError_t launch_predictor(const LaunchRef& r, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_predict, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active);
     return hipGetLastError();
 }
 
-hipError_t launch_local(const DevMesh& m, hipStream_t s, bool debug) {
-    const dim3 g((m.nt + LBLK - 1) / LBLK);
+hipError_t launch_local(const LaunchRef& r, hipStream_t s, bool debug) {
+    if (r.nblocks <= 0) return hipSuccess;
     if (debug)
-        hipLaunchKernelGGL(k_local<true>, g, dim3(LBLK), 0, s, m.nt, m.trec, m.lpos, m.u, m.blk_part,
-                           m.part_pack, m.part, m.flags, m.dbg_T, m.dbg_sig, m.dbg_s);
+        hipLaunchKernelGGL(k_local<true>, dim3(r.nblocks), dim3(LBLK), 0, s, r.G, r.L, r.active);
     else
-        hipLaunchKernelGGL(k_local<false>, g, dim3(LBLK), 0, s, m.nt, m.trec, m.lpos, m.u, m.blk_part,
-                           m.part_pack, m.part, m.flags, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL(k_local<false>, dim3(r.nblocks), dim3(LBLK), 0, s, r.G, r.L, r.active);
     return hipGetLastError();
 }
 
-hipError_t launch_residual(const DevMesh& m, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual, dim3(nblk(m.n_free)), dim3(BLK), 0, s, m.n_free, m.vpart_ptr,
-                       m.vpart, m.part, m.mass, m.x, m.y, 1.0 / (m.dt * m.dt), m.r);
+hipError_t launch_residual(const LaunchRef& r, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_residual, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active);
     return hipGetLastError();
 }
 
-size_t interior_fwd_lds(const DevMesh& m) {
-    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)m.max_sub_n + 3 * (size_t)m.max_cint);
+size_t interior_fwd_lds(int32_t max_n, int32_t max_cint) {
+    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)max_n + 3 * (size_t)max_cint);
 }
 
-size_t interior_bwd_lds(const DevMesh& m) {
-    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)m.max_sub_n + 3 * (size_t)m.max_nb);
+size_t interior_bwd_lds(int32_t max_n, int32_t max_nb) {
+    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)max_n + 3 * (size_t)max_nb);
 }
 
 int32_t interior_chunk_words() { return CHI; }
@@ -829,39 +904,44 @@ hipError_t interior_set_lds_limit(size_t bytes) {
     return e;
 }
 
-hipError_t launch_interior_fwd(const DevMesh& m, hipStream_t s) {
-    hipLaunchKernelGGL(k_interior_fwd, dim3(m.D), dim3(BLKI), interior_fwd_lds(m), s, solve_args(m));
+hipError_t launch_interior_fwd(const LaunchRef& r, size_t lds, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_interior_fwd, dim3(r.nblocks), dim3(BLKI), lds, s, r.G, r.L, r.active);
     return hipGetLastError();
 }
 
-hipError_t launch_interface_phase(const DevMesh& m, const PhaseLaunch& ph, hipStream_t s) {
-    if (ph.ntasks <= 0) return hipSuccess;
-    if (ph.group == 64)
-        hipLaunchKernelGGL(k_coarse<64>, dim3((ph.ntasks + 3) / 4), dim3(BLK), 0, s, solve_args(m),
-                           ph.kind, ph.task0, ph.ntasks);
+hipError_t launch_coarse(const LaunchRef& r, int32_t kind, int32_t group, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    if (group == 64)
+        hipLaunchKernelGGL(k_coarse<64>, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active, kind);
     else
-        hipLaunchKernelGGL(k_coarse<16>, dim3((ph.ntasks + 15) / 16), dim3(BLK), 0, s, solve_args(m),
-                           ph.kind, ph.task0, ph.ntasks);
+        hipLaunchKernelGGL(k_coarse<16>, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active, kind);
     return hipGetLastError();
 }
 
-hipError_t launch_interior_bwd(const DevMesh& m, hipStream_t s, bool apply, bool keep_delta) {
-    hipLaunchKernelGGL(k_interior_bwd, dim3(m.D), dim3(BLKI), interior_bwd_lds(m), s, solve_args(m),
+int32_t coarse_blocks(int32_t ntasks, int32_t group) { return (ntasks + BLK / group - 1) / (BLK / group); }
+
+hipError_t launch_interior_bwd(const LaunchRef& r, size_t lds, hipStream_t s, bool apply, bool keep_delta) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_interior_bwd, dim3(r.nblocks), dim3(BLKI), lds, s, r.G, r.L, r.active,
                        (int32_t)apply, (int32_t)keep_delta);
     return hipGetLastError();
 }
 
-hipError_t launch_refine_residual(const DevMesh& m, hipStream_t s) {
-    hipLaunchKernelGGL(k_refine, dim3(nblk(m.n_free)), dim3(BLK), 0, s, m.n_free, m.K_ptr, m.K_col,
-                       m.K_val, m.delta, m.r);
+hipError_t launch_refine_residual(const LaunchRef& r, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active);
     return hipGetLastError();
 }
 
-hipError_t launch_velocity(const DevMesh& m, hipStream_t s) {
-    hipLaunchKernelGGL(k_velocity, dim3(nblk(m.nv)), dim3(BLK), 0, s, m.nv, m.n_free, 1.0 / m.dt, m.x,
-                       m.xprev, m.v, m.flags);
+hipError_t launch_velocity(const LaunchRef& r, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_velocity, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active);
     return hipGetLastError();
 }
+
+int32_t blocks_vertices(int32_t n) { return (n + BLK - 1) / BLK; }
+int32_t blocks_tets(int32_t nt) { return (nt + LBLK - 1) / LBLK; }
 
 }  // namespace vh
 
