@@ -7,11 +7,18 @@ the scale of the paper's 389K-tet sweater scene).  One "step" is one frame:
 predictor, 10 x (local step, residual gather, decomposed solve), velocity.
 Inputs are resident in HBM before the timed region starts.
 
-Prints ONE JSON line with ms/frame, the live roofline of the dominant
-HBM-bound kernel (algorithmic bytes / average launch time from HIP events
-recorded around its launches inside the timed region), the FP64 oracle timed
-on a bounded sample on the host, and the relative L2 error of the first frame
-against the oracle.
+Prints ONE JSON line with:
+  * ms/frame: HIP events around K frames replayed as a captured graph;
+  * the roofline of every kernel class and of the dominant one: algorithmic
+    bytes (vh_mesh_get_info) / average launch-group time, from HIP events on
+    the bench stream around each launch group inside K more frames; the same
+    from back-to-back launches of one class ("isolated", data warm in cache);
+    HBM traffic per launch from the committed rocprofv3 counter summary while
+    the kernel source is unchanged (else null);
+  * the FP64 oracle timed on a bounded sample on the host (cpu_baseline) and
+    the relative L2 error of the first frame against it;
+  * serving: 64 uneven garments, batched against sequential plain stepping
+    (saturated, Poisson arrivals at several rates, a 1 GB HBM budget).
 """
 
 from __future__ import annotations
@@ -28,6 +35,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def committed_traffic():
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (scaled by the plain-copy calibration), valid only while the kernel
+    source is the one those counters were taken on; otherwise {}."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pd_step_shell390k_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2405_12484_amd", "csrc", "kernels.hip")
+    try:
+        lines = open(path).read().splitlines()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return {}
+    want = [l.split()[1] for l in lines if l.startswith("kernels_sha256 ")]
+    if not want or want[0] != sha:
+        return {}
+    out = {}
+    for l in lines:
+        f = l.split()
+        if len(f) == 3 and f[0] == "traffic":
+            out[f[1]] = int(f[2])
+    return out
 
 
 def copy_calibration(torch, mb=512, reps=5):
@@ -89,10 +119,28 @@ def run(args):
     torch.cuda.synchronize()
     ms_per_frame = ev0.elapsed_time(ev1) / args.steps
 
-    # per-kernel-class duration: HIP events around `reps` back-to-back launches of
-    # that class on the bench stream, at the state the timed frames left
+    info = mesh.info()
+    classes = ("local", "residual", "interior_fwd", "interface", "interior_bwd")
+    nbytes = {"local": info["bytes_local"], "residual": info["bytes_residual"],
+              "interior_fwd": info["bytes_interior_fwd"], "interface": info["bytes_interface"],
+              "interior_bwd": info["bytes_interior_bwd"]}
+    kname = {"local": "k_local", "residual": "k_residual", "interior_fwd": "k_interior_fwd",
+             "interface": "k_coarse", "interior_bwd": "k_interior_bwd"}
+    launches = {k: (info["interface_launches"] if k == "interface" else 1) for k in classes}
+
+    # per-class durations inside real frames: a second timed region of K frames
+    # with HIP events recorded on the bench stream around every launch group of
+    # each class (frames launched directly, not as a graph)
+    mesh.profile(list(vhpd.Mesh.PROFILE_CLASSES))
+    mesh.step(args.steps, stream)
+    br = mesh.profile_read()
+    mesh.profile([])
+    breakdown = {k: round(v[0] / args.steps, 4) for k, v in br.items()}   # ms per frame
+    group_us = {k: br[k][0] * 1e3 / br[k][1] for k in classes}            # us per launch group
+
+    # isolated: `reps` back-to-back launches of one class (its data warm in cache)
     reps = {"local": 40, "residual": 40, "interior_fwd": 10, "interface": 10, "interior_bwd": 10}
-    kt = {}
+    iso_us = {}
     for k, n in reps.items():
         mesh.time_kernel(k, 2, stream)
         torch.cuda.synchronize()
@@ -102,40 +150,35 @@ def run(args):
         mesh.time_kernel(k, n, stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        kt[k] = e0.elapsed_time(e1) / n * 1e3           # us per launch (per solve for the interface)
-    info = mesh.info()
-    nbytes = {"local": info["bytes_local"], "residual": info["bytes_residual"],
-              "interior_fwd": info["bytes_interior_fwd"], "interface": info["bytes_interface"],
-              "interior_bwd": info["bytes_interior_bwd"]}
-    kname = {"local": "k_local", "residual": "k_residual", "interior_fwd": "k_interior_fwd",
-             "interface": "k_coarse", "interior_bwd": "k_interior_bwd"}
-    per_frame_us = {k: kt[k] * p.pd_iters * (1 + args.refine) if k != "local" and k != "residual"
-                    else kt[k] * p.pd_iters for k in kt}
+        iso_us[k] = e0.elapsed_time(e1) / n * 1e3
+
+    traffic = committed_traffic()
     rooflines = {}
-    for k in kt:
-        launches = info["interface_launches"] if k == "interface" else 1
-        gbs = nbytes[k] / (kt[k] * 1e-6) / 1e9
+    for k in classes:
+        gbs = nbytes[k] / (group_us[k] * 1e-6) / 1e9
+        iso = nbytes[k] / (iso_us[k] * 1e-6) / 1e9
+        t = traffic.get(k)
         rooflines[k] = {"kernel": kname[k], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                        "bytes_per_launch": int(nbytes[k] / launches),
-                        "avg_launch_us": round(kt[k] / launches, 3),
-                        "us_per_frame": round(per_frame_us[k], 1)}
-    dominant = max(per_frame_us, key=per_frame_us.get)
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": t, "bytes_per_launch": int(nbytes[k] / launches[k]),
+                        "avg_launch_us": round(group_us[k] / launches[k], 3),
+                        "launches_per_group": launches[k],
+                        "us_per_frame": round(breakdown[k] * 1e3, 1),
+                        "isolated_avg_launch_us": round(iso_us[k] / launches[k], 3),
+                        "isolated_achieved": round(iso, 1), "isolated_frac": round(iso / HBM_PEAK_GBS, 4)}
+    dominant = max(classes, key=lambda k: breakdown[k])
     roofline = dict(rooflines[dominant])
+    ls_b = nbytes["local"] + nbytes["residual"]
     local_scatter = {
         "kernels": "k_local + k_residual",
-        "bytes_per_iteration": nbytes["local"] + nbytes["residual"],
-        "us_per_iteration": round(kt["local"] + kt["residual"], 3),
-        "achieved": round((nbytes["local"] + nbytes["residual"]) / ((kt["local"] + kt["residual"]) * 1e-6) / 1e9, 1),
+        "bytes_per_iteration": ls_b,
+        "us_per_iteration": round(group_us["local"] + group_us["residual"], 3),
+        "achieved": round(ls_b / ((group_us["local"] + group_us["residual"]) * 1e-6) / 1e9, 1),
+        "isolated_us_per_iteration": round(iso_us["local"] + iso_us["residual"], 3),
+        "isolated_achieved": round(ls_b / ((iso_us["local"] + iso_us["residual"]) * 1e-6) / 1e9, 1),
     }
     local_scatter["frac"] = round(local_scatter["achieved"] / HBM_PEAK_GBS, 4)
-
-    # breakdown (separate, untimed pass with every class timed by events around its launch groups)
-    mesh.profile(list(vhpd.Mesh.PROFILE_CLASSES))
-    mesh.step(2, stream)
-    br = mesh.profile_read()
-    mesh.profile([])
-    breakdown = {k: round(v[0] / 2.0, 4) for k, v in br.items()}   # ms per frame
+    local_scatter["isolated_frac"] = round(local_scatter["isolated_achieved"] / HBM_PEAK_GBS, 4)
 
     nt, nv, nf = p.nt, p.nv, info["n_free"]
     out = {
@@ -169,7 +212,162 @@ def run(args):
         out["rel_l2_first_frame_vs_oracle"] = err
     mesh.close()
     ctx.close()
+    if args.serving:
+        out["serving"] = serving(args)
     print(json.dumps(out), flush=True)
+
+
+def _serve_stats(st, extra=None):
+    out = {"frames_per_s": round(st["frames_per_second"], 1),
+           "p50_ms": round(st["latency_p50_s"] * 1e3, 3), "p99_ms": round(st["latency_p99_s"] * 1e3, 3),
+           "max_ms": round(st["latency_max_s"] * 1e3, 3), "frames": st["frames_done"],
+           "launches": st["launches"], "mean_batch": round(st["mean_batch"], 2),
+           "span_s": round(st["span_s"], 3), "hbm_peak_bytes": st["hbm_peak"]}
+    if extra:
+        out.update(extra)
+    return out
+
+
+def _poisson(rate, n_req, frames_left, seed_arr=7, seed_assign=8):
+    """Aggregate Poisson step arrivals at `rate`/s; each request (one frame) goes
+    to a garment drawn uniformly among those with frames left."""
+    ra = np.random.Generator(np.random.PCG64(seed_arr))
+    rg = np.random.Generator(np.random.PCG64(seed_assign))
+    left = np.array(frames_left, dtype=np.int64)
+    t = np.cumsum(ra.exponential(1.0 / rate, n_req))
+    out = []
+    for k in range(n_req):
+        cand = np.flatnonzero(left > 0)
+        if cand.size == 0:
+            break
+        g = int(cand[rg.integers(0, cand.size)])
+        left[g] -= 1
+        out.append((float(t[k]), g))
+    return out
+
+
+def _drive(srv, meshes, arrivals, release_after=None):
+    """Submit `arrivals` [(t, garment)] in real time on the server clock while
+    ticking the server; optionally release a garment right after its last
+    request (release_after[g] = index of that request)."""
+    import time as _t
+    t_base = srv.now()
+    i = 0
+    while i < len(arrivals):
+        now = srv.now() - t_base
+        while i < len(arrivals) and arrivals[i][0] <= now:
+            g = arrivals[i][1]
+            srv.submit(meshes[g], 1, t_base + arrivals[i][0])
+            if release_after is not None and release_after.get(g) == i:
+                srv.release(meshes[g])
+            i += 1
+        if srv.tick() == 0 and i < len(arrivals):
+            wait = arrivals[i][0] - (srv.now() - t_base)
+            if wait > 2e-4:
+                _t.sleep(min(wait - 1e-4, 5e-4))
+    srv.drain()
+
+
+def serving(args):
+    """Continuous batching of step requests from 64 uneven shell garments
+    (5K-200K tets, log-uniform), batched launches against sequential plain
+    stepping on the same GPU with the same kernels (bitwise the same results
+    per garment), plus admission under a 1 GB HBM budget."""
+    import torch
+    from paper_2405_12484_amd import vhpd
+    import synth
+
+    sizes = synth.serving_garment_sizes()
+    t0 = time.perf_counter()
+    probs = [synth.serving_shell_problem(int(n), 100 + g) for g, n in enumerate(sizes)]
+    gen_s = time.perf_counter() - t0
+    torch.cuda.init()
+    ctx = vhpd.Context(0)
+    meshes = []
+    for p in probs:
+        m = vhpd.Mesh(ctx, p.X, p.tets)
+        m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
+        meshes.append(m)
+    ng = len(meshes)
+    out = {"garments": ng, "tets_total": int(sum(p.nt for p in probs)),
+           "tets_min": int(min(p.nt for p in probs)), "tets_max": int(max(p.nt for p in probs)),
+           "subdomains": sorted({int(p.n_subdomains) for p in probs}), "dt": probs[0].dt,
+           "pd_iters": probs[0].pd_iters, "generate_s": round(gen_s, 2)}
+    # host factorization + upload of every garment (outside every timed window)
+    t0 = time.perf_counter()
+    srv = vhpd.Server(ctx, "batched", args.serve_in_flight)
+    for m, p in zip(meshes, probs):
+        srv.add(m, p.n_subdomains)
+    srv.tick()
+    out["prefactor_s"] = round(time.perf_counter() - t0, 2)
+    out["hbm_all_resident_bytes"] = ctx.hbm_in_use()
+    print(f"# serving: {ng} garments, {out['tets_total']} tets, prefactor {out['prefactor_s']} s, "
+          f"{out['hbm_all_resident_bytes'] / 2**30:.2f} GiB resident", file=sys.stderr, flush=True)
+    srv.close()
+
+    def session(mode, arrivals, warm=True):
+        srv = vhpd.Server(ctx, mode, args.serve_in_flight)
+        for m, p in zip(meshes, probs):
+            srv.add(m, p.n_subdomains)
+        if warm:                                  # graphs captured, clocks warm
+            for m in meshes:
+                srv.submit(m, 1)
+            srv.drain()
+            srv.reset_stats()
+        _drive(srv, meshes, arrivals)
+        st = srv.stats()
+        srv.close()
+        return st
+
+    F = args.serve_frames
+    res = {}
+    # saturated: every garment asks for F single-frame steps at t = 0
+    sat = [(0.0, g) for _ in range(F) for g in range(ng)]
+    res["saturated"] = {"requests": len(sat)}
+    for mode in ("batched", "sequential"):
+        st = session(mode, sat)
+        res["saturated"][mode] = _serve_stats(st)
+        print(f"# serving saturated {mode}: {res['saturated'][mode]}", file=sys.stderr, flush=True)
+    res["saturated"]["speedup_frames_per_s"] = round(
+        res["saturated"]["batched"]["frames_per_s"] / max(res["saturated"]["sequential"]["frames_per_s"], 1e-9), 2)
+    # Poisson arrivals at several aggregate rates
+    res["poisson"] = {}
+    for rate in args.serve_rates:
+        arr = _poisson(rate, args.serve_requests, [F * 10] * ng)
+        r = {"requests": len(arr), "rate_per_s": rate}
+        for mode in ("batched", "sequential"):
+            st = session(mode, arr)
+            r[mode] = _serve_stats(st)
+            print(f"# serving poisson {rate}/s {mode}: {r[mode]}", file=sys.stderr, flush=True)
+        res["poisson"][str(rate)] = r
+    # admission under a budget: every garment leaves the device after its last
+    # request, making room for the ones waiting in FIFO order
+    srv = vhpd.Server(ctx, "batched", args.serve_in_flight)
+    for m, p in zip(meshes, probs):               # release all: device memory freed, host plans kept
+        srv.add(m, p.n_subdomains)
+    for m in meshes:
+        srv.release(m)
+    srv.close()
+    budget = int(args.serve_budget_gb * 2**30)
+    ctx.set_hbm_budget(budget)
+    arr = _poisson(args.serve_budget_rate, ng * args.serve_budget_frames, [args.serve_budget_frames] * ng)
+    last = {}
+    for k, (_, g) in enumerate(arr):
+        last[g] = k
+    srv = vhpd.Server(ctx, "batched", args.serve_in_flight)
+    for m, p in zip(meshes, probs):
+        srv.add(m, p.n_subdomains)
+    _drive(srv, meshes, arr, release_after=last)
+    st = srv.stats()
+    srv.close()
+    res["budget"] = _serve_stats(st, {"budget_bytes": budget, "rate_per_s": args.serve_budget_rate,
+                                      "requests": len(arr), "frames_per_garment": args.serve_budget_frames})
+    print(f"# serving budget: {res['budget']}", file=sys.stderr, flush=True)
+    out.update(res)
+    for m in meshes:
+        m.close()
+    ctx.close()
+    return out
 
 
 def cpu_baseline(p, x1_gpu, args):
@@ -207,11 +405,23 @@ def main():
     ap.add_argument("--workload", default="shell")
     ap.add_argument("--refine", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", dest="serving", action="store_false")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving runs (one JSON object)")
+    ap.add_argument("--serve-frames", type=int, default=10, help="frames per garment, saturated run")
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[200.0, 1000.0, 5000.0])
+    ap.add_argument("--serve-requests", type=int, default=600, help="requests per Poisson run")
+    ap.add_argument("--serve-in-flight", type=int, default=2)
+    ap.add_argument("--serve-budget-gb", type=float, default=1.0)
+    ap.add_argument("--serve-budget-rate", type=float, default=1000.0)
+    ap.add_argument("--serve-budget-frames", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
               "path is a design note, not a measured configuration.", file=sys.stderr)
         sys.exit(2)
+    if args.serve_only:
+        print(json.dumps({"serving": serving(args)}), flush=True)
+        return
     run(args)
 
 

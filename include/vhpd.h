@@ -71,6 +71,9 @@ int vh_ctx_create(vh_ctx** out, int device, size_t hbm_budget_bytes);
 int vh_ctx_destroy(vh_ctx* ctx);
 /* Device bytes currently held by the context's meshes. */
 int vh_ctx_hbm_in_use(const vh_ctx* ctx, size_t* bytes);
+/* Change the budget (0 = unlimited).  Memory already held is kept; later
+ * allocations and admissions are checked against the new value. */
+int vh_ctx_set_hbm_budget(vh_ctx* ctx, size_t hbm_budget_bytes);
 
 /* Mesh: rest positions X [nv][3] (metres) and tets [nt][4].  Every tet must
  * have positive rest volume det([X1-X0, X2-X0, X3-X0])/6 > 0 (VH_EINVAL
@@ -167,16 +170,92 @@ int vh_debug_residual(vh_mesh* mesh, const double* x, const double* y, double* r
  * (pinned rows ignored on input, 0 on output). */
 int vh_debug_solve(vh_mesh* mesh, const double* rhs, double* d);
 
-/* ---- Serving: continuous batching of step requests across meshes. ---- */
+/* ---- Serving: continuous batching of step requests across meshes ----
+ *
+ * Not part of the paper's method: a request loop around the step above.  A
+ * context has at most one server.  Meshes handed to it are prefactored on the
+ * host at once and wait, in the order they were added, until their device
+ * memory fits in the context's HBM budget; then they are uploaded
+ * ("resident").  Step requests (n frames of one mesh) are queued per mesh and
+ * run in order.  The caller drives the server from one thread with
+ * vh_serve_tick / vh_serve_drain; launches go to the server's own stream.
+ *
+ * Times are seconds on the server clock, which starts at vh_serve_open.  A
+ * request's latency runs from its arrival to the completion, on the GPU, of
+ * its last frame (the GPU clock is aligned to the host clock at open). */
+
+enum {
+    /* each launch steps one frame of every resident mesh with a request
+     * waiting: one captured frame graph over all resident meshes, with the
+     * meshes that have no request masked off in its kernels (a launch of a
+     * single mesh uses that mesh's own frame graph) */
+    VH_SERVE_BATCHED = 0,
+    /* each launch steps one frame of one mesh with its own frame graph (plain
+     * stepping, one mesh at a time; the baseline for batching) */
+    VH_SERVE_SEQUENTIAL = 1
+};
+
+/* Open the server.  max_in_flight (1..64) bounds the launches enqueued ahead
+ * of the GPU; max_batch (>= 0, 0 = no limit) bounds the meshes per batched
+ * launch. */
+int vh_serve_open(vh_ctx* ctx, int32_t mode, int32_t max_in_flight, int32_t max_batch);
+/* Wait for every launch and close the server.  Meshes still in it leave it
+ * as they are (resident meshes stay on the device and can be stepped with
+ * vh_mesh_step again). */
+int vh_serve_close(vh_ctx* ctx);
+/* Hand a mesh (parameters set) to the server.  A mesh already on the device
+ * (prefactored, not released) is resident at once.  Otherwise it is queued
+ * for admission, after being factored on the host now (as vh_mesh_prefactor
+ * with n_subdomains, refine_steps) unless it kept its host factorization
+ * from an earlier prefactor or server (n_subdomains and refine_steps are then
+ * ignored, and its state restarts at rest when admitted); VH_ENOMEM if it
+ * alone exceeds the budget.  All meshes of a server need equal pd_iters and
+ * refine_steps (VH_EINVAL otherwise).  While a mesh is in the server,
+ * vh_mesh_step, the debug, timing and profiling calls on it return
+ * VH_ESTATE, and its state may be read or written only while it has no
+ * frames outstanding. */
+int vh_serve_add(vh_ctx* ctx, vh_mesh* mesh, int32_t n_subdomains, int32_t refine_steps);
+/* Queue a request for n_frames (>= 1) frames of mesh; t_arrival is its
+ * arrival time on the server clock (< 0: now).  *ticket identifies it. */
+int vh_serve_submit(vh_ctx* ctx, vh_mesh* mesh, int32_t n_frames, double t_arrival, uint64_t* ticket);
+/* One scheduling round: retire completed launches, free released meshes,
+ * admit waiting meshes that fit, then enqueue launches while fewer than
+ * max_in_flight are outstanding.  With wait != 0 and nothing enqueued, block
+ * until the oldest outstanding launch completes.  *n_launched (may be NULL)
+ * receives the launches enqueued. */
+int vh_serve_tick(vh_ctx* ctx, int32_t wait, int32_t* n_launched);
+/* Tick until every request has completed.  VH_ESTATE if requests wait for
+ * meshes that cannot be admitted next to the resident ones. */
+int vh_serve_drain(vh_ctx* ctx);
+/* The mesh takes no more requests; once its queued frames have completed its
+ * device memory is freed (making room for waiting meshes), it leaves the
+ * server, and its last state stays readable with vh_mesh_read_state.  A mesh
+ * still waiting for admission with requests is admitted and runs them
+ * first. */
+int vh_serve_release(vh_ctx* ctx, vh_mesh* mesh);
+/* *done = 1 once every frame of the request has completed, with *latency_s
+ * (may be NULL) its latency; otherwise *done = 0 and *latency_s = -1. */
+int vh_serve_poll(vh_ctx* ctx, uint64_t ticket, int32_t* done, double* latency_s);
+/* Current time on the server clock. */
+int vh_serve_now(vh_ctx* ctx, double* t);
+
+/* Restart the statistics window: completed requests are forgotten, the
+ * launch counters and the HBM peak restart from now. */
+int vh_serve_reset_stats(vh_ctx* ctx);
 
 typedef struct vh_serve_stats {
-    int64_t frames_done;
+    int64_t frames_done;        /* mesh-frames completed */
     int64_t requests_done;
-    double frames_per_second;
-    double latency_p50_s, latency_p99_s;
-    size_t hbm_in_use;
+    int64_t launches;           /* frame launches enqueued */
+    double mean_batch;          /* mesh-frames per launch */
+    double span_s;              /* first arrival to last request completion */
+    double frames_per_second;   /* frames_done / span_s */
+    double latency_p50_s, latency_p99_s, latency_max_s;   /* over completed requests */
+    size_t hbm_in_use, hbm_peak;   /* context device bytes now / at most since the server opened
+                                      (or since vh_serve_reset_stats) */
     int32_t meshes_resident, meshes_waiting;
 } vh_serve_stats;
+int vh_serve_get_stats(vh_ctx* ctx, vh_serve_stats* stats);
 
 #ifdef __cplusplus
 }

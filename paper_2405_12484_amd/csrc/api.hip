@@ -9,95 +9,29 @@
 #include <string>
 #include <vector>
 
-#include "../../include/vhpd.h"
-#include "kernels.h"
-#include "plan.h"
+#include "runtime.h"
+
+namespace vhrt {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
 
-#define VH_HIP(call)                                                                    \
-    do {                                                                                \
-        hipError_t e_ = (call);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(VH_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+const char* last_error() { return g_err.c_str(); }
 
-#define VH_TRY(expr)           \
-    do {                       \
-        int rc_ = (expr);      \
-        if (rc_ != VH_OK) return rc_; \
-    } while (0)
+void charge(vh_ctx* ctx, size_t bytes) {
+    ctx->in_use += bytes;
+    ctx->peak = std::max(ctx->peak, ctx->in_use);
+}
 
-}  // namespace
+void uncharge(vh_ctx* ctx, size_t bytes) { ctx->in_use -= std::min(ctx->in_use, bytes); }
 
 namespace {
-
-struct CoarseLaunch {
-    vh::LaunchRef ref;
-    int32_t kind = 0, group = 16;
-};
-
-// The launches of one frame over a set of garments (one mesh, or a batch).
-struct LaunchSet {
-    vh::DevMesh* G = nullptr;       // device [ng]
-    int32_t* tables = nullptr;      // device launch tables
-    int32_t* active = nullptr;      // device [ng]
-    int32_t ng = 0;
-    vh::LaunchRef predict, local, residual, ifwd, ibwd, refine, velocity;
-    std::vector<CoarseLaunch> cfwd, cbwd;
-    size_t lds_fwd = 0, lds_bwd = 0;
-    int32_t pd_iters = 10, refine_steps = 0;
-    size_t bytes = 0;
-};
-
-}  // namespace
-
-struct vh_ctx {
-    int device = 0;
-    size_t budget = 0;
-    size_t in_use = 0;
-    std::vector<vh_mesh*> meshes;
-};
-
-struct vh_mesh {
-    vh_ctx* ctx = nullptr;
-    int32_t nv = 0, nt = 0;
-    std::vector<double> X;
-    std::vector<int32_t> tets;
-    bool has_params = false, factored = false;
-    std::vector<double> gs, gv, mass;
-    std::vector<uint8_t> pinned;
-    double g[3] = {0, 0, 0};
-    double dt = 0;
-    int32_t iters = 10;
-    vh::Plan plan;
-    vh::DevMesh dm;
-    std::vector<void*> allocs;
-    size_t bytes = 0;
-    LaunchSet ls;                   // this mesh's own frame (one garment)
-    int32_t refine = 0;
-    std::vector<double> stage;   // host staging, nv*3
-    // optional per-kernel-class timing with HIP events on the step's stream
-    uint32_t prof_mask = 0;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    std::vector<std::pair<size_t, int>> ev_pairs;   // start event index, class
-    // one frame captured as a HIP graph (replayed per frame on the caller's stream)
-    bool use_graph = true;
-    hipStream_t cap = nullptr;
-    hipGraphExec_t gexec = nullptr;
-};
-
-namespace {
-
-void free_launch_set(LaunchSet& L);
 
 void release_events(vh_mesh* m) {
     for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
@@ -137,25 +71,15 @@ struct ProfScope {
     }
 };
 
-void free_device(vh_mesh* m) {
-    if (m->gexec) {
-        (void)hipGraphExecDestroy(m->gexec);
-        m->gexec = nullptr;
-    }
-    if (m->ctx) m->ctx->in_use -= std::min(m->ctx->in_use, m->ls.bytes);
-    free_launch_set(m->ls);
-    for (void* p : m->allocs) (void)hipFree(p);
-    m->allocs.clear();
-    if (m->ctx) m->ctx->in_use -= std::min(m->ctx->in_use, m->bytes);
-    m->bytes = 0;
-    m->dm = vh::DevMesh();
-    m->factored = false;
-}
-
 template <class T>
 int dalloc(vh_mesh* m, T** p, size_t count) {
     size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
     bytes = (bytes + 255) & ~(size_t)255;
+    if (m->dry) {
+        m->dry_bytes += bytes;
+        *p = nullptr;
+        return VH_OK;
+    }
     if (m->ctx->budget && m->ctx->in_use + bytes > m->ctx->budget)
         return fail(VH_ENOMEM, "HBM budget exceeded");
     void* q = nullptr;
@@ -163,7 +87,7 @@ int dalloc(vh_mesh* m, T** p, size_t count) {
     if (e != hipSuccess) return fail(VH_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     m->allocs.push_back(q);
     m->bytes += bytes;
-    m->ctx->in_use += bytes;
+    charge(m->ctx, bytes);
     *p = static_cast<T*>(q);
     return VH_OK;
 }
@@ -171,127 +95,80 @@ int dalloc(vh_mesh* m, T** p, size_t count) {
 template <class T>
 int upload(vh_mesh* m, T** p, const std::vector<T>& v) {
     VH_TRY(dalloc(m, p, v.size()));
-    if (!v.empty()) VH_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!m->dry && !v.empty())
+        VH_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return VH_OK;
 }
 
-void free_launch_set(LaunchSet& L) {
-    if (L.G) (void)hipFree(L.G);
-    if (L.tables) (void)hipFree(L.tables);
-    if (L.active) (void)hipFree(L.active);
-    L = LaunchSet();
-}
-
-// Build the launch tables of one frame over `members` (all prefactored, with
-// equal pd_iters and refine steps).  Device memory is charged to ctx.
-int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSet& L) {
-    free_launch_set(L);
-    const int32_t ng = (int32_t)members.size();
-    if (ng == 0) return fail(VH_EINVAL, "empty launch set");
-    L.ng = ng;
-    L.pd_iters = members[0]->plan.pd_iters;
-    L.refine_steps = members[0]->refine;
-    for (vh_mesh* m : members)
-        if (m->plan.pd_iters != L.pd_iters || m->refine != L.refine_steps)
-            return fail(VH_EINVAL, "garments in one batch need equal pd_iters and refine steps");
-    std::vector<int32_t> tab;
-    std::vector<std::pair<vh::LaunchRef*, size_t>> fix;   // ref -> table offset
-    // per-garment blocks and parameters -> one table
-    auto add = [&](vh::LaunchRef* ref, const std::vector<int32_t>& gids, const std::vector<int32_t>& nb,
-                   const std::vector<int32_t>& x0, const std::vector<int32_t>& x1) {
-        const size_t off = tab.size();
-        const int32_t n = (int32_t)gids.size();
-        tab.push_back(n);
-        int32_t acc = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            tab.push_back(acc);
-            acc += nb[i];
+// Allocates (or, in a dry run, counts) every device buffer of the plan and
+// uploads the constant data; the state starts at rest.
+int alloc_plan(vh_mesh* m) {
+    const vh::Plan& P = m->plan;
+    vh::DevMesh& d = m->dm;
+    const size_t nv3 = (size_t)P.nv * 3;
+    int r = VH_OK;
+    auto chk = [&](int x) {
+        if (r == VH_OK) r = x;
+    };
+    chk(upload(m, &d.X, P.X_int));
+    chk(upload(m, &d.x, P.X_int));
+    chk(dalloc(m, &d.v, nv3));
+    chk(dalloc(m, &d.xprev, nv3));
+    chk(dalloc(m, &d.y, nv3));
+    chk(upload(m, &d.mass, P.mass_int));
+    chk(upload(m, &d.perm, P.perm));
+    chk(dalloc(m, &d.u, (size_t)P.nv));
+    {
+        std::vector<float4> tr;
+        std::vector<uint2> lp;
+        if (!m->dry) {
+            tr.resize((size_t)P.nt * 4);
+            std::memcpy(tr.data(), P.trec.data(), P.trec.size() * sizeof(float));
+            lp.resize((size_t)P.nt);
+            std::memcpy(lp.data(), P.lpos.data(), P.lpos.size() * sizeof(uint16_t));
+            chk(upload(m, &d.trec, tr));
+            chk(upload(m, &d.lpos, lp));
+        } else {
+            chk(dalloc(m, &d.trec, (size_t)P.nt * 4));
+            chk(dalloc(m, &d.lpos, (size_t)P.nt));
         }
-        tab.push_back(acc);
-        for (int32_t v : gids) tab.push_back(v);
-        for (int32_t v : x0) tab.push_back(v);
-        for (int32_t v : x1) tab.push_back(v);
-        ref->nblocks = acc;
-        fix.push_back({ref, off});
-    };
-    std::vector<int32_t> all(ng), zero(ng, 0), nb(ng);
-    for (int32_t i = 0; i < ng; ++i) all[i] = i;
-    auto per = [&](auto f) {
-        for (int32_t i = 0; i < ng; ++i) nb[i] = f(members[i]->dm);
-        return nb;
-    };
-    add(&L.predict, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.nv); }), zero, zero);
-    add(&L.local, all, per([](const vh::DevMesh& d) { return vh::blocks_tets(d.nt); }), zero, zero);
-    add(&L.residual, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.n_free); }), zero, zero);
-    add(&L.refine, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.n_free); }), zero, zero);
-    add(&L.velocity, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.nv); }), zero, zero);
-    add(&L.ifwd, all, per([](const vh::DevMesh& d) { return d.D; }), zero, zero);
-    add(&L.ibwd, all, per([](const vh::DevMesh& d) { return d.D; }), zero, zero);
-    // interface phases: phase j of every garment in one launch per lane-group size
-    auto phases = [&](bool fwd, std::vector<CoarseLaunch>& out) {
-        size_t nj = 0;
-        for (vh_mesh* m : members) nj = std::max(nj, (fwd ? m->plan.cfwd : m->plan.cbwd).size());
-        out.reserve(2 * nj);
-        for (size_t j = 0; j < nj; ++j)
-            for (int32_t grp : {16, 64}) {
-                std::vector<int32_t> g, b, x0, x1;
-                int32_t kind = -1;
-                for (int32_t i = 0; i < ng; ++i) {
-                    const auto& ph = fwd ? members[i]->plan.cfwd : members[i]->plan.cbwd;
-                    if (j >= ph.size() || ph[j].group != grp) continue;
-                    kind = ph[j].kind;
-                    g.push_back(i);
-                    b.push_back(vh::coarse_blocks(ph[j].ntasks, grp));
-                    x0.push_back(ph[j].task0);
-                    x1.push_back(ph[j].ntasks);
-                }
-                if (g.empty()) continue;
-                out.push_back(CoarseLaunch{});
-                out.back().kind = kind;
-                out.back().group = grp;
-                add(&out.back().ref, g, b, x0, x1);
-            }
-    };
-    phases(true, L.cfwd);
-    phases(false, L.cbwd);
-    // device copies
-    std::vector<vh::DevMesh> G(ng);
-    int32_t max_n = 1, max_nb = 0, max_cint = 0;
-    for (int32_t i = 0; i < ng; ++i) {
-        G[i] = members[i]->dm;
-        max_n = std::max(max_n, G[i].max_sub_n);
-        max_nb = std::max(max_nb, G[i].max_nb);
-        max_cint = std::max(max_cint, G[i].max_cint);
     }
-    // every garment of a launch carves LDS with its own sizes inside the batch maximum
-    for (auto& d : G) {
-        d.max_sub_n = max_n;
-        d.max_nb = max_nb;
-        d.max_cint = max_cint;
-    }
-    L.lds_fwd = vh::interior_fwd_lds(max_n, max_cint);
-    L.lds_bwd = vh::interior_bwd_lds(max_n, max_nb);
-    const size_t need = sizeof(vh::DevMesh) * ng + sizeof(int32_t) * (tab.size() + ng);
-    if (ctx->budget && ctx->in_use + need > ctx->budget) return fail(VH_ENOMEM, "HBM budget exceeded");
-    VH_HIP(hipMalloc(&L.G, sizeof(vh::DevMesh) * ng));
-    VH_HIP(hipMalloc(&L.tables, sizeof(int32_t) * tab.size()));
-    VH_HIP(hipMalloc(&L.active, sizeof(int32_t) * ng));
-    L.bytes = need;
-    VH_HIP(hipMemcpy(L.G, G.data(), sizeof(vh::DevMesh) * ng, hipMemcpyHostToDevice));
-    VH_HIP(hipMemcpy(L.tables, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice));
-    std::vector<int32_t> ones(ng, 1);
-    VH_HIP(hipMemcpy(L.active, ones.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice));
-    for (auto& f : fix) {
-        f.first->G = L.G;
-        f.first->L = L.tables + f.second;
-        f.first->active = L.active;
-    }
-    return VH_OK;
+    chk(upload(m, &d.blk_part, P.blk_part));
+    chk(upload(m, &d.part_pack, P.part_pack));
+    chk(dalloc(m, &d.part, (size_t)std::max<int32_t>(P.blk_part.back(), 1)));
+    chk(upload(m, &d.vpart_ptr, P.vpart_ptr));
+    chk(upload(m, &d.vpart, P.vpart));
+    chk(dalloc(m, &d.r, (size_t)P.n_free * 3));
+    chk(dalloc(m, &d.zf, (size_t)P.n_int * 3));
+    chk(dalloc(m, &d.rg, (size_t)P.n_gamma * 3));
+    chk(dalloc(m, &d.zg, (size_t)P.n_gamma * 3));
+    chk(dalloc(m, &d.dg, (size_t)P.n_gamma * 3));
+    chk(dalloc(m, &d.delta, (size_t)P.n_free * 3));
+    chk(upload(m, &d.sub_off, P.sub_off));
+    chk(upload(m, &d.chunks, P.chunks));
+    chk(upload(m, &d.sub_fwd_ch, P.sub_fwd_ch));
+    chk(upload(m, &d.sub_bwd_ch, P.sub_bwd_ch));
+    chk(upload(m, &d.ivals, P.ivals));
+    chk(upload(m, &d.bnd, P.bnd));
+    chk(upload(m, &d.bnd_off, P.bnd_off));
+    chk(upload(m, &d.dvals, P.dvals));
+    chk(upload(m, &d.ctasks, P.ctasks));
+    chk(upload(m, &d.cslots, P.cslots));
+    chk(upload(m, &d.cgidx, P.cgidx));
+    chk(dalloc(m, &d.cgf, (size_t)P.n_cgf * 3));
+    chk(dalloc(m, &d.cgd, (size_t)P.n_cgd * 3));
+    chk(upload(m, &d.K_ptr, P.K_ptr));
+    chk(upload(m, &d.K_col, P.K_col));
+    chk(upload(m, &d.K_val, P.K_val));
+    chk(dalloc(m, &d.flags, 4));
+    return r;
 }
 
-int set_device(vh_mesh* m) {
-    VH_HIP(hipSetDevice(m->ctx->device));
-    return VH_OK;
+// device bytes of the launch tables of a batch of ng garments with the given
+// per-garment phase counts (an upper bound on build_launch_set's allocation)
+size_t launch_set_bytes(int32_t ng, size_t coarse_phases) {
+    const size_t tab = 7 * (size_t)(4 * ng + 2) + 2 * coarse_phases * (size_t)(4 * ng + 2);
+    return sizeof(vh::DevMesh) * ng + sizeof(int32_t) * (tab + ng);
 }
 
 int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta) {
@@ -332,49 +209,24 @@ int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s) {
     return VH_OK;
 }
 
-// One frame over the launch set; m (may be null) receives per-class timing.
-int frame_direct(vh_mesh* m, const LaunchSet& L, hipStream_t s) {
-    {
-        ProfScope ps(m, s, 0);
-        VH_HIP(vh::launch_predictor(L.predict, s));
-    }
-    for (int32_t k = 0; k < L.pd_iters; ++k) VH_TRY(pd_iteration(m, L, s));
-    {
-        ProfScope ps(m, s, 7);
-        VH_HIP(vh::launch_velocity(L.velocity, s));
-    }
-    return VH_OK;
-}
-
-// Capture one frame (predictor, pd_iters x [local, residual, solve], velocity)
-// into an executable graph on a private stream.
-int ensure_graph(vh_mesh* m) {
-    if (m->gexec) return VH_OK;
-    if (!m->cap) VH_HIP(hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking));
-    const uint32_t mask = m->prof_mask;
-    m->prof_mask = 0;
-    VH_HIP(hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal));
-    int rc = frame_direct(m, m->ls, m->cap);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(m->cap, &g);
-    m->prof_mask = mask;
-    if (rc != VH_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        return rc;
-    }
-    if (e != hipSuccess) return fail(VH_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&m->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        m->gexec = nullptr;
-        return fail(VH_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    }
-    return VH_OK;
-}
-
 int check_ready(vh_mesh* m) {
     if (!m) return fail(VH_EINVAL, "null mesh");
     if (!m->factored) return fail(VH_ESTATE, "mesh is not prefactored");
+    return VH_OK;
+}
+
+// check_ready plus: no server frames of this mesh pending
+int check_quiet(vh_mesh* m) {
+    VH_TRY(check_ready(m));
+    return server_check_idle(m);
+}
+
+// check_ready plus: the mesh is not driven by the context's server (whose
+// stream the caller's launches would not be ordered against)
+int check_solo(vh_mesh* m) {
+    VH_TRY(check_ready(m));
+    if (m->srv_id >= 0 && m->ctx->srv)
+        return fail(VH_ESTATE, "mesh is driven by the server; release it first");
     return VH_OK;
 }
 
@@ -393,6 +245,198 @@ int put_user(vh_mesh* m, const double* host, double* dev_int, bool positions, hi
     return VH_OK;
 }
 
+}  // namespace
+
+int set_device(vh_mesh* m) {
+    VH_HIP(hipSetDevice(m->ctx->device));
+    return VH_OK;
+}
+
+void free_launch_set(vh_ctx* ctx, LaunchSet& L) {
+    if (L.G) (void)hipFree(L.G);
+    if (L.tables) (void)hipFree(L.tables);
+    if (L.active) (void)hipFree(L.active);
+    if (ctx) uncharge(ctx, L.bytes);
+    L = LaunchSet();
+}
+
+void free_device(vh_mesh* m) {
+    if (m->gexec) {
+        (void)hipGraphExecDestroy(m->gexec);
+        m->gexec = nullptr;
+    }
+    free_launch_set(m->ctx, m->ls);
+    for (void* p : m->allocs) (void)hipFree(p);
+    m->allocs.clear();
+    if (m->ctx) uncharge(m->ctx, m->bytes);
+    m->bytes = 0;
+    m->dm = vh::DevMesh();
+    m->factored = false;
+}
+
+int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSet& L, bool check_budget) {
+    free_launch_set(ctx, L);
+    const int32_t ng = (int32_t)members.size();
+    if (ng == 0) return fail(VH_EINVAL, "empty launch set");
+    L.pd_iters = members[0]->plan.pd_iters;
+    L.refine_steps = members[0]->refine;
+    for (vh_mesh* m : members)
+        if (m->plan.pd_iters != L.pd_iters || m->refine != L.refine_steps)
+            return fail(VH_EINVAL, "garments in one batch need equal pd_iters and refine steps");
+    std::vector<int32_t> tab;
+    std::vector<std::pair<vh::LaunchRef*, size_t>> fix;   // ref -> table offset
+    // per-garment blocks and parameters -> one table
+    auto add = [&](vh::LaunchRef* ref, const std::vector<int32_t>& gids, const std::vector<int32_t>& nb,
+                   const std::vector<int32_t>& x0, const std::vector<int32_t>& x1) {
+        const size_t off = tab.size();
+        const int32_t n = (int32_t)gids.size();
+        tab.push_back(n);
+        int32_t acc = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            tab.push_back(acc);
+            acc += nb[i];
+        }
+        tab.push_back(acc);
+        for (int32_t v : gids) tab.push_back(v);
+        for (int32_t v : x0) tab.push_back(v);
+        for (int32_t v : x1) tab.push_back(v);
+        ref->nblocks = acc;
+        fix.push_back({ref, off});
+    };
+    std::vector<int32_t> all(ng), zero(ng, 0), nb(ng);
+    for (int32_t i = 0; i < ng; ++i) all[i] = i;
+    auto per = [&](auto f) {
+        for (int32_t i = 0; i < ng; ++i) nb[i] = f(members[i]->dm);
+        return nb;
+    };
+    add(&L.predict, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.nv); }), zero, zero);
+    add(&L.local, all, per([](const vh::DevMesh& d) { return vh::blocks_tets(d.nt); }), zero, zero);
+    add(&L.residual, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.n_free); }), zero, zero);
+    add(&L.refine, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.n_free); }), zero, zero);
+    add(&L.velocity, all, per([](const vh::DevMesh& d) { return vh::blocks_vertices(d.nv); }), zero, zero);
+    add(&L.ifwd, all, per([](const vh::DevMesh& d) { return d.D; }), zero, zero);
+    add(&L.ibwd, all, per([](const vh::DevMesh& d) { return d.D; }), zero, zero);
+    // interface phases: phase j of every garment whose phase j has the same
+    // task kind and lane-group size goes into one launch; each garment's
+    // phases stay in their order
+    auto phases = [&](bool fwd, std::vector<CoarseLaunch>& out) {
+        size_t nj = 0;
+        for (vh_mesh* m : members) nj = std::max(nj, (fwd ? m->plan.cfwd : m->plan.cbwd).size());
+        out.reserve(2 * nj);
+        for (size_t j = 0; j < nj; ++j)
+            for (int32_t kind : {(int32_t)vh::PULLSUM, (int32_t)vh::GEMV, (int32_t)vh::BGEMV})
+                for (int32_t grp : {16, 64}) {
+                    std::vector<int32_t> g, b, x0, x1;
+                    for (int32_t i = 0; i < ng; ++i) {
+                        const auto& ph = fwd ? members[i]->plan.cfwd : members[i]->plan.cbwd;
+                        if (j >= ph.size() || ph[j].group != grp || ph[j].kind != kind) continue;
+                        g.push_back(i);
+                        b.push_back(vh::coarse_blocks(ph[j].ntasks, grp));
+                        x0.push_back(ph[j].task0);
+                        x1.push_back(ph[j].ntasks);
+                    }
+                    if (g.empty()) continue;
+                    out.push_back(CoarseLaunch{});
+                    out.back().kind = kind;
+                    out.back().group = grp;
+                    add(&out.back().ref, g, b, x0, x1);
+                }
+    };
+    phases(true, L.cfwd);
+    phases(false, L.cbwd);
+    // device copies
+    std::vector<vh::DevMesh> G(ng);
+    int32_t max_n = 1, max_nb = 0, max_cint = 0;
+    for (int32_t i = 0; i < ng; ++i) {
+        G[i] = members[i]->dm;
+        max_n = std::max(max_n, G[i].max_sub_n);
+        max_nb = std::max(max_nb, G[i].max_nb);
+        max_cint = std::max(max_cint, G[i].max_cint);
+    }
+    // every garment of a launch carves LDS with its own sizes inside the batch maximum
+    for (auto& d : G) {
+        d.max_sub_n = max_n;
+        d.max_nb = max_nb;
+        d.max_cint = max_cint;
+    }
+    L.lds_fwd = vh::interior_fwd_lds(max_n, max_cint);
+    L.lds_bwd = vh::interior_bwd_lds(max_n, max_nb);
+    {
+        int lds_limit = 0;
+        VH_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+        const size_t lds_need = std::max(L.lds_fwd, L.lds_bwd);
+        if (lds_need > (size_t)lds_limit)
+            return fail(VH_EINVAL, "a subdomain needs " + std::to_string(lds_need) + " bytes of LDS (limit " +
+                                       std::to_string(lds_limit) + "); use more subdomains");
+        // the attribute only grows, so launches of smaller sets stay valid
+        static size_t lds_set[64] = {};
+        size_t& cur = lds_set[ctx->device & 63];
+        if (lds_need > std::max<size_t>(cur, 65536)) {
+            VH_HIP(vh::interior_set_lds_limit(lds_need));
+            cur = lds_need;
+        }
+    }
+    const size_t need = sizeof(vh::DevMesh) * ng + sizeof(int32_t) * (tab.size() + ng);
+    if (check_budget && ctx->budget && ctx->in_use + need > ctx->budget)
+        return fail(VH_ENOMEM, "HBM budget exceeded");
+    L.ng = ng;
+    VH_HIP(hipMalloc(&L.G, sizeof(vh::DevMesh) * ng));
+    VH_HIP(hipMalloc(&L.tables, sizeof(int32_t) * tab.size()));
+    VH_HIP(hipMalloc(&L.active, sizeof(int32_t) * ng));
+    L.bytes = need;
+    charge(ctx, need);
+    VH_HIP(hipMemcpy(L.G, G.data(), sizeof(vh::DevMesh) * ng, hipMemcpyHostToDevice));
+    VH_HIP(hipMemcpy(L.tables, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice));
+    std::vector<int32_t> ones(ng, 1);
+    VH_HIP(hipMemcpy(L.active, ones.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice));
+    for (auto& f : fix) {
+        f.first->G = L.G;
+        f.first->L = L.tables + f.second;
+        f.first->active = L.active;
+    }
+    return VH_OK;
+}
+
+int frame_direct(vh_mesh* m, const LaunchSet& L, hipStream_t s) {
+    {
+        ProfScope ps(m, s, 0);
+        VH_HIP(vh::launch_predictor(L.predict, s));
+    }
+    for (int32_t k = 0; k < L.pd_iters; ++k) VH_TRY(pd_iteration(m, L, s));
+    {
+        ProfScope ps(m, s, 7);
+        VH_HIP(vh::launch_velocity(L.velocity, s));
+    }
+    return VH_OK;
+}
+
+int capture_frame(const LaunchSet& L, hipStream_t* cap, hipGraphExec_t* out) {
+    if (!*cap) VH_HIP(hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
+    VH_HIP(hipStreamBeginCapture(*cap, hipStreamCaptureModeThreadLocal));
+    int rc = frame_direct(nullptr, L, *cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(*cap, &g);
+    if (rc != VH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(VH_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return fail(VH_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    return VH_OK;
+}
+
+// Capture one frame (predictor, pd_iters x [local, residual, solve], velocity)
+// into an executable graph on a private stream.
+int ensure_graph(vh_mesh* m) {
+    if (m->gexec) return VH_OK;
+    return capture_frame(m->ls, &m->cap, &m->gexec);
+}
+
 int get_user(vh_mesh* m, const double* dev_int, double* host, int32_t rows, hipStream_t s) {
     const vh::Plan& P = m->plan;
     std::vector<double>& st = m->stage;
@@ -408,11 +452,94 @@ int get_user(vh_mesh* m, const double* dev_int, double* host, int32_t rows, hipS
     return VH_OK;
 }
 
-}  // namespace
+int host_factor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
+    if (!m->has_params) return fail(VH_ESTATE, "set_params must precede prefactor");
+    if (refine_steps < 0) return fail(VH_EINVAL, "refine_steps must be >= 0");
+    m->planned = false;
+    std::string msg;
+    int rc = vh::build_plan(m->X.data(), m->nv, m->tets.data(), m->nt, m->gs.data(), m->gv.data(),
+                            m->mass.data(), m->pinned.data(), m->g, m->dt, m->iters, n_subdomains,
+                            refine_steps, 32, vh::interior_chunk_words(), m->plan, msg);
+    if (rc != 0) return fail(rc, msg);
+    // the interior kernels hold two LDS chunks (48 KB each) next to the
+    // subdomain's vectors: gfx950 gives a workgroup up to 160 KB
+    int lds_limit = 0;
+    VH_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, m->ctx->device));
+    const vh::Plan& P = m->plan;
+    const size_t lds_need = std::max(vh::interior_fwd_lds(std::max(P.max_sub_n, 1), P.max_cint),
+                                     vh::interior_bwd_lds(std::max(P.max_sub_n, 1), P.max_nb));
+    if (lds_need > (size_t)lds_limit)
+        return fail(VH_EINVAL, "a subdomain needs " + std::to_string(lds_need) + " bytes of LDS (limit " +
+                                   std::to_string(lds_limit) + "); use more subdomains");
+    m->refine = refine_steps;
+    m->planned = true;
+    return VH_OK;
+}
+
+int device_need(vh_mesh* m, size_t* bytes) {
+    if (!m->planned) return fail(VH_ESTATE, "mesh has no host factorization");
+    m->dry = true;
+    m->dry_bytes = 0;
+    vh::DevMesh keep = m->dm;
+    int rc = alloc_plan(m);
+    m->dm = keep;
+    m->dry = false;
+    if (rc != VH_OK) return rc;
+    *bytes = m->dry_bytes + launch_set_bytes(1, std::max(m->plan.cfwd.size(), m->plan.cbwd.size()) * 2);
+    return VH_OK;
+}
+
+int upload_device(vh_mesh* m) {
+    if (!m->planned) return fail(VH_ESTATE, "mesh has no host factorization");
+    VH_TRY(set_device(m));
+    free_device(m);
+    const vh::Plan& P = m->plan;
+    vh::DevMesh& d = m->dm;
+    d.nv = P.nv;
+    d.nt = P.nt;
+    d.n_free = P.n_free;
+    d.n_int = P.n_int;
+    d.n_gamma = P.n_gamma;
+    d.D = P.D;
+    d.max_sub_n = std::max(P.max_sub_n, 1);
+    d.max_nb = P.max_nb;
+    d.max_cint = P.max_cint;
+    d.dt = P.dt;
+    for (int c = 0; c < 3; ++c) d.g[c] = P.gravity[c];
+    int r = alloc_plan(m);
+    if (r != VH_OK) {
+        free_device(m);
+        return r;
+    }
+    const size_t nv3 = (size_t)P.nv * 3;
+    VH_HIP(hipMemset(d.v, 0, nv3 * sizeof(double)));
+    VH_HIP(hipMemset(d.flags, 0, 4 * sizeof(uint32_t)));
+    VH_HIP(hipMemset(d.delta, 0, (size_t)P.n_free * 3 * sizeof(double)));
+    {
+        std::vector<vh_mesh*> one{m};
+        int lrc = build_launch_set(m->ctx, one, m->ls, true);
+        if (lrc != VH_OK) {
+            free_device(m);
+            return lrc;
+        }
+    }
+    const char* ng = std::getenv("VHPD_NO_GRAPH");
+    m->use_graph = !(ng && ng[0] == '1');
+    VH_HIP(vh::launch_refresh_u(d, nullptr));
+    VH_HIP(hipDeviceSynchronize());
+    m->has_saved = false;
+    m->factored = true;
+    return VH_OK;
+}
+
+}  // namespace vhrt
+
+using namespace vhrt;
+
 
 extern "C" {
 
-const char* vh_last_error(void) { return g_err.c_str(); }
+const char* vh_last_error(void) { return last_error(); }
 
 int vh_ctx_create(vh_ctx** out, int device, size_t hbm_budget_bytes) {
     if (!out) return fail(VH_EINVAL, "null output handle");
@@ -429,9 +556,17 @@ int vh_ctx_create(vh_ctx** out, int device, size_t hbm_budget_bytes) {
 
 int vh_ctx_destroy(vh_ctx* ctx) {
     if (!ctx) return VH_OK;
+    (void)hipSetDevice(ctx->device);
+    server_destroy(ctx);
     std::vector<vh_mesh*> ms = ctx->meshes;
     for (vh_mesh* m : ms) vh_mesh_destroy(m);
     delete ctx;
+    return VH_OK;
+}
+
+int vh_ctx_set_hbm_budget(vh_ctx* ctx, size_t hbm_budget_bytes) {
+    if (!ctx) return fail(VH_EINVAL, "null context");
+    ctx->budget = hbm_budget_bytes;
     return VH_OK;
 }
 
@@ -459,6 +594,8 @@ int vh_mesh_create(vh_ctx* ctx, vh_mesh** out, const double* rest_xyz, int32_t n
 
 int vh_mesh_destroy(vh_mesh* m) {
     if (!m) return VH_OK;
+    if (m->ctx && m->srv_id >= 0 && m->ctx->srv)
+        return fail(VH_ESTATE, "mesh is still in the server; release it first");
     if (m->ctx) {
         (void)hipSetDevice(m->ctx->device);
         release_events(m);
@@ -486,10 +623,13 @@ int vh_mesh_set_params(vh_mesh* m, const double* gamma_s, const double* gamma_v,
             return fail(VH_EINVAL, "mass must be > 0 on free vertex " + std::to_string(v));
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(gravity[c])) return fail(VH_EINVAL, "gravity must be finite");
+    if (m->srv_id >= 0 && m->ctx->srv) return fail(VH_ESTATE, "mesh is in the server; release it first");
     if (m->factored) {
         (void)hipSetDevice(m->ctx->device);
         free_device(m);
     }
+    m->planned = false;
+    m->has_saved = false;
     m->gs.assign(gamma_s, gamma_s + m->nt);
     m->gv.assign(gamma_v, gamma_v + m->nt);
     m->mass.assign(mass, mass + m->nv);
@@ -503,116 +643,15 @@ int vh_mesh_set_params(vh_mesh* m, const double* gamma_s, const double* gamma_v,
 
 int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     if (!m) return fail(VH_EINVAL, "null mesh");
-    if (!m->has_params) return fail(VH_ESTATE, "set_params must precede prefactor");
-    if (refine_steps < 0) return fail(VH_EINVAL, "refine_steps must be >= 0");
+    if (m->srv_id >= 0 && m->ctx->srv) return fail(VH_ESTATE, "mesh is in the server; release it first");
     VH_TRY(set_device(m));
     free_device(m);
-    // the interior kernels hold two LDS chunks (48 KB each) next to the
-    // subdomain's vectors: gfx950 gives a workgroup up to 160 KB
-    int lds_limit = 0;
-    VH_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock,
-                                 m->ctx->device));
-    std::string msg;
-    int rc = vh::build_plan(m->X.data(), m->nv, m->tets.data(), m->nt, m->gs.data(), m->gv.data(),
-                            m->mass.data(), m->pinned.data(), m->g, m->dt, m->iters, n_subdomains,
-                            refine_steps, 32, vh::interior_chunk_words(), m->plan, msg);
-    if (rc != 0) return fail(rc, msg);
-    const vh::Plan& P = m->plan;
-    vh::DevMesh& d = m->dm;
-    d.nv = P.nv;
-    d.nt = P.nt;
-    d.n_free = P.n_free;
-    d.n_int = P.n_int;
-    d.n_gamma = P.n_gamma;
-    d.D = P.D;
-    d.max_sub_n = std::max(P.max_sub_n, 1);
-    d.max_nb = P.max_nb;
-    d.max_cint = P.max_cint;
-    const size_t lds_need = std::max(vh::interior_fwd_lds(d.max_sub_n, d.max_cint),
-                                     vh::interior_bwd_lds(d.max_sub_n, d.max_nb));
-    if (lds_need > (size_t)lds_limit)
-        return fail(VH_EINVAL, "a subdomain needs " + std::to_string(lds_need) +
-                                   " bytes of LDS (limit " + std::to_string(lds_limit) +
-                                   "); use more subdomains");
-    if (lds_need > 65536) VH_HIP(vh::interior_set_lds_limit(lds_need));
-    d.dt = P.dt;
-    for (int c = 0; c < 3; ++c) d.g[c] = P.gravity[c];
-    const size_t nv3 = (size_t)P.nv * 3;
-    int r = VH_OK;
-    auto chk = [&](int x) {
-        if (r == VH_OK) r = x;
-    };
-    chk(upload(m, &d.X, P.X_int));
-    chk(upload(m, &d.x, P.X_int));
-    chk(dalloc(m, &d.v, nv3));
-    chk(dalloc(m, &d.xprev, nv3));
-    chk(dalloc(m, &d.y, nv3));
-    chk(upload(m, &d.mass, P.mass_int));
-    chk(upload(m, &d.perm, P.perm));
-    chk(dalloc(m, &d.u, (size_t)P.nv));
-    {
-        std::vector<float4> tr((size_t)P.nt * 4);
-        std::memcpy(tr.data(), P.trec.data(), P.trec.size() * sizeof(float));
-        chk(upload(m, &d.trec, tr));
-        std::vector<uint2> lp((size_t)P.nt);
-        std::memcpy(lp.data(), P.lpos.data(), P.lpos.size() * sizeof(uint16_t));
-        chk(upload(m, &d.lpos, lp));
-    }
-    chk(upload(m, &d.blk_part, P.blk_part));
-    chk(upload(m, &d.part_pack, P.part_pack));
-    chk(dalloc(m, &d.part, (size_t)std::max<int32_t>(P.blk_part.back(), 1)));
-    chk(upload(m, &d.vpart_ptr, P.vpart_ptr));
-    chk(upload(m, &d.vpart, P.vpart));
-    chk(dalloc(m, &d.r, (size_t)P.n_free * 3));
-    chk(dalloc(m, &d.zf, (size_t)P.n_int * 3));
-    chk(dalloc(m, &d.rg, (size_t)P.n_gamma * 3));
-    chk(dalloc(m, &d.zg, (size_t)P.n_gamma * 3));
-    chk(dalloc(m, &d.dg, (size_t)P.n_gamma * 3));
-    chk(dalloc(m, &d.delta, (size_t)P.n_free * 3));
-    chk(upload(m, &d.sub_off, P.sub_off));
-    chk(upload(m, &d.chunks, P.chunks));
-    chk(upload(m, &d.sub_fwd_ch, P.sub_fwd_ch));
-    chk(upload(m, &d.sub_bwd_ch, P.sub_bwd_ch));
-    chk(upload(m, &d.ivals, P.ivals));
-    chk(upload(m, &d.bnd, P.bnd));
-    chk(upload(m, &d.bnd_off, P.bnd_off));
-    chk(upload(m, &d.dvals, P.dvals));
-    chk(upload(m, &d.ctasks, P.ctasks));
-    chk(upload(m, &d.cslots, P.cslots));
-    chk(upload(m, &d.cgidx, P.cgidx));
-    chk(dalloc(m, &d.cgf, (size_t)P.n_cgf * 3));
-    chk(dalloc(m, &d.cgd, (size_t)P.n_cgd * 3));
-    chk(upload(m, &d.K_ptr, P.K_ptr));
-    chk(upload(m, &d.K_col, P.K_col));
-    chk(upload(m, &d.K_val, P.K_val));
-    chk(dalloc(m, &d.flags, 4));
-    if (r != VH_OK) {
-        free_device(m);
-        return r;
-    }
-    VH_HIP(hipMemset(d.v, 0, nv3 * sizeof(double)));
-    VH_HIP(hipMemset(d.flags, 0, 4 * sizeof(uint32_t)));
-    VH_HIP(hipMemset(d.delta, 0, (size_t)P.n_free * 3 * sizeof(double)));
-    m->refine = refine_steps;
-    {
-        std::vector<vh_mesh*> one{m};
-        int lrc = build_launch_set(m->ctx, one, m->ls);
-        if (lrc != VH_OK) {
-            free_device(m);
-            return lrc;
-        }
-        m->ctx->in_use += m->ls.bytes;
-    }
-    const char* ng = std::getenv("VHPD_NO_GRAPH");
-    m->use_graph = !(ng && ng[0] == '1');
-    VH_HIP(vh::launch_refresh_u(d, nullptr));
-    VH_HIP(hipDeviceSynchronize());
-    m->factored = true;
-    return VH_OK;
+    VH_TRY(host_factor(m, n_subdomains, refine_steps));
+    return upload_device(m);
 }
 
 int vh_mesh_step(vh_mesh* m, int32_t n_frames, void* stream) {
-    VH_TRY(check_ready(m));
+    VH_TRY(check_solo(m));
     if (n_frames < 0) return fail(VH_EINVAL, "n_frames must be >= 0");
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -626,8 +665,14 @@ int vh_mesh_step(vh_mesh* m, int32_t n_frames, void* stream) {
 }
 
 int vh_mesh_read_state(vh_mesh* m, double* x, double* v, void* stream) {
-    VH_TRY(check_ready(m));
+    if (!m) return fail(VH_EINVAL, "null mesh");
     if (!x && !v) return fail(VH_EINVAL, "null output arrays");
+    if (!m->factored && m->has_saved) {
+        if (x) std::copy(m->saved_x.begin(), m->saved_x.end(), x);
+        if (v) std::copy(m->saved_v.begin(), m->saved_v.end(), v);
+        return VH_OK;
+    }
+    VH_TRY(check_quiet(m));
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (x) VH_TRY(get_user(m, m->dm.x, x, m->plan.nv, s));
@@ -639,7 +684,7 @@ int vh_mesh_read_state(vh_mesh* m, double* x, double* v, void* stream) {
 }
 
 int vh_mesh_write_state(vh_mesh* m, const double* x, const double* v, void* stream) {
-    VH_TRY(check_ready(m));
+    VH_TRY(check_quiet(m));
     if (!x || !v) return fail(VH_EINVAL, "null input arrays");
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -652,22 +697,24 @@ int vh_mesh_write_state(vh_mesh* m, const double* x, const double* v, void* stre
 }
 
 int vh_mesh_read_state_device(vh_mesh* m, double* x_dev, double* v_dev, void* stream) {
-    VH_TRY(check_ready(m));
+    VH_TRY(check_quiet(m));
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (x_dev) VH_HIP(vh::launch_to_user(m->dm.nv, m->dm.perm, m->dm.x, x_dev, s));
     if (v_dev) VH_HIP(vh::launch_to_user(m->dm.nv, m->dm.perm, m->dm.v, v_dev, s));
+    if (m->srv_id >= 0) VH_HIP(hipStreamSynchronize(s));   // ordered before the server's next frame
     return VH_OK;
 }
 
 int vh_mesh_write_state_device(vh_mesh* m, const double* x_dev, const double* v_dev, void* stream) {
-    VH_TRY(check_ready(m));
+    VH_TRY(check_quiet(m));
     if (!x_dev || !v_dev) return fail(VH_EINVAL, "null input arrays");
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
     VH_HIP(vh::launch_from_user(m->dm.nv, m->dm.n_free, m->dm.perm, x_dev, m->dm.X, m->dm.x, s));
     VH_HIP(vh::launch_from_user(m->dm.nv, m->dm.n_free, m->dm.perm, v_dev, nullptr, m->dm.v, s));
     VH_HIP(vh::launch_refresh_u(m->dm, s));
+    if (m->srv_id >= 0) VH_HIP(hipStreamSynchronize(s));   // ordered before the server's next frame
     return VH_OK;
 }
 
@@ -710,7 +757,7 @@ int vh_mesh_get_info(const vh_mesh* m, vh_mesh_info* info) {
 }
 
 int vh_debug_local_step(vh_mesh* m, const double* x, double* T, double* sigma, double* s_out) {
-    VH_TRY(check_ready(m));
+    VH_TRY(check_solo(m));
     if (!x || !T) return fail(VH_EINVAL, "null argument");
     VH_TRY(set_device(m));
     vh::DevMesh& d = m->dm;
@@ -742,7 +789,7 @@ int vh_debug_local_step(vh_mesh* m, const double* x, double* T, double* sigma, d
 }
 
 int vh_debug_residual(vh_mesh* m, const double* x, const double* y, double* r) {
-    VH_TRY(check_ready(m));
+    VH_TRY(check_solo(m));
     if (!x || !y || !r) return fail(VH_EINVAL, "null argument");
     VH_TRY(set_device(m));
     vh::DevMesh& d = m->dm;
@@ -756,7 +803,7 @@ int vh_debug_residual(vh_mesh* m, const double* x, const double* y, double* r) {
 }
 
 int vh_debug_solve(vh_mesh* m, const double* rhs, double* out) {
-    VH_TRY(check_ready(m));
+    VH_TRY(check_solo(m));
     if (!rhs || !out) return fail(VH_EINVAL, "null argument");
     VH_TRY(set_device(m));
     vh::DevMesh& d = m->dm;
@@ -771,7 +818,7 @@ int vh_debug_solve(vh_mesh* m, const double* rhs, double* out) {
 }
 
 int vh_mesh_time_kernel(vh_mesh* m, int32_t kernel_class, int32_t reps, void* stream) {
-    VH_TRY(check_ready(m));
+    VH_TRY(check_solo(m));
     if (reps < 1) return fail(VH_EINVAL, "reps must be >= 1");
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -792,7 +839,7 @@ int vh_mesh_time_kernel(vh_mesh* m, int32_t kernel_class, int32_t reps, void* st
 }
 
 int vh_mesh_profile(vh_mesh* m, uint32_t class_mask) {
-    VH_TRY(check_ready(m));
+    VH_TRY(check_solo(m));
     VH_TRY(set_device(m));
     m->prof_mask = class_mask & 0xFFu;
     m->ev_used = 0;

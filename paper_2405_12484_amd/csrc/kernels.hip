@@ -461,20 +461,28 @@ constexpr int BLKI = 1024;
 constexpr int NV4I = 3;                       // float4 per thread per chunk
 constexpr int32_t CHI = NV4I * 4 * BLKI;      // chunk capacity in 32-bit words (48 KB)
 
-// Coalesced copy of one chunk (nv4 float4) into registers / LDS.
-__device__ __forceinline__ void chunk_load(const float4* __restrict__ src, int32_t nv4, float4 (&reg)[NV4I]) {
-#pragma unroll
-    for (int i = 0; i < NV4I; ++i) {
-        const int32_t j = threadIdx.x + i * BLKI;
-        if (j < nv4) reg[i] = src[j];
-    }
+// Coalesced copy of one chunk (nv4 float4) into registers / LDS.  Three
+// named registers rather than an array: the array ends up in scratch memory.
+static_assert(NV4I == 3, "chunk staging holds three float4 per thread");
+struct ChunkRegs {
+    float a0, a1, a2, a3, b0, b1, b2, b3, c0, c1, c2, c3;
+};
+// Loads are unconditional (indices clamped into the chunk, nv4 >= 1) so the
+// registers are always defined; only the stores are predicated.
+__device__ __forceinline__ void chunk_load(const float4* __restrict__ src, int32_t nv4, ChunkRegs& reg) {
+    const int32_t j = threadIdx.x, last = nv4 - 1;
+    float4 t = src[min(j, last)];
+    reg.a0 = t.x; reg.a1 = t.y; reg.a2 = t.z; reg.a3 = t.w;
+    t = src[min(j + BLKI, last)];
+    reg.b0 = t.x; reg.b1 = t.y; reg.b2 = t.z; reg.b3 = t.w;
+    t = src[min(j + 2 * BLKI, last)];
+    reg.c0 = t.x; reg.c1 = t.y; reg.c2 = t.z; reg.c3 = t.w;
 }
-__device__ __forceinline__ void chunk_store(float4* dst, int32_t nv4, const float4 (&reg)[NV4I]) {
-#pragma unroll
-    for (int i = 0; i < NV4I; ++i) {
-        const int32_t j = threadIdx.x + i * BLKI;
-        if (j < nv4) dst[j] = reg[i];
-    }
+__device__ __forceinline__ void chunk_store(float4* dst, int32_t nv4, const ChunkRegs& reg) {
+    const int32_t j = threadIdx.x;
+    if (j < nv4) dst[j] = make_float4(reg.a0, reg.a1, reg.a2, reg.a3);
+    if (j + BLKI < nv4) dst[j + BLKI] = make_float4(reg.b0, reg.b1, reg.b2, reg.b3);
+    if (j + 2 * BLKI < nv4) dst[j + 2 * BLKI] = make_float4(reg.c0, reg.c1, reg.c2, reg.c3);
 }
 
 // Interior forward solve.  Per supernode level: PULLSUM (thread per row)
@@ -491,7 +499,6 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
     const SolveArgs a = solve_args(GM[sl.g]);
     extern __shared__ float4 sm4[];
     float* sm = reinterpret_cast<float*>(sm4);
-    float* bufs[2] = {sm, sm + CHI};
     float* R = sm + 2 * CHI;
     float* Z = R + 3 * a.max_n;
     float* C = Z + 3 * a.max_n;
@@ -502,18 +509,18 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
     for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)a.r[3 * base + i];
     const int32_t c0 = a.sub_fwd_ch[d], c1 = a.sub_fwd_ch[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
-    float4 reg[NV4I];
+    ChunkRegs reg;
     if (c0 < c1) {
         const Chunk K = a.chunks[c0];
         chunk_load(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
-        chunk_store(reinterpret_cast<float4*>(bufs[0]), (K.nv + 3) / 4, reg);
+        chunk_store(reinterpret_cast<float4*>(sm), (K.nv + 3) / 4, reg);
     }
     __syncthreads();
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
     for (int32_t c = c0; c < c1; ++c) {
         const Chunk K = a.chunks[c];
-        const float* cur = bufs[(c - c0) & 1];
+        const float* cur = sm + ((c - c0) & 1) * CHI;   // double buffer
         const bool more = c + 1 < c1;
         int32_t nxt4 = 0;
         if (more) {
@@ -568,7 +575,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
                 op[2] = s2;
             }
         }
-        if (more) chunk_store(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
+        if (more) chunk_store(reinterpret_cast<float4*>(sm + ((c + 1 - c0) & 1) * CHI), nxt4, reg);
         __syncthreads();
     }
     for (int32_t i = tid; i < 3 * n_loc; i += BLKI) a.zf[3 * base + i] = Z[i];
@@ -693,7 +700,6 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
     const SolveArgs a = solve_args(GM[sl.g]);
     extern __shared__ float4 sm4[];
     float* sm = reinterpret_cast<float*>(sm4);
-    float* bufs[2] = {sm, sm + CHI};
     float* Z = sm + 2 * CHI;
     float* DL = Z + 3 * a.max_n;
     const int32_t d = sl.lb;
@@ -708,18 +714,18 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
     }
     const int32_t c0 = a.sub_bwd_ch[d], c1 = a.sub_bwd_ch[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
-    float4 reg[NV4I];
+    ChunkRegs reg;
     if (c0 < c1) {
         const Chunk K = a.chunks[c0];
         chunk_load(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
-        chunk_store(reinterpret_cast<float4*>(bufs[0]), (K.nv + 3) / 4, reg);
+        chunk_store(reinterpret_cast<float4*>(sm), (K.nv + 3) / 4, reg);
     }
     __syncthreads();
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
     for (int32_t c = c0; c < c1; ++c) {
         const Chunk K = a.chunks[c];
-        const float* cur = bufs[(c - c0) & 1];
+        const float* cur = sm + ((c - c0) & 1) * CHI;   // double buffer
         const bool more = c + 1 < c1;
         int32_t nxt4 = 0;
         if (more) {
@@ -772,7 +778,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
                 op[2] = s2;
             }
         }
-        if (more) chunk_store(reinterpret_cast<float4*>(bufs[(c + 1 - c0) & 1]), nxt4, reg);
+        if (more) chunk_store(reinterpret_cast<float4*>(sm + ((c + 1 - c0) & 1) * CHI), nxt4, reg);
         __syncthreads();
     }
     // interior rows of this subdomain

@@ -42,11 +42,24 @@ class MeshInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServeStats(ctypes.Structure):
+    _fields_ = [("frames_done", ctypes.c_int64), ("requests_done", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("span_s", ctypes.c_double),
+                ("frames_per_second", ctypes.c_double), ("latency_p50_s", ctypes.c_double),
+                ("latency_p99_s", ctypes.c_double), ("latency_max_s", ctypes.c_double),
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t),
+                ("meshes_resident", ctypes.c_int32), ("meshes_waiting", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 SIGNATURES = {
     "vh_last_error": (ctypes.c_char_p, []),
     "vh_ctx_create": (ctypes.c_int, [_P(_vp), ctypes.c_int, _sz]),
     "vh_ctx_destroy": (ctypes.c_int, [_vp]),
     "vh_ctx_hbm_in_use": (ctypes.c_int, [_vp, _P(_sz)]),
+    "vh_ctx_set_hbm_budget": (ctypes.c_int, [_vp, _sz]),
     "vh_mesh_create": (ctypes.c_int, [_vp, _P(_vp), _vp, _i32, _vp, _i32]),
     "vh_mesh_destroy": (ctypes.c_int, [_vp]),
     "vh_mesh_set_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32]),
@@ -63,6 +76,17 @@ SIGNATURES = {
     "vh_debug_local_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vh_debug_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_debug_solve": (ctypes.c_int, [_vp, _vp, _vp]),
+    "vh_serve_open": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
+    "vh_serve_close": (ctypes.c_int, [_vp]),
+    "vh_serve_add": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
+    "vh_serve_submit": (ctypes.c_int, [_vp, _vp, _i32, _dbl, _P(ctypes.c_uint64)]),
+    "vh_serve_tick": (ctypes.c_int, [_vp, _i32, _P(_i32)]),
+    "vh_serve_drain": (ctypes.c_int, [_vp]),
+    "vh_serve_release": (ctypes.c_int, [_vp, _vp]),
+    "vh_serve_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(_i32), _P(_dbl)]),
+    "vh_serve_now": (ctypes.c_int, [_vp, _P(_dbl)]),
+    "vh_serve_reset_stats": (ctypes.c_int, [_vp]),
+    "vh_serve_get_stats": (ctypes.c_int, [_vp, _P(ServeStats)]),
 }
 
 
@@ -121,15 +145,21 @@ class Context:
         _check(_lib.vh_ctx_create(ctypes.byref(h), device, hbm_budget))
         self.h = h
         self._meshes = weakref.WeakSet()
+        self._server = None
 
     def hbm_in_use(self) -> int:
         b = ctypes.c_size_t()
         _check(_lib.vh_ctx_hbm_in_use(self.h, ctypes.byref(b)))
         return b.value
 
+    def set_hbm_budget(self, nbytes: int):
+        _check(_lib.vh_ctx_set_hbm_budget(self.h, int(nbytes)))
+
     def close(self):
         """Destroy the context and every mesh still open on it."""
         if self.h:
+            if self._server is not None:
+                self._server.close()
             for m in list(self._meshes):
                 m.close()
             _lib.vh_ctx_destroy(self.h)
@@ -257,6 +287,76 @@ class Mesh:
             if self.ctx.h:                      # a closed context already destroyed it
                 _lib.vh_mesh_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The context's step server (continuous batching of step requests).
+
+    mode "batched": each launch steps one frame of every resident mesh with a
+    request waiting; "sequential": one mesh's frame per launch (plain stepping).
+    """
+
+    MODES = {"batched": 0, "sequential": 1}
+
+    def __init__(self, ctx: Context, mode: str = "batched", max_in_flight: int = 2, max_batch: int = 0):
+        if not ctx.h:
+            raise VHError(VH_ESTATE, "context is closed")
+        _check(_lib.vh_serve_open(ctx.h, self.MODES[mode], int(max_in_flight), int(max_batch)))
+        self.ctx = ctx
+        self.mode = mode
+        ctx._server = self
+
+    def add(self, mesh: Mesh, n_subdomains: int, refine_steps: int = 0):
+        _check(_lib.vh_serve_add(self.ctx.h, mesh.h, int(n_subdomains), int(refine_steps)))
+
+    def submit(self, mesh: Mesh, n_frames: int = 1, t_arrival: float = -1.0) -> int:
+        t = ctypes.c_uint64()
+        _check(_lib.vh_serve_submit(self.ctx.h, mesh.h, int(n_frames), float(t_arrival), ctypes.byref(t)))
+        return t.value
+
+    def tick(self, wait: bool = False) -> int:
+        n = ctypes.c_int32()
+        _check(_lib.vh_serve_tick(self.ctx.h, 1 if wait else 0, ctypes.byref(n)))
+        return n.value
+
+    def drain(self):
+        _check(_lib.vh_serve_drain(self.ctx.h))
+
+    def release(self, mesh: Mesh):
+        _check(_lib.vh_serve_release(self.ctx.h, mesh.h))
+
+    def poll(self, ticket: int):
+        """(done, latency seconds or None)."""
+        d = ctypes.c_int32()
+        lat = ctypes.c_double()
+        _check(_lib.vh_serve_poll(self.ctx.h, ctypes.c_uint64(ticket), ctypes.byref(d), ctypes.byref(lat)))
+        return bool(d.value), (lat.value if d.value else None)
+
+    def now(self) -> float:
+        t = ctypes.c_double()
+        _check(_lib.vh_serve_now(self.ctx.h, ctypes.byref(t)))
+        return t.value
+
+    def reset_stats(self):
+        _check(_lib.vh_serve_reset_stats(self.ctx.h))
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        _check(_lib.vh_serve_get_stats(self.ctx.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.ctx is not None and self.ctx.h and self.ctx._server is self:
+            rc = _lib.vh_serve_close(self.ctx.h)
+            self.ctx._server = None
+            self.ctx = None
+            _check(rc)
 
     def __del__(self):
         try:

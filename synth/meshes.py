@@ -202,8 +202,10 @@ def serving_shell_problem(target_tets, seed, radius=0.25, height=0.6, leaf_verts
     n_z = max(2, int(round(height / h)))
     p = make_shell_problem(seed=seed, n_theta=n_theta, n_z=n_z, radius=radius, height=height,
                            frames=150, name=f"shell{target_tets}")
+    # the fewest power-of-two subdomains with at most about leaf_verts free
+    # vertices each (the 390,400-tet shell's 128 subdomains hold 915)
     n_free = int((p.pinned == 0).sum())
-    d = 2 ** max(0, int(round(math.log2(max(1.0, n_free / leaf_verts)))))
+    d = 2 ** max(0, int(math.ceil(math.log2(max(1.0, n_free / leaf_verts)))))
     p.n_subdomains = d
     return p
 

@@ -46,6 +46,7 @@ void vhp_info(void* h, long long* out) {
     out[4] = (long long)P.sn.size(); out[5] = P.n_clevels; out[6] = P.nnz_int;
     out[7] = P.nnz_coarse; out[8] = P.max_sub_phases; out[9] = (long long)P.chunks.size();
     out[10] = (long long)P.ctasks.size(); out[11] = (long long)P.cslots.size(); out[12] = P.max_sub_n;
+    out[13] = P.max_cint; out[14] = P.max_nb;
 }
 
 void vhp_perm(void* h, int* perm) {

@@ -35,10 +35,11 @@ def _build(hl, p, D, leaf=32, pinned=None):
     h = hl.vhp_build(keep[0].ctypes.data, p.nv, keep[1].ctypes.data, p.nt, keep[2].ctypes.data,
                      keep[3].ctypes.data, keep[4].ctypes.data, keep[5].ctypes.data, keep[6].ctypes.data,
                      p.dt, p.pd_iters, D, 0, leaf, ctypes.byref(rc), msg, 256)
-    info = np.zeros(13, dtype=np.int64)
+    info = np.zeros(15, dtype=np.int64)
     if h:
         hl.vhp_info(h, info.ctypes.data)
-    keys = "n_free n_int n_gamma D n_sn n_clevels nnz_int nnz_coarse max_sub_phases n_chunks n_ctasks n_cslots max_sub_n"
+    keys = ("n_free n_int n_gamma D n_sn n_clevels nnz_int nnz_coarse max_sub_phases n_chunks n_ctasks n_cslots "
+            "max_sub_n max_cint max_nb")
     return h, rc.value, msg.value.decode(), dict(zip(keys.split(), info.tolist()))
 
 
