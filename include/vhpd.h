@@ -239,6 +239,13 @@ int vh_serve_poll(vh_ctx* ctx, uint64_t ticket, int32_t* done, double* latency_s
 /* Current time on the server clock. */
 int vh_serve_now(vh_ctx* ctx, double* t);
 
+/* Launch the batched local step (kernel_class 1) or residual gather (2)
+ * over every resident mesh `reps` times back to back on `stream`, after the
+ * server's own launches have completed, for timing with events around the
+ * call (batched servers only).  Each launch overwrites only that kernel's
+ * outputs. */
+int vh_serve_time_kernel(vh_ctx* ctx, int32_t kernel_class, int32_t reps, void* stream);
+
 /* Restart the statistics window: completed requests are forgotten, the
  * launch counters and the HBM peak restart from now. */
 int vh_serve_reset_stats(vh_ctx* ctx);

@@ -40,6 +40,9 @@ constexpr int OK = 0, EINVAL_ = -1, ENOMEM_ = -2, ENOTSPD_ = -3;
 constexpr int32_t kMaxInteriorCols = 32;
 // tets per local-step workgroup (one thread per tet)
 constexpr int32_t kLocalBlock = 256;
+// largest dense root supernode formed from the top interface levels
+constexpr int64_t kMaxRootCols = 3000;
+constexpr int32_t kMaxRootLevels = 2;
 
 inline void tet_dm(const double* X, const int32_t* t, double Dm[9]) {
     // Dm[r][k] = X[t[k+1]][r] - X[t[0]][r]
@@ -303,13 +306,16 @@ int partial_cholesky(double* F, int32_t f, int32_t n, bool par) {
 void lower_inverse(const double* L, int32_t f, int32_t n, std::vector<double>& Ti, bool par) {
     Ti.assign((size_t)n * n, 0.0);
     auto col = [&](int32_t j) {
-        // solve L x = e_j, x[i] = 0 for i < j
+        // solve L x = e_j (x[i] = 0 for i < j) column by column of L, each
+        // column read contiguously
         std::vector<double> x(n, 0.0);
-        x[j] = 1.0 / L[(size_t)j * f + j];
-        for (int32_t i = j + 1; i < n; ++i) {
-            double s = 0.0;
-            for (int32_t k = j; k < i; ++k) s += L[(size_t)k * f + i] * x[k];
-            x[i] = -s / L[(size_t)i * f + i];
+        x[j] = 1.0;
+        for (int32_t k = j; k < n; ++k) {
+            const double* lk = L + (size_t)k * f;
+            const double xk = x[k] / lk[k];
+            x[k] = xk;
+            if (xk == 0.0) continue;
+            for (int32_t i = k + 1; i < n; ++i) x[i] -= lk[i] * xk;
         }
         for (int32_t i = j; i < n; ++i) Ti[(size_t)i * n + j] = x[i];
     };
@@ -399,6 +405,21 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             msg = "free vertex " + std::to_string(v) + " belongs to no element";
             return EINVAL_;
         }
+    // The top tree levels hold few, large separators, and every level costs the
+    // solve a fixed latency per phase: the separators of the top two levels
+    // form one dense root supernode if it stays within kMaxRootCols columns
+    // (deeper merges add more dense fill than the phases they save).
+    if (D > 1) {
+        std::vector<int64_t> per_depth(kbits + 1, 0);
+        for (int32_t v = 0; v < nv; ++v)
+            if (node[v] >= 1 && node[v] < D) per_depth[31 - __builtin_clz((uint32_t)node[v])]++;
+        int32_t ktop = 1;
+        int64_t cum = per_depth[0];
+        while (ktop < std::min(kbits, kMaxRootLevels) && cum + per_depth[ktop] <= kMaxRootCols)
+            cum += per_depth[ktop++];
+        for (int32_t v = 0; v < nv; ++v)
+            if (node[v] >= 1 && node[v] < D && (31 - __builtin_clz((uint32_t)node[v])) < ktop) node[v] = 1;
+    }
 
     // ---- vertex adjacency ------------------------------------------------------
     std::vector<int32_t> vptr(nv + 1, 0), vadj;

@@ -63,15 +63,26 @@ __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x)
 // minimal branching and elementary floating point operations", with exact
 // Jacobi angles in place of their approximate quaternion ones.
 // ---------------------------------------------------------------------------
+// an off-diagonal below 2^-24 of its diagonal pair is negligible (no rotation);
+// this also keeps denormals out of the hardware square root and reciprocal
+__device__ __forceinline__ bool jacobi_negligible(float app, float aqq, float apq) {
+    return !(fabsf(apq) > 5.96e-8f * (fabsf(app) + fabsf(aqq)) + 1e-30f);
+}
+
+// One Jacobi rotation zeroing apq.  With d = aqq - app, e = 2 apq and
+// r = sqrt(d^2 + e^2), the smaller rotation has tan = t = sgn(d) e / (|d| + r),
+// hence c = (|d| + r) w, s = sgn(d) e w and t = 2 r sgn(d) e w^2 with
+// w = 1 / sqrt(2 r (|d| + r)): one square root and one reciprocal square root.
 __device__ __forceinline__ void jacobi_pair(float& app, float& aqq, float& apq, float& arp,
                                             float& arq, float* W, int p, int q) {
-    // negligible off-diagonals (below 2^-24 of the diagonal pair): no rotation.
-    // This also keeps denormals out of the hardware reciprocal (inf, and 0 * inf).
-    if (!(fabsf(apq) > 5.96e-8f * (fabsf(app) + fabsf(aqq)) + 1e-30f)) return;
-    float tau = (aqq - app) * frcp(2.0f * apq);
-    float t = copysignf(frcp(fabsf(tau) + fsqrt(1.0f + tau * tau)), tau);
-    float c = frsq(1.0f + t * t);
-    float s = t * c;
+    if (jacobi_negligible(app, aqq, apq)) return;
+    const float d = aqq - app, ad = fabsf(d);
+    const float e = (d < 0.0f) ? -2.0f * apq : 2.0f * apq;
+    const float r = fsqrt(d * d + e * e);
+    const float w = frsq(2.0f * r * (ad + r));
+    const float c = (ad + r) * w;
+    const float s = e * w;
+    const float t = 2.0f * r * e * w * w;
     app -= t * apq;
     aqq += t * apq;
     apq = 0.0f;
@@ -135,8 +146,13 @@ __device__ __forceinline__ void svd3(const float* F, float* U, float* sig, float
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) W[i] = (i % 4 == 0) ? 1.0f : 0.0f;
+    // at most 4 sweeps; once every off-diagonal of every lane of the wave is
+    // negligible, further sweeps would rotate nothing, so they are skipped
 #pragma unroll
     for (int sweep = 0; sweep < 4; ++sweep) {
+        if (sweep > 0 && __all(jacobi_negligible(a00, a11, a01) && jacobi_negligible(a00, a22, a02) &&
+                               jacobi_negligible(a11, a22, a12)))
+            break;
         jacobi_pair(a00, a11, a01, a02, a12, W, 0, 1);   // r = 2
         jacobi_pair(a00, a22, a02, a01, a12, W, 0, 2);   // r = 1: a10 = a01, a12 -> a21
         jacobi_pair(a11, a22, a12, a01, a02, W, 1, 2);   // r = 0: a01, a02
@@ -190,9 +206,14 @@ __device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_o
         }
         float p = s[0] * s[1] * s[2];
         if (fabsf(p - 1.0f) < 2.4e-7f) break;
-        float h = (fabsf(p - 1.0f) < 0.25f) ? (p - 1.0f) * frcp(p) : logf(p);
-        float hp = frcp(q[0] * s[0]) + frcp(q[1] * s[1]) + frcp(q[2] * s[2]);
-        float mun = mu - h * frcp(hp);
+        // h' = sum_i 1 / (q_i s_i); with A_i = q_i s_i the Newton step h / h' is
+        // h A1 A2 A3 / (A2 A3 + A1 A3 + A1 A2), and near the root h = (p - 1) / p
+        const float A0 = q[0] * s[0], A1 = q[1] * s[1], A2 = q[2] * s[2];
+        const float num = A0 * A1 * A2, den = A1 * A2 + A0 * A2 + A0 * A1;
+        float step;
+        if (fabsf(p - 1.0f) < 0.25f) step = (p - 1.0f) * num * frcp(p * den);
+        else step = logf(p) * num * frcp(den);
+        float mun = mu - step;
         if (!(mun > lo)) mun = 0.5f * (mu + lo);
         mu = mun;
         if (it == 7) {
@@ -485,6 +506,77 @@ __device__ __forceinline__ void chunk_store(float4* dst, int32_t nv4, const Chun
     if (j + 2 * BLKI < nv4) dst[j + 2 * BLKI] = make_float4(reg.c0, reg.c1, reg.c2, reg.c3);
 }
 
+// Descriptors of a subdomain's first CHD chunks are copied to LDS at kernel
+// start, so the chunk pipeline never waits on a global descriptor read.
+constexpr int32_t CHD = 64;
+
+__device__ __forceinline__ Chunk chunk_desc(const Chunk* __restrict__ chunks, const int4* cd, int32_t c0,
+                                            int32_t c) {
+    Chunk K;
+    if (c - c0 < CHD) {
+        const int4 v = cd[c - c0];
+        K.kind = v.x;
+        K.ntasks = v.y;
+        K.v0 = v.z;
+        K.nv = v.w;
+    } else {
+        K = chunks[c];
+    }
+    return K;
+}
+
+// Runs compute(K, buf, spare) over the chunks c0..c1-1 of one subdomain.
+// Chunk c is computed from LDS buffer (c - c0) & 1 while chunk c + 1 waits in
+// registers for the other buffer (`spare`, free during compute) and the loads
+// of chunk c + 2 are in flight, so every chunk's global read has two phases of
+// compute to complete.  compute is called by every thread; ends with a barrier.
+template <class F>
+__device__ __forceinline__ void chunk_pipeline(const Chunk* __restrict__ chunks, const float4* __restrict__ iv4,
+                                               int32_t c0, int32_t c1, float* sm, int4* cd, F&& compute) {
+    for (int32_t c = c0 + (int32_t)threadIdx.x; c < min(c1, c0 + CHD); c += BLKI) {
+        const Chunk K = chunks[c];
+        cd[c - c0] = make_int4(K.kind, K.ntasks, K.v0, K.nv);
+    }
+    __syncthreads();
+    if (c0 >= c1) return;
+    float* buf0 = sm;
+    float* buf1 = sm + CHI;
+    ChunkRegs ra, rb;   // ra: next chunk for buffer 1, rb: next chunk for buffer 0
+    Chunk K0 = chunk_desc(chunks, cd, c0, c0), K1 = K0, N0 = K0, N1 = K0;
+    chunk_load(iv4 + K0.v0 / 4, (K0.nv + 3) / 4, ra);
+    chunk_store(reinterpret_cast<float4*>(buf0), (K0.nv + 3) / 4, ra);
+    if (c0 + 1 < c1) {
+        N1 = chunk_desc(chunks, cd, c0, c0 + 1);
+        chunk_load(iv4 + N1.v0 / 4, (N1.nv + 3) / 4, ra);
+    }
+    __syncthreads();
+    for (int32_t c = c0; c < c1; c += 2) {
+        // chunk c in buffer 0, chunk c + 1 in ra
+        if (c + 2 < c1) {
+            N0 = chunk_desc(chunks, cd, c0, c + 2);
+            chunk_load(iv4 + N0.v0 / 4, (N0.nv + 3) / 4, rb);
+        }
+        compute(K0, buf0, buf1);
+        if (c + 1 < c1) {
+            chunk_store(reinterpret_cast<float4*>(buf1), (N1.nv + 3) / 4, ra);
+            K1 = N1;
+        }
+        __syncthreads();
+        if (c + 1 >= c1) break;
+        // chunk c + 1 in buffer 1, chunk c + 2 in rb
+        if (c + 3 < c1) {
+            N1 = chunk_desc(chunks, cd, c0, c + 3);
+            chunk_load(iv4 + N1.v0 / 4, (N1.nv + 3) / 4, ra);
+        }
+        compute(K1, buf1, buf0);
+        if (c + 2 < c1) {
+            chunk_store(reinterpret_cast<float4*>(buf0), (N0.nv + 3) / 4, rb);
+            K0 = N0;
+        }
+        __syncthreads();
+    }
+}
+
 // Interior forward solve.  Per supernode level: PULLSUM (thread per row)
 // r'_row -= sum of its LDS contribution slots; GEMV (lane per row of
 // [Ti; B Ti], 64 rows per wave item) accumulating column by column of the
@@ -499,7 +591,8 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
     const SolveArgs a = solve_args(GM[sl.g]);
     extern __shared__ float4 sm4[];
     float* sm = reinterpret_cast<float*>(sm4);
-    float* R = sm + 2 * CHI;
+    int4* cd = reinterpret_cast<int4*>(sm + 2 * CHI);   // 16-byte aligned: CHI is a multiple of 4
+    float* R = sm + 2 * CHI + 4 * CHD;
     float* Z = R + 3 * a.max_n;
     float* C = Z + 3 * a.max_n;
     const int32_t d = sl.lb;
@@ -509,25 +602,9 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
     for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)a.r[3 * base + i];
     const int32_t c0 = a.sub_fwd_ch[d], c1 = a.sub_fwd_ch[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
-    ChunkRegs reg;
-    if (c0 < c1) {
-        const Chunk K = a.chunks[c0];
-        chunk_load(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
-        chunk_store(reinterpret_cast<float4*>(sm), (K.nv + 3) / 4, reg);
-    }
-    __syncthreads();
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
-    for (int32_t c = c0; c < c1; ++c) {
-        const Chunk K = a.chunks[c];
-        const float* cur = sm + ((c - c0) & 1) * CHI;   // double buffer
-        const bool more = c + 1 < c1;
-        int32_t nxt4 = 0;
-        if (more) {
-            const Chunk Kn = a.chunks[c + 1];
-            nxt4 = (Kn.nv + 3) / 4;
-            chunk_load(iv4 + Kn.v0 / 4, nxt4, reg);
-        }
+    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, [&](const Chunk& K, const float* cur, float*) {
         const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
         if (K.kind == PULLSUM) {
             const int32_t* idat = desc + 4 * K.ntasks;
@@ -575,9 +652,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
                 op[2] = s2;
             }
         }
-        if (more) chunk_store(reinterpret_cast<float4*>(sm + ((c + 1 - c0) & 1) * CHI), nxt4, reg);
-        __syncthreads();
-    }
+    });
     for (int32_t i = tid; i < 3 * n_loc; i += BLKI) a.zf[3 * base + i] = Z[i];
 }
 
@@ -635,10 +710,23 @@ __global__ __launch_bounds__(BLK) void k_coarse(const DevMesh* __restrict__ GM, 
             s2 += v * xp[2];
         }
     } else {
+        // four independent elements per lane and round keep enough loads in
+        // flight; the per-lane summation order is fixed by the lane index
         const double* vp = a.dvals + T.a[1];
         const int32_t len1 = T.a[2], len2 = T.a[4];
         const double* zb = a.zg + 3 * T.a[3];
-        for (int32_t k = lane; k < len1; k += G) {
+        int32_t k = lane;
+        for (; k + 3 * G < len1; k += 4 * G) {
+            const double v0 = vp[k], v1 = vp[k + G], v2 = vp[k + 2 * G], v3 = vp[k + 3 * G];
+            const double* x0 = zb + 3 * k;
+            const double* x1 = x0 + 3 * G;
+            const double* x2 = x1 + 3 * G;
+            const double* x3 = x2 + 3 * G;
+            s0 += v0 * x0[0] + v1 * x1[0] + v2 * x2[0] + v3 * x3[0];
+            s1 += v0 * x0[1] + v1 * x1[1] + v2 * x2[1] + v3 * x3[1];
+            s2 += v0 * x0[2] + v1 * x1[2] + v2 * x2[2] + v3 * x3[2];
+        }
+        for (; k < len1; k += G) {
             const double v = vp[k];
             const double* xp = zb + 3 * k;
             s0 += v * xp[0];
@@ -647,16 +735,19 @@ __global__ __launch_bounds__(BLK) void k_coarse(const DevMesh* __restrict__ GM, 
         }
         const double* v2p = vp + len1;
         const int32_t* gi = a.cgidx + T.a[5];
-        int32_t k = lane;
-        for (; k + G < len2; k += 2 * G) {
-            const double va = v2p[k], vb = v2p[k + G];
-            const double* xa = a.dg + 3 * gi[k];
-            const double* xb2 = a.dg + 3 * gi[k + G];
-            s0 += va * xa[0] + vb * xb2[0];
-            s1 += va * xa[1] + vb * xb2[1];
-            s2 += va * xa[2] + vb * xb2[2];
+        k = lane;
+        for (; k + 3 * G < len2; k += 4 * G) {
+            const int32_t g0 = gi[k], g1 = gi[k + G], g2 = gi[k + 2 * G], g3 = gi[k + 3 * G];
+            const double v0 = v2p[k], v1 = v2p[k + G], v2 = v2p[k + 2 * G], v3 = v2p[k + 3 * G];
+            const double* x0 = a.dg + 3 * g0;
+            const double* x1 = a.dg + 3 * g1;
+            const double* x2 = a.dg + 3 * g2;
+            const double* x3 = a.dg + 3 * g3;
+            s0 += v0 * x0[0] + v1 * x1[0] + v2 * x2[0] + v3 * x3[0];
+            s1 += v0 * x0[1] + v1 * x1[1] + v2 * x2[1] + v3 * x3[1];
+            s2 += v0 * x0[2] + v1 * x1[2] + v2 * x2[2] + v3 * x3[2];
         }
-        if (k < len2) {
+        for (; k < len2; k += G) {
             const double v = v2p[k];
             const double* xp = a.dg + 3 * gi[k];
             s0 += v * xp[0];
@@ -700,7 +791,8 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
     const SolveArgs a = solve_args(GM[sl.g]);
     extern __shared__ float4 sm4[];
     float* sm = reinterpret_cast<float*>(sm4);
-    float* Z = sm + 2 * CHI;
+    int4* cd = reinterpret_cast<int4*>(sm + 2 * CHI);   // 16-byte aligned: CHI is a multiple of 4
+    float* Z = sm + 2 * CHI + 4 * CHD;
     float* DL = Z + 3 * a.max_n;
     const int32_t d = sl.lb;
     const int32_t base = a.sub_off[d];
@@ -714,41 +806,32 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
     }
     const int32_t c0 = a.sub_bwd_ch[d], c1 = a.sub_bwd_ch[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
-    ChunkRegs reg;
-    if (c0 < c1) {
-        const Chunk K = a.chunks[c0];
-        chunk_load(iv4 + K.v0 / 4, (K.nv + 3) / 4, reg);
-        chunk_store(reinterpret_cast<float4*>(sm), (K.nv + 3) / 4, reg);
-    }
-    __syncthreads();
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
-    for (int32_t c = c0; c < c1; ++c) {
-        const Chunk K = a.chunks[c];
-        const float* cur = sm + ((c - c0) & 1) * CHI;   // double buffer
-        const bool more = c + 1 < c1;
-        int32_t nxt4 = 0;
-        if (more) {
-            const Chunk Kn = a.chunks[c + 1];
-            nxt4 = (Kn.nv + 3) / 4;
-            chunk_load(iv4 + Kn.v0 / 4, nxt4, reg);
-        }
+    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, [&](const Chunk& K, const float* cur, float* spare) {
         const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
         const float* dat = cur + 8 * K.ntasks;
         const int32_t* idat = reinterpret_cast<const int32_t*>(dat);
-        for (int32_t t = wave; t < K.ntasks; t += NW) {
+        // a phase with fewer tasks than waves gives each task wpt waves, each
+        // taking every wpt-th group of rows; their column sums meet in `spare`
+        int32_t wpt = 1;
+        while (2 * wpt * K.ntasks <= NW) wpt *= 2;
+        const int32_t sub = wave % wpt;
+        for (int32_t t = wave / wpt; t < K.ntasks; t += NW / wpt) {
             const int32_t* q = desc + 8 * t;
             const int32_t col0 = q[0], n = q[1], m = q[2];
             // lanes per column: the wave's 64 lanes are split into `lpc` groups of
-            // `ncp` columns (ncp >= n, a power of two); group j takes rows j, j+lpc, ...
+            // `ncp` columns (ncp >= n, a power of two); group j of sub-wave `sub`
+            // takes rows j + lpc sub, j + lpc (sub + wpt), ...
             const int32_t ncp = (n <= 8) ? 8 : (n <= 16) ? 16 : (n <= 32) ? 32 : 64;
-            const int32_t lpc = 64 / ncp;
-            const int32_t k = q[5] + (lane & (ncp - 1)), j = lane / ncp;
+            const int32_t lpc = 64 / ncp, stride = lpc * wpt;
+            const int32_t kl = lane & (ncp - 1), j = lane / ncp;
+            const int32_t k = q[5] + kl;
             const bool act = k < n;
             const float* w = dat + q[3] + k;
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
             if (act) {
-                for (int32_t i = k + j; i < n; i += lpc) {
+                for (int32_t i = k + j + lpc * sub; i < n; i += stride) {
                     const float v = w[i * (i + 1) / 2];
                     const float* xp = Z + 3 * (col0 + i);
                     s0 += v * xp[0];
@@ -758,7 +841,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
                 const float* wb = w + n * (n + 1) / 2;
                 const int32_t* g = idat + q[4];
 #pragma unroll 2
-                for (int32_t p = j; p < m; p += lpc) {
+                for (int32_t p = j + lpc * sub; p < m; p += stride) {
                     const float v = wb[p * n];
                     const float* xp = DL + 3 * g[p];
                     s0 -= v * xp[0];
@@ -772,15 +855,38 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
                 s2 += __shfl_xor(s2, off, 64);
             }
             if (act && j == 0) {
-                float* op = DL + 3 * (col0 + k);
+                float* op = (wpt == 1) ? DL + 3 * (col0 + k) : spare + 3 * (wave * 64 + kl);
                 op[0] = s0;
                 op[1] = s1;
                 op[2] = s2;
             }
         }
-        if (more) chunk_store(reinterpret_cast<float4*>(sm + ((c + 1 - c0) & 1) * CHI), nxt4, reg);
-        __syncthreads();
-    }
+        if (wpt > 1) {
+            // every task had one round: sum its sub-waves' partials in order
+            __syncthreads();
+            const int32_t t = wave / wpt;
+            if (sub == 0 && t < K.ntasks) {
+                const int32_t* q = desc + 8 * t;
+                const int32_t n = q[1];
+                const int32_t ncp = (n <= 8) ? 8 : (n <= 16) ? 16 : (n <= 32) ? 32 : 64;
+                const int32_t kl = lane & (ncp - 1), k = q[5] + kl;
+                if (lane < ncp && k < n) {
+                    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+                    for (int32_t u = 0; u < wpt; ++u) {
+                        const float* pp = spare + 3 * ((wave + u) * 64 + kl);
+                        s0 += pp[0];
+                        s1 += pp[1];
+                        s2 += pp[2];
+                    }
+                    float* op = DL + 3 * (q[0] + k);
+                    op[0] = s0;
+                    op[1] = s1;
+                    op[2] = s2;
+                }
+            }
+            __syncthreads();   // `spare` receives the next chunk after this phase
+        }
+    });
     // interior rows of this subdomain
     for (int32_t i = tid; i < n_loc; i += BLKI) {
         const int32_t gi = base + i;
@@ -892,11 +998,11 @@ hipError_t launch_residual(const LaunchRef& r, hipStream_t s) {
 }
 
 size_t interior_fwd_lds(int32_t max_n, int32_t max_cint) {
-    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)max_n + 3 * (size_t)max_cint);
+    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)max_n + 3 * (size_t)max_cint) + sizeof(int4) * CHD;
 }
 
 size_t interior_bwd_lds(int32_t max_n, int32_t max_nb) {
-    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)max_n + 3 * (size_t)max_nb);
+    return sizeof(float) * (2 * (size_t)CHI + 6 * (size_t)max_n + 3 * (size_t)max_nb) + sizeof(int4) * CHD;
 }
 
 int32_t interior_chunk_words() { return CHI; }

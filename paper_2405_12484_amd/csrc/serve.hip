@@ -426,6 +426,28 @@ int vh_serve_now(vh_ctx* ctx, double* t) {
     return VH_OK;
 }
 
+int vh_serve_time_kernel(vh_ctx* ctx, int32_t kernel_class, int32_t reps, void* stream) {
+    Server* S = server_of(ctx);
+    if (!S) return fail(VH_ESTATE, "the server is not open");
+    if (S->mode != VH_SERVE_BATCHED) return fail(VH_ESTATE, "kernel timing needs a batched server");
+    if (reps < 1) return fail(VH_EINVAL, "reps must be >= 1");
+    if (kernel_class != 1 && kernel_class != 2) return fail(VH_EINVAL, "kernel_class must be 1 or 2");
+    VH_HIP(hipSetDevice(ctx->device));
+    VH_TRY(drain(*S));
+    if (S->dirty) VH_TRY(rebuild(ctx, *S));
+    if (S->ls.ng == 0) return fail(VH_ESTATE, "no resident mesh");
+    std::vector<int32_t> on(S->ls.ng, 0);
+    for (int32_t g = 0; g < (int32_t)S->pos.size(); ++g)
+        if (S->pos[g] >= 0) on[S->pos[g]] = 1;
+    VH_HIP(hipMemcpy(S->ls.active, on.data(), sizeof(int32_t) * S->ls.ng, hipMemcpyHostToDevice));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int32_t r = 0; r < reps; ++r) {
+        if (kernel_class == 1) VH_HIP(vh::launch_local(S->ls.local, s, false));
+        else VH_HIP(vh::launch_residual(S->ls.residual, s));
+    }
+    return VH_OK;
+}
+
 int vh_serve_reset_stats(vh_ctx* ctx) {
     Server* S = server_of(ctx);
     if (!S) return fail(VH_ESTATE, "the server is not open");

@@ -85,6 +85,7 @@ SIGNATURES = {
     "vh_serve_release": (ctypes.c_int, [_vp, _vp]),
     "vh_serve_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(_i32), _P(_dbl)]),
     "vh_serve_now": (ctypes.c_int, [_vp, _P(_dbl)]),
+    "vh_serve_time_kernel": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
     "vh_serve_reset_stats": (ctypes.c_int, [_vp]),
     "vh_serve_get_stats": (ctypes.c_int, [_vp, _P(ServeStats)]),
 }
@@ -345,6 +346,12 @@ class Server:
 
     def reset_stats(self):
         _check(_lib.vh_serve_reset_stats(self.ctx.h))
+
+    def time_kernel(self, kernel_class: str, reps: int, stream=None):
+        """Launch the batched local step or residual over every resident mesh
+        `reps` times back to back (for event timing)."""
+        idx = {"local": 1, "residual": 2}[kernel_class]
+        _check(_lib.vh_serve_time_kernel(self.ctx.h, idx, int(reps), _stream_ptr(stream)))
 
     def stats(self) -> dict:
         st = ServeStats()
