@@ -152,6 +152,34 @@ int vh_mesh_profile_read(vh_mesh* mesh, double* ms, int64_t* launches);
  * overwrite only their outputs; the solve kernels only their work vectors. */
 int vh_mesh_time_kernel(vh_mesh* mesh, int32_t kernel_class, int32_t reps, void* stream);
 
+/* ---- Discrete adjoint with respect to gamma_s (gradients of a trajectory).
+ *
+ * The forward map is n_frames PD steps (Sec. 7) from (x0, v0); the adjoint
+ * reverses every local/global iteration: with lambda = K^{-1} xbar^(k+1),
+ * gamma_s gets V_e <G_e lambda, R_e(x^(k)) - F_e(x^(k+1))> (the right-hand side
+ * and K both depend on gamma_s, Sec. 7.1) and xbar^(k) = sum_e G_e^T
+ * J_P(F_e(x^(k))) [G_e lambda], the derivative of the projections of Eq.
+ * pd_local and Eq. vol_pre (FP32, like the local step); then the predictor and
+ * the BDF1 velocity are reversed.  Out-of-regime projections (clamped
+ * singular values) are not differentiated through; they are counted like in
+ * the forward step. ---- */
+
+/* Run n_frames (>= 1) steps from the host state x0, v0 [nv][3] (user order)
+ * on `stream`, keeping (x, v) on the device every ckpt_every (>= 1) frames
+ * (2 * ceil(n_frames / ckpt_every) * nv * 3 doubles, charged to the budget
+ * until the next call, set_params or destroy); x_final [nv][3] receives the
+ * final positions (the stream is synchronised). */
+int vh_mesh_adjoint_forward(vh_mesh* mesh, const double* x0, const double* v0, int32_t n_frames,
+                            int32_t ckpt_every, double* x_final, void* stream);
+/* Given dLoss/dx_final (xbar [nv][3]) and optionally dLoss/dv_final (vbar,
+ * NULL = 0), write dLoss/dgamma_s [nt] (user element order) for the last
+ * vh_mesh_adjoint_forward.  Each checkpoint segment is replayed once, keeping
+ * its iterates (ckpt_every * (pd_iters + 1) * nv * 3 doubles of scratch); the
+ * mesh state is left at an unspecified frame.  Pinned rows of xbar, vbar are
+ * ignored.  VH_ESTATE without a preceding forward. */
+int vh_mesh_adjoint_backward(vh_mesh* mesh, const double* xbar, const double* vbar, double* grad_gamma_s,
+                             void* stream);
+
 /* ---- Entry points that run one part of the step, for testing each kernel
  * against a reference.  All arrays are host arrays in user vertex order. ---- */
 

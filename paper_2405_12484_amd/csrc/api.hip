@@ -171,6 +171,8 @@ size_t launch_set_bytes(int32_t ng, size_t coarse_phases) {
     return sizeof(vh::DevMesh) * ng + sizeof(int32_t) * (tab + ng);
 }
 
+}  // namespace
+
 int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta) {
     {
         ProfScope ps(m, s, 3);
@@ -245,6 +247,8 @@ int put_user(vh_mesh* m, const double* host, double* dev_int, bool positions, hi
     return VH_OK;
 }
 
+namespace {
+
 }  // namespace
 
 int set_device(vh_mesh* m) {
@@ -261,6 +265,7 @@ void free_launch_set(vh_ctx* ctx, LaunchSet& L) {
 }
 
 void free_device(vh_mesh* m) {
+    free_adjoint(m);
     if (m->gexec) {
         (void)hipGraphExecDestroy(m->gexec);
         m->gexec = nullptr;
@@ -325,7 +330,7 @@ int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSe
         out.reserve(2 * nj);
         for (size_t j = 0; j < nj; ++j)
             for (int32_t kind : {(int32_t)vh::PULLSUM, (int32_t)vh::GEMV, (int32_t)vh::BGEMV})
-                for (int32_t grp : {16, 64}) {
+                for (int32_t grp : {16, 32, 64}) {
                     std::vector<int32_t> g, b, x0, x1;
                     for (int32_t i = 0; i < ng; ++i) {
                         const auto& ph = fwd ? members[i]->plan.cfwd : members[i]->plan.cbwd;

@@ -25,6 +25,8 @@
 #include <omp.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -43,6 +45,8 @@ constexpr int32_t kLocalBlock = 256;
 // largest dense root supernode formed from the top interface levels
 constexpr int64_t kMaxRootCols = 3000;
 constexpr int32_t kMaxRootLevels = 2;
+// interface tasks use 32 / 64 lanes from these mean lengths (16 below)
+constexpr int64_t kIfaceG32Min = 96, kIfaceG64Min = 384;
 
 inline void tet_dm(const double* X, const int32_t* t, double Dm[9]) {
     // Dm[r][k] = X[t[k+1]][r] - X[t[0]][r]
@@ -627,6 +631,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         }
         rec[13] = (float)(Vol[e] * gamma_s[u]);
         rec[14] = (float)(Vol[e] * gamma_v[u]);
+        rec[15] = (float)Vol[e];
     }
 
     // ---- scatter: per-block reduction of corner forces ----------------------------
@@ -1070,6 +1075,16 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
     P.cgidx.clear();
     P.cfwd.clear();
     P.cbwd.clear();
+    // lanes per interface task by the phase's mean task length; VHPD_IFACE_G
+    // ("g32,g64": the mean lengths from which 32 and 64 lanes are used) overrides
+    int64_t g32_min = kIfaceG32Min, g64_min = kIfaceG64Min;
+    if (const char* ge = std::getenv("VHPD_IFACE_G")) {
+        long long a = 0, b = 0;
+        if (std::sscanf(ge, "%lld,%lld", &a, &b) == 2 && a > 0 && b > 0) {
+            g32_min = a;
+            g64_min = b;
+        }
+    }
     auto open_cphase = [&](int32_t kind) {
         CPhase ph;
         ph.kind = kind;
@@ -1081,7 +1096,8 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
     auto close_cphase = [&](CPhase ph, int64_t total_len, std::vector<CPhase>& lst) {
         ph.ntasks = (int32_t)P.ctasks.size() - ph.task0;
         if (ph.ntasks == 0) return;
-        ph.group = (total_len / ph.ntasks >= 96) ? 64 : 16;
+        const int64_t avg = total_len / ph.ntasks;
+        ph.group = (avg >= g64_min) ? 64 : (avg >= g32_min) ? 32 : 16;
         lst.push_back(ph);
     };
     std::vector<int32_t> cg_goff(nsn, -1);

@@ -21,7 +21,7 @@ struct DevMesh {
     int32_t* perm = nullptr;        // internal vertex -> user vertex
     float4* u = nullptr;            // float(x - X), w unused
     // elements
-    float4* trec = nullptr;         // [nt][4]: ids, Dm^{-1}, V gs, V gv
+    float4* trec = nullptr;         // [nt][4]: ids, Dm^{-1}, V gs, V gv, V
     uint2* lpos = nullptr;          // [nt]: 4 x uint16 LDS positions of the corner forces
     int32_t *blk_part = nullptr, *part_pack = nullptr;
     float4* part = nullptr;         // per (block, vertex) partial force sums
@@ -91,4 +91,14 @@ hipError_t launch_from_user(int32_t nv, int32_t n_free, const int32_t* perm, con
                             const double* X_or_null, double* dst_int, hipStream_t s);
 // u = float(x - X)
 hipError_t launch_refresh_u(const DevMesh& m, hipStream_t s);
+// discrete adjoint of one PD iteration (one garment; dev_mesh: its device DevMesh):
+// gbar += gamma_s term, partials of the J_P [G lambda] corner forces
+hipError_t launch_adj_local(const DevMesh* dev_mesh, int32_t nt, const double* xk, const double* xk1,
+                            const double* lam, double* gbar, hipStream_t s);
+// xbar = sum of partials, ybar += M lambda / dt^2 (free rows)
+hipError_t launch_adj_gather(const DevMesh* dev_mesh, int32_t n_free, const double* lam, double* xbar,
+                             double* ybar, hipStream_t s);
+// frame boundaries of the reverse sweep over n3 = 3 n_free values
+hipError_t launch_adj_frame(int32_t n3, double dt, bool begin, double* xbar, double* vbar, double* xk, double* xn,
+                            double* ybar, hipStream_t s);
 }  // namespace vh

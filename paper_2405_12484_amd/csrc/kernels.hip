@@ -417,6 +417,207 @@ __global__ __launch_bounds__(BLK) void k_residual(const DevMesh* __restrict__ GM
 }
 
 // ---------------------------------------------------------------------------
+// Discrete adjoint of the PD iteration with respect to gamma_s (one garment).
+// For x^(k+1) = L^{-1} b(x^(k)) and lambda = L^{-1} xbar^(k+1):
+//   gbar_e  += V_e <G_e lambda, R_e(x^(k)) - F_e(x^(k+1))>   (b and L depend on gamma_s)
+//   xbar^(k) = sum_e G_e^T dP_e,  dP_e = J_P(F_e(x^(k))) [G_e lambda]
+// with P = w_s R + w_v V.  J_P is symmetric (R and V are projections), so the
+// transposed product is this directional derivative.  In the singular bases
+// (M = U^T dF W, a / b its symmetric / skew parts, s = Proj_SL3(sigma),
+// q_i = sqrt(sigma_i^2 + 4 mu) = sigma_i + 2 (s_i - sigma_i)):
+//   U^T dR W:  off-diagonal 2 b_ij / (sigma_i + sigma_j), diagonal 0
+//   U^T dV W:  off-diagonal a_ij (1/2 + (sigma_i + sigma_j) / (2 (q_i + q_j)))
+//                         + b_ij (s_i + s_j) / (sigma_i + sigma_j),
+//              diagonal ds_i = (dmu + s_i M_ii) / q_i,
+//              dmu = -(sum_i M_ii / q_i) / (sum_i 1 / (q_i s_i))
+// (the divided difference (s_j - s_i) / (sigma_j - sigma_i) at the common mu is
+// written without the difference, so equal singular values are harmless).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tet_F(const double* __restrict__ x, const double* __restrict__ X, const int32_t* id,
+                                      const float* G, bool identity, float* F) {
+    float u[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            u[a][c] = X ? (float)(x[3 * id[a] + c] - X[3 * id[a] + c]) : (float)x[3 * id[a] + c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            F[r * 3 + j] = (identity && r == j ? 1.0f : 0.0f) + (u[1][r] - u[0][r]) * G[0 * 3 + j] +
+                           (u[2][r] - u[0][r]) * G[1 * 3 + j] + (u[3][r] - u[0][r]) * G[2 * 3 + j];
+}
+
+__global__ __launch_bounds__(LBLK) void k_adj_local(const DevMesh* __restrict__ GM, const double* __restrict__ xk,
+                                                    const double* __restrict__ xk1,
+                                                    const double* __restrict__ lam, double* __restrict__ gbar) {
+    __shared__ float LF[3][4 * LBLK];
+    const DevMesh& M = GM[0];
+    const int32_t nt = M.nt;
+    const int32_t e = blockIdx.x * LBLK + threadIdx.x;
+    if (e < nt) {
+        const float4* rec = M.trec + 4 * (size_t)e;
+        const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
+        const int32_t id[4] = {__float_as_int(r0.x), __float_as_int(r0.y), __float_as_int(r0.z),
+                               __float_as_int(r0.w)};
+        const float G[9] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
+        const float ws = r3.y, wv = r3.z, Ve = r3.w;
+        float F[9], F1[9], Gl[9];
+        tet_F(xk, M.X, id, G, true, F);
+        tet_F(xk1, M.X, id, G, true, F1);
+        tet_F(lam, nullptr, id, G, false, Gl);
+        float U[9], W[9], sg[3], dsv[3];
+        svd3(F, U, sg, W);
+        bool oor = false;
+        proj_sl3(sg, dsv, oor);
+        float s[3], q[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            s[i] = sg[i] + dsv[i];
+            q[i] = sg[i] + 2.0f * dsv[i];
+        }
+        // gamma_s term: V_e <G lambda, R - F(x^(k+1))>, R = U W^T
+        float gs = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const float Rij = U[i * 3 + 0] * W[j * 3 + 0] + U[i * 3 + 1] * W[j * 3 + 1] + U[i * 3 + 2] * W[j * 3 + 2];
+                gs += Gl[i * 3 + j] * (Rij - F1[i * 3 + j]);
+            }
+        gbar[e] += (double)(Ve * gs);
+        // M = U^T (G lambda) W
+        float T1[9], Mm[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                T1[i * 3 + j] = Gl[i * 3 + 0] * W[0 * 3 + j] + Gl[i * 3 + 1] * W[1 * 3 + j] + Gl[i * 3 + 2] * W[2 * 3 + j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Mm[i * 3 + j] = U[0 * 3 + i] * T1[0 * 3 + j] + U[1 * 3 + i] * T1[1 * 3 + j] + U[2 * 3 + i] * T1[2 * 3 + j];
+        // Q = U^T dP W = w_s U^T dR W + w_v U^T dV W
+        float Q[9];
+        {
+            float sq = 0.0f, sis = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                sq += Mm[i * 4] * frcp(q[i]);
+                sis += frcp(q[i] * s[i]);
+            }
+            const float dmu = -sq * frcp(sis);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Q[i * 4] = wv * (dmu + s[i] * Mm[i * 4]) * frcp(q[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (i == j) continue;
+                const float a = 0.5f * (Mm[i * 3 + j] + Mm[j * 3 + i]);
+                const float b = 0.5f * (Mm[i * 3 + j] - Mm[j * 3 + i]);
+                const float isum = frcp(sg[i] + sg[j]);
+                const float dR = 2.0f * b * isum;
+                const float dV = a * (0.5f + 0.5f * (sg[i] + sg[j]) * frcp(q[i] + q[j])) + b * (s[i] + s[j]) * isum;
+                Q[i * 3 + j] = ws * dR + wv * dV;
+            }
+        // dP = U Q W^T
+        float T2[9], dP[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                T2[i * 3 + j] = U[i * 3 + 0] * Q[0 * 3 + j] + U[i * 3 + 1] * Q[1 * 3 + j] + U[i * 3 + 2] * Q[2 * 3 + j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                dP[i * 3 + j] = T2[i * 3 + 0] * W[j * 3 + 0] + T2[i * 3 + 1] * W[j * 3 + 1] + T2[i * 3 + 2] * W[j * 3 + 2];
+        // corner forces of dP, grouped by vertex in LDS as in the local step
+        const uint2 lp = M.lpos[e];
+        const uint32_t pos[4] = {lp.x & 0xFFFFu, lp.x >> 16, lp.y & 0xFFFFu, lp.y >> 16};
+        float s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int c = 1; c < 4; ++c) {
+            const float fx = dP[0] * G[(c - 1) * 3 + 0] + dP[1] * G[(c - 1) * 3 + 1] + dP[2] * G[(c - 1) * 3 + 2];
+            const float fy = dP[3] * G[(c - 1) * 3 + 0] + dP[4] * G[(c - 1) * 3 + 1] + dP[5] * G[(c - 1) * 3 + 2];
+            const float fz = dP[6] * G[(c - 1) * 3 + 0] + dP[7] * G[(c - 1) * 3 + 1] + dP[8] * G[(c - 1) * 3 + 2];
+            if (pos[c] != 0xFFFFu) {
+                LF[0][pos[c]] = fx;
+                LF[1][pos[c]] = fy;
+                LF[2][pos[c]] = fz;
+            }
+            s0 += fx;
+            s1 += fy;
+            s2 += fz;
+        }
+        if (pos[0] != 0xFFFFu) {
+            LF[0][pos[0]] = -s0;
+            LF[1][pos[0]] = -s1;
+            LF[2][pos[0]] = -s2;
+        }
+        if (__builtin_expect(oor, 0)) atomicAdd(&M.flags[1], 1u);
+    }
+    __syncthreads();
+    const int32_t p0 = M.blk_part[blockIdx.x], np = M.blk_part[blockIdx.x + 1] - p0;
+    for (int32_t k = threadIdx.x; k < np; k += LBLK) {
+        const int32_t pk = M.part_pack[p0 + k];
+        const int32_t st = pk >> 16, cnt = pk & 0xFFFF;
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        for (int32_t q2 = st; q2 < st + cnt; ++q2) {
+            fx += LF[0][q2];
+            fy += LF[1][q2];
+            fz += LF[2][q2];
+        }
+        M.part[p0 + k] = make_float4(fx, fy, fz, 0.0f);
+    }
+}
+
+// xbar^(k)[a] = sum of the vertex's partials (fixed order); ybar[a] += m_a lambda_a / dt^2
+__global__ __launch_bounds__(BLK) void k_adj_gather(const DevMesh* __restrict__ GM, const double* __restrict__ lam,
+                                                    double* __restrict__ xbar, double* __restrict__ ybar) {
+    const DevMesh& M = GM[0];
+    const int32_t a = blockIdx.x * BLK + threadIdx.x;
+    if (a >= M.n_free) return;
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    for (int32_t j = M.vpart_ptr[a]; j < M.vpart_ptr[a + 1]; ++j) {
+        const float4 f = M.part[M.vpart[j]];
+        fx += f.x;
+        fy += f.y;
+        fz += f.z;
+    }
+    const double m = M.mass[a] / (M.dt * M.dt);
+    xbar[3 * a + 0] = (double)fx;
+    xbar[3 * a + 1] = (double)fy;
+    xbar[3 * a + 2] = (double)fz;
+    ybar[3 * a + 0] += m * lam[3 * a + 0];
+    ybar[3 * a + 1] += m * lam[3 * a + 1];
+    ybar[3 * a + 2] += m * lam[3 * a + 2];
+}
+
+// frame boundaries of the reverse sweep (free rows only):
+//   begin: xk = xbar + vbar / dt, xn = -vbar / dt, ybar = 0
+//   end:   ybar += xk (x^(0) = y), xbar = xn + ybar, vbar = dt ybar
+__global__ __launch_bounds__(BLK) void k_adj_frame(int32_t n3, double dt, int32_t begin, double* __restrict__ xbar,
+                                                   double* __restrict__ vbar, double* __restrict__ xk,
+                                                   double* __restrict__ xn, double* __restrict__ ybar) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= n3) return;
+    if (begin) {
+        xk[i] = xbar[i] + vbar[i] / dt;
+        xn[i] = -vbar[i] / dt;
+        ybar[i] = 0.0;
+    } else {
+        const double yb = ybar[i] + xk[i];
+        xbar[i] = xn[i] + yb;
+        vbar[i] = dt * yb;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Decomposed solve
 // ---------------------------------------------------------------------------
 
@@ -1026,6 +1227,8 @@ hipError_t launch_coarse(const LaunchRef& r, int32_t kind, int32_t group, hipStr
     if (r.nblocks <= 0) return hipSuccess;
     if (group == 64)
         hipLaunchKernelGGL(k_coarse<64>, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active, kind);
+    else if (group == 32)
+        hipLaunchKernelGGL(k_coarse<32>, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active, kind);
     else
         hipLaunchKernelGGL(k_coarse<16>, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active, kind);
     return hipGetLastError();
@@ -1108,6 +1311,28 @@ hipError_t launch_from_user(int32_t nv, int32_t n_free, const int32_t* perm, con
 
 hipError_t launch_refresh_u(const DevMesh& m, hipStream_t s) {
     hipLaunchKernelGGL(k_refresh_u, dim3(nblk(m.nv)), dim3(BLK), 0, s, m.nv, m.x, m.X, m.u);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_local(const DevMesh* dev_mesh, int32_t nt, const double* xk, const double* xk1,
+                            const double* lam, double* gbar, hipStream_t s) {
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_local, dim3(blocks_tets(nt)), dim3(LBLK), 0, s, dev_mesh, xk, xk1, lam, gbar);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_gather(const DevMesh* dev_mesh, int32_t n_free, const double* lam, double* xbar,
+                             double* ybar, hipStream_t s) {
+    if (n_free <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_gather, dim3(nblk(n_free)), dim3(BLK), 0, s, dev_mesh, lam, xbar, ybar);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_frame(int32_t n3, double dt, bool begin, double* xbar, double* vbar, double* xk, double* xn,
+                            double* ybar, hipStream_t s) {
+    if (n3 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_frame, dim3(nblk(n3)), dim3(BLK), 0, s, n3, dt, (int32_t)begin, xbar, vbar, xk, xn,
+                       ybar);
     return hipGetLastError();
 }
 }  // namespace vh

@@ -97,6 +97,10 @@ struct vh_mesh {
     bool use_graph = true;
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // adjoint: checkpoints of the last vh_mesh_adjoint_forward (device, owned)
+    int32_t adj_frames = 0, adj_every = 0;
+    double* adj_ckpt = nullptr;     // [n_ckpt][2][nv][3] (x, v), internal order
+    size_t adj_ckpt_bytes = 0;
 };
 
 namespace vhrt {
@@ -110,6 +114,8 @@ int device_need(vh_mesh* m, size_t* bytes);
 int upload_device(vh_mesh* m);
 // frees every device buffer of the mesh (state included)
 void free_device(vh_mesh* m);
+// frees the adjoint checkpoints of the mesh
+void free_adjoint(vh_mesh* m);
 void charge(vh_ctx* ctx, size_t bytes);
 void uncharge(vh_ctx* ctx, size_t bytes);
 
@@ -129,6 +135,16 @@ int ensure_graph(vh_mesh* m);
 
 // internal device rows -> user-ordered host array [nv][3] (rows >= n given are 0)
 int get_user(vh_mesh* m, const double* dev_int, double* host, int32_t rows, hipStream_t s);
+// user-ordered host [nv][3] -> internal device rows (pinned rows: X if positions, else 0); synchronises s
+int put_user(vh_mesh* m, const double* host, double* dev_int, bool positions, hipStream_t s);
+
+// d = K^{-1} r on the mesh's device vectors (r -> delta; apply: x += d)
+int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta);
+// one local/global iteration (local step, residual, solve with refinement, x += d)
+int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s);
+// VH_ESTATE unless the mesh is prefactored; check_solo: and not driven by a server
+int check_ready(vh_mesh* m);
+int check_solo(vh_mesh* m);
 
 // server teardown (drains its launches); called by vh_ctx_destroy
 void server_destroy(vh_ctx* ctx);

@@ -76,6 +76,8 @@ SIGNATURES = {
     "vh_debug_local_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vh_debug_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_debug_solve": (ctypes.c_int, [_vp, _vp, _vp]),
+    "vh_mesh_adjoint_forward": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _vp, _vp]),
+    "vh_mesh_adjoint_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vh_serve_open": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
     "vh_serve_close": (ctypes.c_int, [_vp]),
     "vh_serve_add": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
@@ -260,6 +262,25 @@ class Mesh:
         n = np.zeros(8, dtype=np.int64)
         _check(_lib.vh_mesh_profile_read(self.h, _ptr(ms), _ptr(n)))
         return {c: (float(ms[i]), int(n[i])) for i, c in enumerate(self.PROFILE_CLASSES) if n[i]}
+
+    # -- discrete adjoint with respect to gamma_s --
+    def adjoint_forward(self, x0, v0, n_frames, ckpt_every=5, stream=None):
+        """Run n_frames from (x0, v0) keeping checkpoints; returns x_final."""
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        v0 = np.ascontiguousarray(v0, dtype=np.float64)
+        xf = np.empty((self.nv, 3))
+        _check(_lib.vh_mesh_adjoint_forward(self.h, _ptr(x0), _ptr(v0), int(n_frames), int(ckpt_every),
+                                            _ptr(xf), _stream_ptr(stream)))
+        return xf
+
+    def adjoint_backward(self, xbar, vbar=None, stream=None):
+        """dLoss/dgamma_s [nt] for dLoss/dx_final = xbar (and dLoss/dv_final = vbar)."""
+        xbar = np.ascontiguousarray(xbar, dtype=np.float64)
+        vb = None if vbar is None else np.ascontiguousarray(vbar, dtype=np.float64)
+        g = np.empty(self.nt)
+        _check(_lib.vh_mesh_adjoint_backward(self.h, _ptr(xbar), None if vb is None else _ptr(vb), _ptr(g),
+                                             _stream_ptr(stream)))
+        return g
 
     # -- per-kernel entry points (clobber the state) --
     def debug_local_step(self, x):
