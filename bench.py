@@ -18,7 +18,9 @@ Prints ONE JSON line with:
   * the FP64 oracle timed on a bounded sample on the host (cpu_baseline) and
     the relative L2 error of the first frame against it;
   * serving: 64 uneven garments, batched against sequential plain stepping
-    (saturated, Poisson arrivals at several rates, a 1 GB HBM budget).
+    (saturated, Poisson arrivals at several rates, a 1 GB HBM budget);
+  * the discrete adjoint with respect to gamma_s on the 20,000-tet slab
+    (30 frames, checkpoints every 5): forward and backward wall times.
 """
 
 from __future__ import annotations
@@ -216,6 +218,8 @@ def run(args):
     ctx.close()
     if args.serving:
         out["serving"] = serving(args)
+    if args.adjoint:
+        out["adjoint"] = adjoint_timing(args)
     print(json.dumps(out), flush=True)
 
 
@@ -397,6 +401,39 @@ def serving(args):
     return out
 
 
+def adjoint_timing(args):
+    """Gradient of 1/2 ||x_30 - x_30(hidden)||^2 with respect to gamma_s on the
+    20,000-tet slab (30 frames of 10 iterations, checkpoints every 5) with the
+    GPU discrete adjoint: forward and backward wall times."""
+    import torch
+    from paper_2405_12484_amd import vhpd
+    import synth
+    p = synth.problem_by_name("slab")
+    ctx = vhpd.Context(0)
+    m = vhpd.Mesh(ctx, p.X, p.tets)
+    x0, v0 = p.initial_state()
+    m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
+    m.prefactor(p.n_subdomains)
+    xt = m.adjoint_forward(x0, v0, 30, 5)
+    gs0 = np.full(p.nt, 1e4)
+    m.set_params(gs0, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
+    m.prefactor(p.n_subdomains)
+    m.adjoint_forward(x0, v0, 30, 5)            # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xf = m.adjoint_forward(x0, v0, 30, 5)
+    t1 = time.perf_counter()
+    d = xf - xt
+    d[p.pinned.astype(bool)] = 0.0
+    g = m.adjoint_backward(d)
+    t2 = time.perf_counter()
+    m.close()
+    ctx.close()
+    return {"workload": "slab_20000tets_8subdomains_30frames_ckpt5", "forward_ms": round((t1 - t0) * 1e3, 2),
+            "backward_ms": round((t2 - t1) * 1e3, 2), "loss": 0.5 * float((d * d).sum()),
+            "grad_norm": float(np.linalg.norm(g))}
+
+
 def cpu_baseline(p, x1_gpu, args):
     """The FP64 oracle (as it stands) on a bounded sample: the first frame of the
     same workload from rest, single-threaded BLAS; its ms/frame, and the GPU's
@@ -434,6 +471,7 @@ def main():
     ap.add_argument("--subdomains", type=int, default=0, help="override the workload's subdomain count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", dest="serving", action="store_false")
+    ap.add_argument("--no-adjoint", dest="adjoint", action="store_false")
     ap.add_argument("--serve-only", action="store_true", help="only the serving runs (one JSON object)")
     ap.add_argument("--serve-frames", type=int, default=10, help="frames per garment, saturated run")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[200.0, 1000.0, 5000.0])

@@ -324,28 +324,35 @@ int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSe
     // interface phases: phase j of every garment whose phase j has the same
     // task kind and lane-group size goes into one launch; each garment's
     // phases stay in their order
+    // (the launch list is complete before `add` keeps pointers into it)
     auto phases = [&](bool fwd, std::vector<CoarseLaunch>& out) {
+        struct Pending {
+            int32_t kind, grp;
+            std::vector<int32_t> g, b, x0, x1;
+        };
+        std::vector<Pending> pend;
         size_t nj = 0;
         for (vh_mesh* m : members) nj = std::max(nj, (fwd ? m->plan.cfwd : m->plan.cbwd).size());
-        out.reserve(2 * nj);
         for (size_t j = 0; j < nj; ++j)
             for (int32_t kind : {(int32_t)vh::PULLSUM, (int32_t)vh::GEMV, (int32_t)vh::BGEMV})
                 for (int32_t grp : {16, 32, 64}) {
-                    std::vector<int32_t> g, b, x0, x1;
+                    Pending p{kind, grp, {}, {}, {}, {}};
                     for (int32_t i = 0; i < ng; ++i) {
                         const auto& ph = fwd ? members[i]->plan.cfwd : members[i]->plan.cbwd;
                         if (j >= ph.size() || ph[j].group != grp || ph[j].kind != kind) continue;
-                        g.push_back(i);
-                        b.push_back(vh::coarse_blocks(ph[j].ntasks, grp));
-                        x0.push_back(ph[j].task0);
-                        x1.push_back(ph[j].ntasks);
+                        p.g.push_back(i);
+                        p.b.push_back(vh::coarse_blocks(ph[j].ntasks, grp));
+                        p.x0.push_back(ph[j].task0);
+                        p.x1.push_back(ph[j].ntasks);
                     }
-                    if (g.empty()) continue;
-                    out.push_back(CoarseLaunch{});
-                    out.back().kind = kind;
-                    out.back().group = grp;
-                    add(&out.back().ref, g, b, x0, x1);
+                    if (!p.g.empty()) pend.push_back(std::move(p));
                 }
+        out.assign(pend.size(), CoarseLaunch{});
+        for (size_t k = 0; k < pend.size(); ++k) {
+            out[k].kind = pend[k].kind;
+            out[k].group = pend[k].grp;
+            add(&out[k].ref, pend[k].g, pend[k].b, pend[k].x0, pend[k].x1);
+        }
     };
     phases(true, L.cfwd);
     phases(false, L.cbwd);

@@ -42,9 +42,8 @@ constexpr int OK = 0, EINVAL_ = -1, ENOMEM_ = -2, ENOTSPD_ = -3;
 constexpr int32_t kMaxInteriorCols = 32;
 // tets per local-step workgroup (one thread per tet)
 constexpr int32_t kLocalBlock = 256;
-// largest dense root supernode formed from the top interface levels
-constexpr int64_t kMaxRootCols = 3000;
-constexpr int32_t kMaxRootLevels = 2;
+// largest interface supernode formed by merging a separator with its children's
+constexpr int64_t kMaxMergedCols = 3000;
 // interface tasks use 32 / 64 lanes from these mean lengths (16 below)
 constexpr int64_t kIfaceG32Min = 96, kIfaceG64Min = 384;
 
@@ -409,20 +408,26 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             msg = "free vertex " + std::to_string(v) + " belongs to no element";
             return EINVAL_;
         }
-    // The top tree levels hold few, large separators, and every level costs the
-    // solve a fixed latency per phase: the separators of the top two levels
-    // form one dense root supernode if it stays within kMaxRootCols columns
-    // (deeper merges add more dense fill than the phases they save).
+    // Every interface tree level costs the solve a fixed latency per phase
+    // (three launches), while the separators are small: the separators at odd
+    // depths (1, 3, 5, ... from the root) join their parent's, halving the
+    // levels, as long as the merged supernode stays within kMaxMergedCols
+    // columns (a merge replaces three sparse blocks by one denser block).
     if (D > 1) {
-        std::vector<int64_t> per_depth(kbits + 1, 0);
+        auto depth_of = [](int32_t h) { return 31 - __builtin_clz((uint32_t)h); };
+        std::vector<int64_t> cnt(D, 0);
         for (int32_t v = 0; v < nv; ++v)
-            if (node[v] >= 1 && node[v] < D) per_depth[31 - __builtin_clz((uint32_t)node[v])]++;
-        int32_t ktop = 1;
-        int64_t cum = per_depth[0];
-        while (ktop < std::min(kbits, kMaxRootLevels) && cum + per_depth[ktop] <= kMaxRootCols)
-            cum += per_depth[ktop++];
+            if (node[v] >= 1 && node[v] < D) cnt[node[v]]++;
+        std::vector<int32_t> into(D);
+        for (int32_t h = 1; h < D; ++h) into[h] = h;
+        for (int32_t h = 2; h < D; ++h) {
+            if (depth_of(h) % 2 == 0) continue;
+            const int32_t par = h >> 1, sib = h ^ 1;
+            const int64_t merged = cnt[par] + cnt[h] + ((sib < D) ? cnt[sib] : 0);
+            if (merged <= kMaxMergedCols) into[h] = par;
+        }
         for (int32_t v = 0; v < nv; ++v)
-            if (node[v] >= 1 && node[v] < D && (31 - __builtin_clz((uint32_t)node[v])) < ktop) node[v] = 1;
+            if (node[v] >= 1 && node[v] < D) node[v] = into[node[v]];
     }
 
     // ---- vertex adjacency ------------------------------------------------------

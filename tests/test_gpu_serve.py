@@ -3,6 +3,8 @@ is bitwise the same served alone, in a mix of uneven garments, sequentially,
 and by plain stepping; admission under an HBM budget is first come, first
 served; misuse is reported."""
 
+import os
+
 import numpy as np
 import pytest
 
@@ -127,6 +129,58 @@ def test_mix_is_bitwise_alone(vh, probs, alone, in_flight, seed):
     assert st["frames_done"] == sum(sum(r) for r in REQUESTS)
     assert st["requests_done"] == sum(len(r) for r in REQUESTS)
     assert st["mean_batch"] > 1.0            # frames of different garments shared launches
+
+
+# interface lane-group thresholds per garment ("g32,g64" mean task lengths):
+# the default, 32 lanes everywhere, 64 lanes everywhere
+LANE_GROUPS = {0: None, 1: "1,100000000", 2: "1,1"}
+
+
+def _add_with_groups(srv, m, p, spec):
+    old = os.environ.pop("VHPD_IFACE_G", None)
+    if spec:
+        os.environ["VHPD_IFACE_G"] = spec
+    try:
+        srv.add(m, p.n_subdomains)
+    finally:
+        os.environ.pop("VHPD_IFACE_G", None)
+        if old is not None:
+            os.environ["VHPD_IFACE_G"] = old
+
+
+def test_mix_of_lane_groups_is_bitwise_alone(vh, probs):
+    """Phase j of the three garments has three lane-group sizes, so one
+    interface phase index becomes several batched launches."""
+    def run(which, seed):
+        ctx = vh.Context(0)
+        srv = vh.Server(ctx, "batched", 2)
+        ms = {}
+        for g in which:
+            ms[g] = new_mesh(vh, ctx, probs[g])
+            _add_with_groups(srv, ms[g], probs[g], LANE_GROUPS[g])
+        rng = np.random.default_rng(seed)
+        queues = {g: list(REQUESTS[g]) for g in which}
+        while any(queues.values()):
+            g = rng.choice([k for k, q in queues.items() if q])
+            srv.submit(ms[g], queues[g].pop(0))
+            srv.tick()
+        srv.drain()
+        st = srv.stats()
+        out = {g: ms[g].read_state() for g in which}
+        srv.close()
+        for m in ms.values():
+            m.close()
+        ctx.close()
+        return out, st
+
+    say("[serve] lane groups alone")
+    alone = {g: run([g], 0)[0][g] for g in range(3)}
+    say("[serve] lane groups mixed")
+    out, st = run([0, 1, 2], 7)
+    for g in range(3):
+        assert np.array_equal(out[g][0], alone[g][0]), g
+        assert np.array_equal(out[g][1], alone[g][1]), g
+    assert st["mean_batch"] > 1.0
 
 
 def test_sequential_mode_is_bitwise_alone(vh, probs, alone):
