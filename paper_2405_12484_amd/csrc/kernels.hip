@@ -404,11 +404,21 @@ __global__ __launch_bounds__(BLK) void k_residual(const DevMesh* __restrict__ GM
     if (a >= n_free) return;
     const int32_t j0 = vpart_ptr[a], j1 = vpart_ptr[a + 1];
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    for (int32_t j = j0; j < j1; ++j) {
-        const float4 f = part[vpart[j]];
-        fx += f.x;
-        fy += f.y;
-        fz += f.z;
+    // up to four partials per round: their indices, then their values, are
+    // loaded together (most vertices have one to three); absent ones add +0
+    for (int32_t j = j0; j < j1; j += 4) {
+        int32_t id[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) id[u] = (j + u < j1) ? vpart[j + u] : -1;
+        float4 f[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f[u] = (id[u] >= 0) ? part[id[u]] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            fx += f[u].x;
+            fy += f[u].y;
+            fz += f[u].z;
+        }
     }
     const double m = mass[a] * inv_dt2;
     r[3 * a + 0] = m * (y[3 * a + 0] - x[3 * a + 0]) + (double)fx;
