@@ -164,11 +164,14 @@ int alloc_plan(vh_mesh* m) {
     return r;
 }
 
-// device bytes of the launch tables of a batch of ng garments with the given
-// per-garment phase counts (an upper bound on build_launch_set's allocation)
-size_t launch_set_bytes(int32_t ng, size_t coarse_phases) {
-    const size_t tab = 7 * (size_t)(4 * ng + 2) + 2 * coarse_phases * (size_t)(4 * ng + 2);
-    return sizeof(vh::DevMesh) * ng + sizeof(int32_t) * (tab + ng);
+// device bytes of the launch set of one garment alone: what build_launch_set
+// allocates for it (one 16-byte table entry per block of each launch)
+size_t launch_set_bytes(const vh::Plan& P) {
+    size_t blocks = 2 * (size_t)vh::blocks_vertices(P.nv) + (size_t)vh::blocks_tets(P.nt) +
+                    2 * (size_t)vh::blocks_vertices(P.n_free) + 2 * (size_t)P.D;
+    for (const auto* ph : {&P.cfwd, &P.cbwd})
+        for (const vh::CPhase& c : *ph) blocks += (size_t)vh::coarse_blocks(c.ntasks, c.group);
+    return sizeof(vh::DevMesh) + sizeof(int32_t) * (4 * blocks + 1);
 }
 
 }  // namespace
@@ -291,20 +294,18 @@ int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSe
     std::vector<int32_t> tab;
     std::vector<std::pair<vh::LaunchRef*, size_t>> fix;   // ref -> table offset
     // per-garment blocks and parameters -> one table
+    // one {garment, block within it, x0, x1} entry per block of the launch
     auto add = [&](vh::LaunchRef* ref, const std::vector<int32_t>& gids, const std::vector<int32_t>& nb,
                    const std::vector<int32_t>& x0, const std::vector<int32_t>& x1) {
-        const size_t off = tab.size();
-        const int32_t n = (int32_t)gids.size();
-        tab.push_back(n);
+        const size_t off = tab.size();   // a multiple of 4: entries stay 16-byte aligned
         int32_t acc = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            tab.push_back(acc);
+        for (size_t i = 0; i < gids.size(); ++i) {
+            for (int32_t lb = 0; lb < nb[i]; ++lb) {
+                const int32_t e[4] = {gids[i], lb, x0[i], x1[i]};
+                tab.insert(tab.end(), e, e + 4);
+            }
             acc += nb[i];
         }
-        tab.push_back(acc);
-        for (int32_t v : gids) tab.push_back(v);
-        for (int32_t v : x0) tab.push_back(v);
-        for (int32_t v : x1) tab.push_back(v);
         ref->nblocks = acc;
         fix.push_back({ref, off});
     };
@@ -497,7 +498,7 @@ int device_need(vh_mesh* m, size_t* bytes) {
     m->dm = keep;
     m->dry = false;
     if (rc != VH_OK) return rc;
-    *bytes = m->dry_bytes + launch_set_bytes(1, std::max(m->plan.cfwd.size(), m->plan.cbwd.size()) * 2);
+    *bytes = m->dry_bytes + launch_set_bytes(m->plan);
     return VH_OK;
 }
 

@@ -50,8 +50,9 @@ struct DevMesh {
 };
 
 // One launch over one or more garments: G is a device array of DevMesh, L the
-// launch table [ng, bstart[0..ng], gid[0..ng-1], x0[0..ng-1], x1[0..ng-1]]
-// (device), active a device array of per-garment flags, nblocks = bstart[ng].
+// launch table (device, 16-byte aligned) of one {garment index into G, block
+// index within the garment, x0, x1} entry per block, active a device array of
+// per-garment flags, nblocks the number of blocks.
 struct LaunchRef {
     const DevMesh* G = nullptr;
     const int32_t* L = nullptr;

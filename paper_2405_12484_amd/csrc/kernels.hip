@@ -23,30 +23,22 @@ namespace {
 
 constexpr int BLK = 256;
 
-// A launch covers one or more garments.  Its table L is
-//   [ng, bstart[0..ng], gid[0..ng-1], x0[0..ng-1], x1[0..ng-1]]
-// (bstart: block prefix; gid: garment index into the DevMesh array; x0, x1:
-// per-garment launch parameters).  A block finds its garment by binary search
-// and skips the work when the garment is not active in this launch.
+// A launch covers one or more garments.  Its table L holds one int4 per block:
+// {g: garment index into the DevMesh array, lb: block index within the
+// garment, x0, x1: per-garment launch parameters}, so a block finds its
+// garment with one load, and skips the work when the garment is not active in
+// this launch.
 struct Slot {
     int32_t g, lb, x0, x1;
 };
 
 __device__ __forceinline__ bool slot_of(const int32_t* __restrict__ L, const int32_t* __restrict__ active,
                                         Slot& s) {
-    const int32_t ng = L[0];
-    const int32_t* bs = L + 1;
-    const int32_t b = blockIdx.x;
-    int32_t lo = 0, hi = ng;
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (bs[mid] <= b) lo = mid;
-        else hi = mid;
-    }
-    s.g = L[2 + ng + lo];
-    s.lb = b - bs[lo];
-    s.x0 = L[2 + 2 * ng + lo];
-    s.x1 = L[2 + 3 * ng + lo];
+    const int4 v = reinterpret_cast<const int4*>(L)[blockIdx.x];
+    s.g = v.x;
+    s.lb = v.y;
+    s.x0 = v.z;
+    s.x1 = v.w;
     return active[s.g] != 0;
 }
 
