@@ -371,6 +371,16 @@ def serving(args):
             r[mode] = _serve_stats(st)
             print(f"# serving poisson {rate}/s {mode}: {r[mode]}", file=sys.stderr, flush=True)
         res["poisson"][str(rate)] = r
+    if args.serve_full:
+        # the whole stream: every garment asks for 150 frames, one per request,
+        # at an aggregate 200 requests/s (9,600 requests, about 48 s per mode)
+        arr = _poisson(200.0, ng * 150, [150] * ng)
+        r = {"requests": len(arr), "rate_per_s": 200.0, "frames_per_garment": 150}
+        for mode in ("batched", "sequential"):
+            st = session(mode, arr)
+            r[mode] = _serve_stats(st)
+            print(f"# serving full stream 200/s {mode}: {r[mode]}", file=sys.stderr, flush=True)
+        res["poisson_full_stream"] = r
     # admission under a budget: every garment leaves the device after its last
     # request, making room for the ones waiting in FIFO order
     srv = vhpd.Server(ctx, "batched", args.serve_in_flight)
@@ -476,6 +486,8 @@ def main():
     ap.add_argument("--serve-frames", type=int, default=10, help="frames per garment, saturated run")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[200.0, 1000.0, 5000.0])
     ap.add_argument("--serve-requests", type=int, default=600, help="requests per Poisson run")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="also serve the whole 200/s stream (150 frames per garment; about 100 s)")
     ap.add_argument("--serve-in-flight", type=int, default=2)
     ap.add_argument("--serve-budget-gb", type=float, default=1.0)
     ap.add_argument("--serve-budget-rate", type=float, default=1000.0)
