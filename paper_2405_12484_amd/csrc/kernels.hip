@@ -182,15 +182,19 @@ __device__ __forceinline__ float plus_delta(float sg, float mu, float& q) {
 
 // Nearest volume-preserving singular values (Eq. vol_pre): the Lagrange
 // condition gives s_i (s_i - sigma_i) = mu for all i; Newton on
-// h(mu) = ln(s1 s2 s3)(mu) from mu = 0, at most 8 steps, stop when
-// |s1 s2 s3 - 1| is within 2 ulp of 1.  Near the root ln p is replaced by
-// (p - 1)/p, which has the same root and slope.  Returns ds_i = s_i - sigma_i.
+// h(mu) = ln(s1 s2 s3)(mu) from mu = 0, stop when |s1 s2 s3 - 1| is within
+// 2 ulp of 1, at most kSl3Steps steps.  Near the root ln p is replaced by
+// (p - 1)/p, which has the same root and slope.  Strains of a few percent take
+// 3-4 steps; strongly compressed, nearly flat or inverted elements (sigma_3
+// down to 1e-3, det F close to 2) take up to 10-12, and 16 leaves margin.
+// Returns ds_i = s_i - sigma_i.
+constexpr int kSl3Steps = 16;
 __device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_of_regime) {
     const float lo = (sg[2] > 0.0f) ? -0.25f * sg[2] * sg[2] : 0.0f;
     float mu = (sg[2] > 0.0f) ? 0.0f : 0.25f;
     float q[3], s[3];
 #pragma unroll 1
-    for (int it = 0; it < 8; ++it) {
+    for (int it = 0; it < kSl3Steps; ++it) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             ds[i] = plus_delta(sg[i], mu, q[i]);
@@ -208,7 +212,7 @@ __device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_o
         float mun = mu - step;
         if (!(mun > lo)) mun = 0.5f * (mu + lo);
         mu = mun;
-        if (it == 7) {
+        if (it == kSl3Steps - 1) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 ds[i] = plus_delta(sg[i], mu, q[i]);

@@ -52,6 +52,48 @@ def test_local_step_matches_oracle(vh, ctx, name):
     m.close()
 
 
+def _shared_regime(S, s_ref):
+    """Elements where the oracle's projection is the + branch root (Eq. vol_pre
+    has one: always when det F <= 1, else when h(-sigma_min^2 / 4) <= 0) and
+    the device keeps its Newton result (det F < 2, no clamp)."""
+    det = S.prod(axis=1)
+    smin = np.abs(S).min(axis=1)
+    arg = np.maximum(S * S - smin[:, None] ** 2, 0.0)
+    h_lo = np.log(np.maximum((S + np.sqrt(arg)) / 2, 1e-300)).sum(axis=1)
+    plus_root = (det <= 1.0) | (h_lo <= 0.0)
+    return plus_root & (det < 2.0) & (s_ref.min(axis=1) > 0.011)
+
+
+@pytest.mark.parametrize("amp", [0.01, 0.02])
+def test_local_step_large_strain_and_inverted(vh, ctx, amp):
+    """Singular values from about 0.25 to 3.7, and (amp 0.02) inverted elements."""
+    say(f"[local] large strain amp={amp}")
+    p = synth.problem_by_name("box")
+    m = make_mesh(vh, ctx, p)
+    sim = oracle.OracleSim.from_problem(p)
+    x = deformed(p, amp=amp, seed=1)
+    T, sig, s = m.debug_local_step(x)
+    loc = oracle.local_step(x, sim.tets, sim.grads, sim.w_s, sim.w_v)
+    S = loc["sigma"]
+    keep = _shared_regime(S, loc["s"])
+    n_inv = int((S[:, 2] < 0).sum())
+    say(f"[local] amp={amp}: {keep.sum()} of {len(S)} elements compared, {n_inv} inverted")
+    assert keep.sum() > 0.9 * len(S)
+    if amp >= 0.02:
+        assert (keep & (S[:, 2] < 0)).sum() > 0      # inverted elements are in the comparison
+    Tref = loc["P"] - (sim.w_s + sim.w_v)[:, None, None] * loc["F"]
+    w = (sim.w_s + sim.w_v)[:, None, None]
+    err = (np.abs(T - Tref) / w).max(axis=(1, 2))
+    # the rotation's sensitivity to rounding of F grows like 2 / (sigma_i + sigma_j)
+    pair = np.minimum.reduce([S[:, 0] + S[:, 1], S[:, 0] + S[:, 2], S[:, 1] + S[:, 2]])
+    scale = np.maximum(1.0, np.abs(S).max(axis=1)) * np.maximum(1.0, 2.0 / np.abs(pair))
+    assert (err[keep] / scale[keep]).max() < 2e-5, (err[keep] / scale[keep]).max()
+    big = np.maximum(1.0, np.abs(S).max(axis=1))[:, None]
+    assert (np.abs(sig - S) / big)[keep].max() < 4e-6
+    assert (np.abs(s - loc["s"]) / big)[keep].max() < 4e-6
+    m.close()
+
+
 def test_local_step_rigid_rotation_zero_stress(vh, ctx):
     say("[local] rigid rotation")
     p = synth.problem_by_name("box")
