@@ -211,6 +211,9 @@ def run(args):
         "prefactor_s": round(prefactor_s, 3),
     }
 
+    if not args.no_embed:
+        out["embed"] = embed_timing(mesh, p, stream, torch)
+        print(f"# embed: {out['embed']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"], err = cpu_baseline(p, x1, args)
         out["rel_l2_first_frame_vs_oracle"] = err
@@ -221,6 +224,35 @@ def run(args):
     if args.adjoint:
         out["adjoint"] = adjoint_timing(args)
     print(json.dumps(out), flush=True)
+
+
+def embed_timing(mesh, p, stream, torch, per_tet=4, reps=20):
+    """Positions of points embedded in the shell (Eq. m2y) for the current
+    state: `per_tet` seeded points per tet, one k_embed launch per call.
+    Algorithmic bytes: a 32-byte record and a 24-byte output row per point,
+    plus each vertex position (24 bytes) read once."""
+    import synth
+    tet, P = synth.yarn_points(p.X, p.tets, per_tet=per_tet)
+    mesh.set_embedding(tet, P)
+    n = len(tet)
+    out_t = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    mesh.embed_device(out_t, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        mesh.embed_device(out_t, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    nbytes = 56 * n + 24 * p.nv
+    gbs = nbytes / (us * 1e-6) / 1e9
+    mesh.set_embedding(np.zeros(0, dtype=np.int32), np.zeros((0, 3)))
+    return {"kernel": "k_embed", "points": n, "points_per_tet": per_tet, "bound": "hbm",
+            "bytes_per_launch": nbytes, "avg_launch_us": round(us, 3), "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "mpoints_per_s": round(n / us, 1)}
 
 
 def _serve_stats(st, extra=None):
@@ -486,6 +518,7 @@ def main():
     ap.add_argument("--serve-frames", type=int, default=10, help="frames per garment, saturated run")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[200.0, 1000.0, 5000.0])
     ap.add_argument("--serve-requests", type=int, default=600, help="requests per Poisson run")
+    ap.add_argument("--no-embed", action="store_true", help="skip the embedded-point timing")
     ap.add_argument("--serve-full", action="store_true",
                     help="also serve the whole 200/s stream (150 frames per garment; about 100 s)")
     ap.add_argument("--serve-in-flight", type=int, default=2)

@@ -152,6 +152,27 @@ int vh_mesh_profile_read(vh_mesh* mesh, double* ms, int64_t* launches);
  * overwrite only their outputs; the solve kernels only their work vectors. */
 int vh_mesh_time_kernel(vh_mesh* mesh, int32_t kernel_class, int32_t reps, void* stream);
 
+/* ---- Embedded points (Eq. m2y): positions of points carried by the mesh,
+ * e.g. the vertices of yarn curves, phi(x) = N x, where row i of N holds the
+ * linear shape functions N_0..N_3 of point i's tet evaluated at the point's
+ * rest position (natural coordinates N_1..3 = Dm^{-1} (X^i - X_0), N_0 =
+ * 1 - N_1 - N_2 - N_3, Dm the tet's rest edge matrix).  Points outside their
+ * tet are extrapolated linearly. ---- */
+
+/* Set (replace) the embedded points: tet[n_points] user element indices and
+ * rest_xyz[n_points][3] rest positions (float64), both copied.  n_points = 0
+ * clears.  N is formed in FP64 on the host and stored as FP32 next to the
+ * tet's four vertex ids (32 bytes per point on the device, plus a 24-byte
+ * output row; charged to the HBM budget when the mesh is resident).
+ * VH_EINVAL on n_points < 0, null arrays or a tet index out of range. */
+int vh_mesh_set_embedding(vh_mesh* mesh, int32_t n_points, const int32_t* tet, const double* rest_xyz);
+/* Positions of the embedded points for the current state, [n_points][3]
+ * float64 in the order given: into host `out` (synchronises `stream`), or into
+ * device `out_dev` (asynchronous on `stream`).  The mesh must be prefactored
+ * and, when it is driven by the server, have no frames pending (VH_ESTATE). */
+int vh_mesh_embed(vh_mesh* mesh, double* out, void* stream);
+int vh_mesh_embed_device(vh_mesh* mesh, double* out_dev, void* stream);
+
 /* ---- Discrete adjoint with respect to gamma_s (gradients of a trajectory).
  *
  * The forward map is n_frames PD steps (Sec. 7) from (x0, v0); the adjoint

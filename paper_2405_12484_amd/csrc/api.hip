@@ -269,6 +269,7 @@ void free_launch_set(vh_ctx* ctx, LaunchSet& L) {
 
 void free_device(vh_mesh* m) {
     free_adjoint(m);
+    free_embedding_device(m);
     if (m->gexec) {
         (void)hipGraphExecDestroy(m->gexec);
         m->gexec = nullptr;

@@ -80,6 +80,8 @@ hipError_t launch_coarse(const LaunchRef& r, int32_t kind, int32_t group, hipStr
 hipError_t launch_interior_bwd(const LaunchRef& r, size_t lds, hipStream_t s, bool apply, bool keep_delta);
 hipError_t launch_refine_residual(const LaunchRef& r, hipStream_t s);
 hipError_t launch_velocity(const LaunchRef& r, hipStream_t s);
+// embedded points: out[n][3] (internal record order) from the internal state x
+hipError_t launch_embed(const float4* rec, const double* x, int32_t n, double* out, hipStream_t s);
 
 }  // namespace vh
 

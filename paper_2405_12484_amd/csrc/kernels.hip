@@ -422,6 +422,27 @@ __global__ __launch_bounds__(BLK) void k_residual(const DevMesh* __restrict__ GM
     r[3 * a + 2] = m * (y[3 * a + 2] - x[3 * a + 2]) + (double)fz;
 }
 
+// Embedded points (Eq. m2y): p = N x over the four vertices of the point's tet,
+// evaluated as x_0 + sum_{a=1..3} N_a (x_a - x_0) in FP64 with N_1..3 stored as
+// FP32 (N_0 = 1 - N_1 - N_2 - N_3 is implied).  Records: two float4 per point,
+// {v0, v1, v2, v3} (internal vertex ids, as int bits) and {N_1, N_2, N_3, 0}.
+__global__ __launch_bounds__(BLK) void k_embed(const float4* __restrict__ rec, const double* __restrict__ x,
+                                               int32_t n, double* __restrict__ out) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= n) return;
+    const float4 r0 = rec[2 * (size_t)i], r1 = rec[2 * (size_t)i + 1];
+    const double* x0 = x + 3 * (size_t)__float_as_int(r0.x);
+    const double* x1 = x + 3 * (size_t)__float_as_int(r0.y);
+    const double* x2 = x + 3 * (size_t)__float_as_int(r0.z);
+    const double* x3 = x + 3 * (size_t)__float_as_int(r0.w);
+    const double n1 = r1.x, n2 = r1.y, n3 = r1.z;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double b = x0[c];
+        out[3 * (size_t)i + c] = b + n1 * (x1[c] - b) + n2 * (x2[c] - b) + n3 * (x3[c] - b);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Discrete adjoint of the PD iteration with respect to gamma_s (one garment).
 // For x^(k+1) = L^{-1} b(x^(k)) and lambda = L^{-1} xbar^(k+1):
@@ -1252,6 +1273,12 @@ hipError_t launch_interior_bwd(const LaunchRef& r, size_t lds, hipStream_t s, bo
 hipError_t launch_refine_residual(const LaunchRef& r, hipStream_t s) {
     if (r.nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_refine, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active);
+    return hipGetLastError();
+}
+
+hipError_t launch_embed(const float4* rec, const double* x, int32_t n, double* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_embed, dim3((n + BLK - 1) / BLK), dim3(BLK), 0, s, rec, x, n, out);
     return hipGetLastError();
 }
 

@@ -101,11 +101,19 @@ struct vh_mesh {
     int32_t adj_frames = 0, adj_every = 0;
     double* adj_ckpt = nullptr;     // [n_ckpt][2][nv][3] (x, v), internal order
     size_t adj_ckpt_bytes = 0;
+    // embedded points (Eq. m2y): host definition, and device records built
+    // from it while the mesh is resident (freed with the device data)
+    std::vector<int32_t> emb_tet;   // user element per point
+    std::vector<double> emb_X;      // rest positions [n][3]
+    float4* emb_rec = nullptr;      // 2 float4 per point
+    double* emb_out = nullptr;      // [n][3] device staging for host reads
+    size_t emb_bytes = 0;
 };
 
 namespace vhrt {
 
 int set_device(vh_mesh* m);
+void free_embedding_device(vh_mesh* m);
 // host FP64 factorization into m->plan (no device memory)
 int host_factor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps);
 // device bytes the upload of m->plan will take (budgeted allocations)
@@ -142,9 +150,11 @@ int put_user(vh_mesh* m, const double* host, double* dev_int, bool positions, hi
 int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta);
 // one local/global iteration (local step, residual, solve with refinement, x += d)
 int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s);
-// VH_ESTATE unless the mesh is prefactored; check_solo: and not driven by a server
+// VH_ESTATE unless the mesh is prefactored; check_solo: and not driven by a
+// server; check_quiet: and no server frames of it pending
 int check_ready(vh_mesh* m);
 int check_solo(vh_mesh* m);
+int check_quiet(vh_mesh* m);
 
 // server teardown (drains its launches); called by vh_ctx_destroy
 void server_destroy(vh_ctx* ctx);

@@ -76,6 +76,9 @@ SIGNATURES = {
     "vh_debug_local_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vh_debug_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_debug_solve": (ctypes.c_int, [_vp, _vp, _vp]),
+    "vh_mesh_set_embedding": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
+    "vh_mesh_embed": (ctypes.c_int, [_vp, _vp, _vp]),
+    "vh_mesh_embed_device": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_mesh_adjoint_forward": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _vp, _vp]),
     "vh_mesh_adjoint_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vh_serve_open": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
@@ -228,6 +231,29 @@ class Mesh:
                 raise ValueError("state tensors must be contiguous float64 [nv, 3]")
         _check(_lib.vh_mesh_read_state_device(self.h, ctypes.c_void_p(x_t.data_ptr()),
                                               ctypes.c_void_p(v_t.data_ptr()), _stream_ptr(stream)))
+
+    # -- embedded points (Eq. m2y) --
+    def set_embedding(self, tet, rest_xyz):
+        """Points carried by the mesh: tet[n] user element indices, rest_xyz[n, 3]."""
+        tet = np.ascontiguousarray(tet, dtype=np.int32)
+        rest = np.ascontiguousarray(rest_xyz, dtype=np.float64)
+        if tet.ndim != 1 or rest.shape != (tet.shape[0], 3):
+            raise ValueError("tet must be [n] and rest_xyz [n, 3]")
+        _check(_lib.vh_mesh_set_embedding(self.h, int(tet.shape[0]), _ptr(tet), _ptr(rest)))
+        self.n_embedded = int(tet.shape[0])
+
+    def embed(self, stream=None):
+        """Positions of the embedded points for the current state, [n, 3] float64."""
+        out = np.empty((getattr(self, "n_embedded", 0), 3))
+        _check(_lib.vh_mesh_embed(self.h, _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def embed_device(self, out_t, stream=None):
+        """Same into a contiguous float64 [n, 3] device tensor (asynchronous)."""
+        n = getattr(self, "n_embedded", 0)
+        if out_t.dtype.__str__() != "torch.float64" or tuple(out_t.shape) != (n, 3) or not out_t.is_contiguous():
+            raise ValueError("output must be a contiguous float64 [n, 3] tensor")
+        _check(_lib.vh_mesh_embed_device(self.h, ctypes.c_void_p(out_t.data_ptr()), _stream_ptr(stream)))
 
     def write_state_device(self, x_t, v_t, stream=None):
         for t in (x_t, v_t):

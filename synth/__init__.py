@@ -17,3 +17,4 @@ from .meshes import (  # noqa: F401
     serving_garment_sizes,
     serving_shell_problem,
 )
+from .yarn import yarn_points  # noqa: F401
