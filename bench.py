@@ -320,6 +320,7 @@ def serving(args):
     probs = [synth.serving_shell_problem(int(n), 100 + g) for g, n in enumerate(sizes)]
     gen_s = time.perf_counter() - t0
     torch.cuda.init()
+    copy_cal = copy_calibration(torch)      # also the reference dispatch for scaling rocprofv3 counters
     ctx = vhpd.Context(0)
     meshes = []
     for p in probs:
@@ -330,7 +331,7 @@ def serving(args):
     out = {"garments": ng, "tets_total": int(sum(p.nt for p in probs)),
            "tets_min": int(min(p.nt for p in probs)), "tets_max": int(max(p.nt for p in probs)),
            "subdomains": sorted({int(p.n_subdomains) for p in probs}), "dt": probs[0].dt,
-           "pd_iters": probs[0].pd_iters, "generate_s": round(gen_s, 2)}
+           "pd_iters": probs[0].pd_iters, "generate_s": round(gen_s, 2), "hbm_copy_calibration": copy_cal}
     # host factorization + upload of every garment (outside every timed window)
     t0 = time.perf_counter()
     srv = vhpd.Server(ctx, "batched", args.serve_in_flight)
