@@ -845,6 +845,30 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         }
         double* vals = (s.sub >= 0) ? ivd.data() : P.dvals.data();
         const int64_t tri = (int64_t)n * (n + 1) / 2;
+        if (s.sub < 0 && m == 0) {
+            // an interface root (no rows below): its forward and backward
+            // solves compose to d = Ti^T Ti r', so the full symmetric
+            // A = Ti^T Ti (n^2 <= 2 tri values, both layouts' space) is stored
+            // row-major and applied in one pass.  A[i][j] = sum_{k >= max(i, j)}
+            // Ti[k][i] Ti[k][j], dot products of Ti's columns.
+            std::vector<double> TC((size_t)n * n, 0.0);   // TC[i][k] = Ti[k][i]
+            for (int32_t k = 0; k < n; ++k)
+                for (int32_t i = 0; i <= k; ++i) TC[(size_t)i * n + k] = Ti[(size_t)k * n + i];
+            double* A = vals + s.wf_off;
+#pragma omp parallel for schedule(dynamic, 8) if (par)
+            for (int32_t i = 0; i < n; ++i) {
+                const double* ci = &TC[(size_t)i * n];
+                for (int32_t j = i; j < n; ++j) {
+                    const double* cj = &TC[(size_t)j * n];
+                    double acc = 0.0;
+                    for (int32_t k = j; k < n; ++k) acc += ci[k] * cj[k];
+                    A[(int64_t)i * n + j] = acc;
+                    A[(int64_t)j * n + i] = acc;
+                }
+            }
+            upd[t].clear();
+            return OK;
+        }
         for (int32_t a = 0; a < n; ++a)
             for (int32_t b = 0; b <= a; ++b) vals[s.wf_off + (int64_t)a * (a + 1) / 2 + b] = Ti[(size_t)a * n + b];
         for (int32_t p = 0; p < m; ++p)
@@ -1138,6 +1162,20 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             const Supernode& S = SN[t];
             const int32_t n = S.n, m = (int32_t)S.rows.size();
             const int64_t tri = (int64_t)n * (n + 1) / 2;
+            if (m == 0) {
+                // a root: rows of A = Ti^T Ti straight into the solution
+                for (int32_t i = 0; i < n; ++i) {
+                    CTask c{};
+                    c.a[0] = 2;
+                    c.a[1] = S.col0 - P.n_int + i;
+                    c.a[2] = (int32_t)(S.wf_off + (int64_t)i * n);
+                    c.a[3] = n;
+                    c.a[4] = S.col0 - P.n_int;
+                    tl += n;
+                    P.ctasks.push_back(c);
+                }
+                continue;
+            }
             for (int32_t i = 0; i < n + m; ++i) {
                 CTask c{};
                 c.a[0] = (i < n) ? 0 : 1;
@@ -1158,6 +1196,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             if (SN[t].sub >= 0 || SN[t].clevel != l) continue;
             const Supernode& S = SN[t];
             const int32_t n = S.n, m = (int32_t)S.rows.size();
+            if (m == 0) continue;   // a root was solved whole in the forward pass
             for (int32_t k = 0; k < n; ++k) {
                 CTask c{};
                 c.a[0] = S.col0 - P.n_int + k;

@@ -886,7 +886,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
 
 // Interface phases, one group of G lanes per task (FP64).
 //   PULLSUM: rg[row] = r[row] - sum FP32 slots - sum FP64 slots
-//   GEMV:    zg[idx] or cgd[idx] = row of W . rg
+//   GEMV:    zg[idx], cgd[idx] or (a root, rows of Ti^T Ti) dg[idx] = row . rg
 //   BGEMV:   dg[out] = Ti column . zg + (-W_B) column . dg[gather]
 template <int G>
 __global__ __launch_bounds__(BLK) void k_coarse(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
@@ -996,7 +996,8 @@ __global__ __launch_bounds__(BLK) void k_coarse(const DevMesh* __restrict__ GM, 
             op[2] = rp[2] - s2;
             return;
         }
-        if (kind == GEMV) op = (T.a[0] == 0) ? a.zg + 3 * T.a[1] : a.cgd + 3 * (size_t)T.a[1];
+        if (kind == GEMV) op = (T.a[0] == 0) ? a.zg + 3 * T.a[1]
+                               : (T.a[0] == 1) ? a.cgd + 3 * (size_t)T.a[1] : a.dg + 3 * T.a[1];
         else op = a.dg + 3 * T.a[0];
         op[0] = s0;
         op[1] = s1;

@@ -47,7 +47,8 @@ struct Chunk {
 
 // Interface task (global memory, FP64 values):
 //   PULLSUM: {row, FP32-slot list offset, count, FP64-slot list offset, count}
-//   GEMV:    {dest (0 z, 1 FP64 slot), index, value offset, len, x offset}
+//   GEMV:    {dest (0 z, 1 FP64 slot, 2 solution d), index, value offset, len, x offset}
+//            (dest 2: a root supernode, whose rows of A = Ti^T Ti give d at once)
 //   BGEMV:   {out, value offset, len1, z offset, len2, gather list offset}
 struct CTask {
     int32_t a[8];

@@ -113,7 +113,8 @@ void vhp_solve(void* h, const double* rhs, double* d) {
                     double acc = 0.0;
                     for (int k = 0; k < a[3]; ++k) acc += P.dvals[a[2] + k] * rg[a[4] + k];
                     if (a[0] == 0) zg[a[1]] = acc;
-                    else CGD[a[1]] = acc;
+                    else if (a[0] == 1) CGD[a[1]] = acc;
+                    else dg[a[1]] = acc;
                 }
             }
         // interface backward
