@@ -274,6 +274,43 @@ def test_errors_are_reported(vh, ctx):
     m.close()
 
 
+def test_degenerate_meshes(vh, ctx):
+    """Every vertex pinned (no unknowns: the state stays at rest exactly), zero
+    frames, and a single tet with one free vertex against the oracle."""
+    say("[degenerate] all pinned")
+    p = synth.problem_by_name("box")
+    m = make_mesh(vh, ctx, p, pinned=np.ones(p.nv, dtype=np.uint8))
+    assert m.info()["n_free"] == 0
+    m.step(0)
+    m.step(3)
+    x, v = m.read_state()
+    assert np.array_equal(x, p.X) and not np.any(v)
+    m.close()
+    say("[degenerate] single tet")
+    X = np.array([[0.0, 0.0, 0.0], [0.01, 0.0, 0.0], [0.0, 0.01, 0.0], [0.003, 0.002, 0.01]])
+    T = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    gs, gv = np.array([1e4]), np.array([3e3])
+    mass = np.full(4, 1e-4)
+    pins = np.array([1, 1, 1, 0], dtype=np.uint8)
+    g = np.array([0.0, 0.0, -9.8])
+    m = vh.Mesh(ctx, X, T)
+    m.set_params(gs, gv, mass, pins, g, 1.0 / 150, 10)
+    with pytest.raises(vh.VHError) as ei:
+        m.prefactor(2)                                    # more subdomains than elements
+    assert ei.value.code == vh.VH_EINVAL
+    m.prefactor(1)
+    m.step(5)
+    x, _ = m.read_state()
+    sim = oracle.OracleSim(X, T, gs, gv, mass, pins, g, 1.0 / 150, 10)
+    xo, vo = X.copy(), np.zeros_like(X)
+    for _ in range(5):
+        xo, vo = sim.step(xo, vo)
+    err = rel_disp(x, xo, X)
+    say(f"[degenerate] single tet after 5 frames: displacement-relative {err:.2e}")
+    assert rel_l2(x, xo) < 1e-5 and err < 1e-4
+    m.close()
+
+
 def test_budget_refuses(vh):
     say("[budget]")
     p = synth.problem_by_name("box")
