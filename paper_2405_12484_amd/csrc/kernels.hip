@@ -761,6 +761,14 @@ __device__ __forceinline__ Chunk chunk_desc(const Chunk* __restrict__ chunks, co
 template <class F>
 __device__ __forceinline__ void chunk_pipeline(const Chunk* __restrict__ chunks, const float4* __restrict__ iv4,
                                                int32_t c0, int32_t c1, float* sm, int4* cd, F&& compute) {
+    // the first chunk's descriptor comes straight from global memory, so its
+    // load is in flight while the descriptor table is staged
+    ChunkRegs ra, rb;   // ra: next chunk for buffer 1, rb: next chunk for buffer 0
+    Chunk K0{};
+    if (c0 < c1) {
+        K0 = chunks[c0];
+        chunk_load(iv4 + K0.v0 / 4, (K0.nv + 3) / 4, ra);
+    }
     for (int32_t c = c0 + (int32_t)threadIdx.x; c < min(c1, c0 + CHD); c += BLKI) {
         const Chunk K = chunks[c];
         cd[c - c0] = make_int4(K.kind, K.ntasks, K.v0, K.nv);
@@ -769,9 +777,7 @@ __device__ __forceinline__ void chunk_pipeline(const Chunk* __restrict__ chunks,
     if (c0 >= c1) return;
     float* buf0 = sm;
     float* buf1 = sm + CHI;
-    ChunkRegs ra, rb;   // ra: next chunk for buffer 1, rb: next chunk for buffer 0
-    Chunk K0 = chunk_desc(chunks, cd, c0, c0), K1 = K0, N0 = K0, N1 = K0;
-    chunk_load(iv4 + K0.v0 / 4, (K0.nv + 3) / 4, ra);
+    Chunk K1 = K0, N0 = K0, N1 = K0;
     chunk_store(reinterpret_cast<float4*>(buf0), (K0.nv + 3) / 4, ra);
     if (c0 + 1 < c1) {
         N1 = chunk_desc(chunks, cd, c0, c0 + 1);
@@ -1033,6 +1039,36 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
         const int32_t k = i / 3, c = i - 3 * k;
         DL[3 * n_loc + i] = (float)a.dg[3 * (a.bnd[b0 + k] - a.n_int) + c];
     }
+    // this thread's first interior row: x and X fetched now for the update at the end
+    double px[3] = {0.0, 0.0, 0.0}, pX[3] = {0.0, 0.0, 0.0};
+    if (apply && tid < n_loc) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            px[c] = a.x[3 * (size_t)(base + tid) + c];
+            pX[c] = a.X[3 * (size_t)(base + tid) + c];
+        }
+    }
+    // a slice of the interface rows (their values are final): updated first,
+    // while the first chunks load
+    {
+        const int32_t chunk = (a.n_gamma + a.D - 1) / a.D;
+        const int32_t g0 = d * chunk, g1 = min(a.n_gamma, g0 + chunk);
+        for (int32_t i = g0 + tid; i < g1; i += BLKI) {
+            const int32_t gi = a.n_int + i;
+            float du[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double dv = a.dg[3 * i + c];
+                if (keep_delta) a.delta[3 * gi + c] = dv;
+                if (apply) {
+                    const double xn = a.x[3 * gi + c] + dv;
+                    a.x[3 * gi + c] = xn;
+                    du[c] = (float)(xn - a.X[3 * gi + c]);
+                }
+            }
+            if (apply) a.u[gi] = make_float4(du[0], du[1], du[2], 0.0f);
+        }
+    }
     const int32_t c0 = a.sub_bwd_ch[d], c1 = a.sub_bwd_ch[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
     const int wave = tid / 64, lane = tid % 64;
@@ -1119,33 +1155,18 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
     // interior rows of this subdomain
     for (int32_t i = tid; i < n_loc; i += BLKI) {
         const int32_t gi = base + i;
+        const bool first = (i == tid);
         float du[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double dv = (double)DL[3 * i + c];
             if (keep_delta) a.delta[3 * gi + c] = dv;
             if (apply) {
-                const double xn = a.x[3 * gi + c] + dv;
+                const double xo = first ? px[c] : a.x[3 * gi + c];
+                const double Xo = first ? pX[c] : a.X[3 * gi + c];
+                const double xn = xo + dv;
                 a.x[3 * gi + c] = xn;
-                du[c] = (float)(xn - a.X[3 * gi + c]);
-            }
-        }
-        if (apply) a.u[gi] = make_float4(du[0], du[1], du[2], 0.0f);
-    }
-    // a slice of the interface rows
-    const int32_t chunk = (a.n_gamma + a.D - 1) / a.D;
-    const int32_t g0 = d * chunk, g1 = min(a.n_gamma, g0 + chunk);
-    for (int32_t i = g0 + tid; i < g1; i += BLKI) {
-        const int32_t gi = a.n_int + i;
-        float du[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double dv = a.dg[3 * i + c];
-            if (keep_delta) a.delta[3 * gi + c] = dv;
-            if (apply) {
-                const double xn = a.x[3 * gi + c] + dv;
-                a.x[3 * gi + c] = xn;
-                du[c] = (float)(xn - a.X[3 * gi + c]);
+                du[c] = (float)(xn - Xo);
             }
         }
         if (apply) a.u[gi] = make_float4(du[0], du[1], du[2], 0.0f);
