@@ -311,6 +311,44 @@ def test_degenerate_meshes(vh, ctx):
     m.close()
 
 
+def test_refinement_steps(vh, ctx):
+    """Refinement against the FP64 residual (k_refine + further solves): the
+    refined trajectory meets the same bar, differs from the plain one, and is
+    bitwise the same when two copies of the garment are served batched."""
+    say("[refine]")
+    p = synth.problem_by_name("shell_small")
+    sim = oracle.OracleSim.from_problem(p)
+    xo, vo = p.initial_state()
+    for _ in range(3):
+        xo, vo = sim.step(xo, vo)
+    res = {}
+    for R in (0, 2):
+        m = make_mesh(vh, ctx, p, refine=R)
+        m.step(3)
+        res[R] = m.read_state()[0]
+        m.close()
+        say(f"[refine] steps={R}: rel L2 vs oracle {rel_l2(res[R], xo):.2e}")
+    assert rel_l2(res[2], xo) < 1e-5
+    assert not np.array_equal(res[0], res[2])
+    c2 = vh.Context(0)
+    srv = vh.Server(c2, "batched", 2)
+    ms = []
+    for _ in range(2):
+        mm = vh.Mesh(c2, p.X, p.tets)
+        mm.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
+        srv.add(mm, p.n_subdomains, 2)
+        ms.append(mm)
+    for mm in ms:
+        srv.submit(mm, 3)
+    srv.drain()
+    assert srv.stats()["mean_batch"] > 1.0
+    srv.close()
+    for mm in ms:
+        assert np.array_equal(mm.read_state()[0], res[2])
+        mm.close()
+    c2.close()
+
+
 def test_budget_refuses(vh):
     say("[budget]")
     p = synth.problem_by_name("box")
