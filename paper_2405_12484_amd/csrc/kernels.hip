@@ -847,6 +847,9 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
                 const int32_t* sl = idat + q[1];
                 const int32_t cnt = q[2];
                 float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+                // unrolled so that several slot indices are in flight at once
+                // (the sum stays in slot order)
+#pragma unroll 4
                 for (int32_t k = 0; k < cnt; ++k) {
                     const float* cp = C + 3 * sl[k];
                     s0 += cp[0];
