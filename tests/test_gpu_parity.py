@@ -173,6 +173,23 @@ def test_trajectory_matches_oracle(vh, ctx, name):
     m.close()
 
 
+def test_box_matches_stored_oracle_frames(vh, ctx):
+    """The 1,000-tet box workload (20 frames) against the oracle positions
+    stored in tests/golden/box_oracle_frames.txt."""
+    from tests.test_golden import load_box_frames
+    ref = load_box_frames()
+    p = synth.problem_by_name("box")
+    m = make_mesh(vh, ctx, p)
+    for f in range(1, 21):
+        m.step(1)
+        if f in ref:
+            x, _ = m.read_state()
+            e = rel_l2(x, ref[f])
+            say(f"[golden] box frame {f}: rel L2 {e:.2e}")
+            assert e <= 1e-5
+    m.close()
+
+
 def test_free_fall_without_stiffness(vh, ctx):
     say("[free fall]")
     p = synth.problem_by_name("box")
