@@ -164,7 +164,8 @@ int vh_mesh_time_kernel(vh_mesh* mesh, int32_t kernel_class, int32_t reps, void*
  * clears.  N is formed in FP64 on the host and stored as FP32 next to the
  * tet's four vertex ids (32 bytes per point on the device, plus a 24-byte
  * output row; charged to the HBM budget when the mesh is resident).
- * VH_EINVAL on n_points < 0, null arrays or a tet index out of range. */
+ * VH_EINVAL on n_points < 0, null arrays, a tet index out of range or a
+ * non-finite rest coordinate. */
 int vh_mesh_set_embedding(vh_mesh* mesh, int32_t n_points, const int32_t* tet, const double* rest_xyz);
 /* Positions of the embedded points for the current state, [n_points][3]
  * float64 in the order given: into host `out` (synchronises `stream`), or into

@@ -3,6 +3,7 @@
 // functions of each point's tet evaluated at the point's rest position.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -86,9 +87,13 @@ int vh_mesh_set_embedding(vh_mesh* m, int32_t n_points, const int32_t* tet, cons
     if (!m) return fail(VH_EINVAL, "null mesh");
     if (n_points < 0) return fail(VH_EINVAL, "n_points must be >= 0");
     if (n_points > 0 && (!tet || !rest_xyz)) return fail(VH_EINVAL, "null input arrays");
-    for (int32_t i = 0; i < n_points; ++i)
+    for (int32_t i = 0; i < n_points; ++i) {
         if (tet[i] < 0 || tet[i] >= m->nt)
             return fail(VH_EINVAL, "embedded point " + std::to_string(i) + ": tet index out of range");
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(rest_xyz[3 * (size_t)i + c]))
+                return fail(VH_EINVAL, "embedded point " + std::to_string(i) + ": rest position not finite");
+    }
     if (m->ctx) VH_TRY(set_device(m));
     free_embedding_device(m);
     m->emb_tet.assign(tet, tet + n_points);

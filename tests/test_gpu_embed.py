@@ -99,4 +99,6 @@ def test_embed_edge_cases(vh, ctx):
         m.set_embedding(np.array([p.nt], dtype=np.int32), np.zeros((1, 3)))
     with pytest.raises(vh.VHError):
         m.set_embedding(np.array([-1], dtype=np.int32), np.zeros((1, 3)))
+    with pytest.raises(vh.VHError):
+        m.set_embedding(np.array([0], dtype=np.int32), np.array([[0.0, np.nan, 0.0]]))
     m.close()
