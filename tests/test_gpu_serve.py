@@ -183,6 +183,41 @@ def test_mix_of_lane_groups_is_bitwise_alone(vh, probs):
     assert st["mean_batch"] > 1.0
 
 
+def test_serving_sizes_span_is_bitwise_alone(vh):
+    """The smallest, median and largest of the 64 serving garments (about 5K,
+    31K and 191K tets; 2 to 64 subdomains), served together and alone: the
+    same final states bit for bit."""
+    sizes = synth.serving_garment_sizes()
+    order = np.argsort(sizes)
+    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    ps = [synth.serving_shell_problem(int(sizes[g]), 100 + g) for g in pick]
+
+    def run(which):
+        ctx = vh.Context(0)
+        srv = vh.Server(ctx, "batched", 2)
+        ms = {}
+        for i in which:
+            ms[i] = new_mesh(vh, ctx, ps[i])
+            srv.add(ms[i], ps[i].n_subdomains)
+        for i in which:
+            srv.submit(ms[i], 3)
+        srv.drain()
+        st = srv.stats()
+        out = {i: ms[i].read_state()[0] for i in which}
+        srv.close()
+        for m in ms.values():
+            m.close()
+        ctx.close()
+        return out, st
+
+    say(f"[serve] sizes {[ps[i].nt for i in range(3)]}, subdomains {[ps[i].n_subdomains for i in range(3)]}")
+    alone = {i: run([i])[0][i] for i in range(3)}
+    mixed, st = run([0, 1, 2])
+    assert st["mean_batch"] > 1.0
+    for i in range(3):
+        assert np.array_equal(mixed[i], alone[i]), i
+
+
 def test_sequential_mode_is_bitwise_alone(vh, probs, alone):
     say("[serve] sequential mix")
     out, st = serve(vh, probs, [0, 1, 2], mode="sequential", order_seed=5)
