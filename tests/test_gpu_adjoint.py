@@ -35,22 +35,24 @@ def _target(p, frames, seed=0):
     return xt
 
 
-@pytest.mark.parametrize("name,frames,every", [("box", 4, 3), ("shell_small", 3, 2)])
-def test_adjoint_matches_oracle(vh, name, frames, every):
-    say(f"[adjoint] {name} frames={frames} every={every}")
+@pytest.mark.parametrize("name,frames,every,refine", [("box", 4, 3, 0), ("shell_small", 3, 2, 0), ("box", 3, 2, 1)])
+def test_adjoint_matches_oracle(vh, name, frames, every, refine):
+    """refine > 0: the forward and its replay refine every solve against the
+    FP64 residual; the reverse sweep reverses the exact-solve iteration."""
+    say(f"[adjoint] {name} frames={frames} every={every} refine={refine}")
     p = synth.problem_by_name(name)
     xt = _target(p, frames)
     _, g_ref = loss_and_grad(p, p.gamma_s, xt, frames)
     ctx = vh.Context(0)
     m = vh.Mesh(ctx, p.X, p.tets)
     m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
-    m.prefactor(p.n_subdomains)
+    m.prefactor(p.n_subdomains, refine)
     x0, v0 = p.initial_state()
     xf = m.adjoint_forward(x0, v0, frames, every)
     # same trajectory as plain stepping, bit for bit
     m2 = vh.Mesh(ctx, p.X, p.tets)
     m2.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
-    m2.prefactor(p.n_subdomains)
+    m2.prefactor(p.n_subdomains, refine)
     m2.step(frames)
     assert np.array_equal(m2.read_state()[0], xf)
     d = xf - xt
