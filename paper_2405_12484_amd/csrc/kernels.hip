@@ -23,6 +23,31 @@ namespace {
 
 constexpr int BLK = 256;
 
+// Global views of generic pointers.  Pointers read from a descriptor table are
+// generic, and an access through a generic pointer is a FLAT instruction,
+// which counts against the LDS wait counter as well as the vector-memory one:
+// in a kernel that also uses LDS, every wait for an LDS read would then wait
+// for all global loads still in flight (a prefetch among them).
+#define VH_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const VH_GLOBAL T* as_global(const T* p) {
+    return (const VH_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ VH_GLOBAL T* as_global(T* p) {
+    return (VH_GLOBAL T*)p;
+}
+// Whole 16-byte records go through native vector types: HIP's float4 and int4
+// are classes whose copy operations take generic references.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4 load_global4(const float4* p) {
+    return *reinterpret_cast<const VH_GLOBAL f32x4*>(as_global(p));
+}
+__device__ __forceinline__ void store_global4(float4* p, float x, float y, float z, float w) {
+    *reinterpret_cast<VH_GLOBAL f32x4*>(as_global(p)) = f32x4{x, y, z, w};
+}
+
 // A launch covers one or more garments.  Its table L holds one int4 per block:
 // {g: garment index into the DevMesh array, lb: block index within the
 // garment, x0, x1: per-garment launch parameters}, so a block finds its
@@ -718,25 +743,40 @@ struct ChunkRegs {
 };
 // Loads are unconditional (indices clamped into the chunk, nv4 >= 1) so the
 // registers are always defined; only the stores are predicated.
-__device__ __forceinline__ void chunk_load(const float4* __restrict__ src, int32_t nv4, ChunkRegs& reg) {
+__device__ __forceinline__ void chunk_load(const float4* __restrict__ src_, int32_t nv4, ChunkRegs& reg) {
     const int32_t j = threadIdx.x, last = nv4 - 1;
-    float4 t = src[min(j, last)];
+    f32x4 t = load_global4(src_ + min(j, last));
     reg.a0 = t.x; reg.a1 = t.y; reg.a2 = t.z; reg.a3 = t.w;
-    t = src[min(j + BLKI, last)];
+    t = load_global4(src_ + min(j + BLKI, last));
     reg.b0 = t.x; reg.b1 = t.y; reg.b2 = t.z; reg.b3 = t.w;
-    t = src[min(j + 2 * BLKI, last)];
+    t = load_global4(src_ + min(j + 2 * BLKI, last));
     reg.c0 = t.x; reg.c1 = t.y; reg.c2 = t.z; reg.c3 = t.w;
 }
-__device__ __forceinline__ void chunk_store(float4* dst, int32_t nv4, const ChunkRegs& reg) {
+// The stores fill the whole buffer (NV4I * BLKI float4, words past the chunk
+// get copies of its last float4): unpredicated, they leave the wait-count pass
+// no path on which a load could still be pending when its registers are
+// reused, so the loads of the next chunk can stay in flight across a phase.
+__device__ __forceinline__ void chunk_store(float4* dst, const ChunkRegs& reg) {
     const int32_t j = threadIdx.x;
-    if (j < nv4) dst[j] = make_float4(reg.a0, reg.a1, reg.a2, reg.a3);
-    if (j + BLKI < nv4) dst[j + BLKI] = make_float4(reg.b0, reg.b1, reg.b2, reg.b3);
-    if (j + 2 * BLKI < nv4) dst[j + 2 * BLKI] = make_float4(reg.c0, reg.c1, reg.c2, reg.c3);
+    dst[j] = make_float4(reg.a0, reg.a1, reg.a2, reg.a3);
+    dst[j + BLKI] = make_float4(reg.b0, reg.b1, reg.b2, reg.b3);
+    dst[j + 2 * BLKI] = make_float4(reg.c0, reg.c1, reg.c2, reg.c3);
 }
 
 // Descriptors of a subdomain's first CHD chunks are copied to LDS at kernel
 // start, so the chunk pipeline never waits on a global descriptor read.
 constexpr int32_t CHD = 64;
+
+// kind, ntasks, v0, nv of chunk c, read from global memory
+__device__ __forceinline__ Chunk chunk_desc_global(const Chunk* __restrict__ chunks, int32_t c) {
+    const i32x4 v = *reinterpret_cast<const VH_GLOBAL i32x4*>(as_global(chunks + c));
+    Chunk K{};
+    K.kind = v.x;
+    K.ntasks = v.y;
+    K.v0 = v.z;
+    K.nv = v.w;
+    return K;
+}
 
 __device__ __forceinline__ Chunk chunk_desc(const Chunk* __restrict__ chunks, const int4* cd, int32_t c0,
                                             int32_t c) {
@@ -748,7 +788,13 @@ __device__ __forceinline__ Chunk chunk_desc(const Chunk* __restrict__ chunks, co
         K.v0 = v.z;
         K.nv = v.w;
     } else {
-        K = chunks[c];
+        // a non-temporal read cannot be merged with the LDS read above into
+        // one FLAT load of a selected address (a plain one was)
+        const i32x4 v = __builtin_nontemporal_load(reinterpret_cast<const VH_GLOBAL i32x4*>(as_global(chunks + c)));
+        K.kind = v.x;
+        K.ntasks = v.y;
+        K.v0 = v.z;
+        K.nv = v.w;
     }
     return K;
 }
@@ -764,49 +810,51 @@ __device__ __forceinline__ void chunk_pipeline(const Chunk* __restrict__ chunks,
     // the first chunk's descriptor comes straight from global memory, so its
     // load is in flight while the descriptor table is staged
     ChunkRegs ra, rb;   // ra: next chunk for buffer 1, rb: next chunk for buffer 0
-    Chunk K0{};
-    if (c0 < c1) {
-        K0 = chunks[c0];
-        chunk_load(iv4 + K0.v0 / 4, (K0.nv + 3) / 4, ra);
+    if (c0 >= c1) {
+        __syncthreads();   // the caller's LDS writes before the pipeline stay ordered before its reads after
+        return;
     }
+    const int32_t last = c1 - 1;
+    Chunk K0 = chunk_desc_global(chunks, c0);
+    chunk_load(iv4 + K0.v0 / 4, (K0.nv + 3) / 4, ra);
     for (int32_t c = c0 + (int32_t)threadIdx.x; c < min(c1, c0 + CHD); c += BLKI) {
-        const Chunk K = chunks[c];
+        const Chunk K = chunk_desc_global(chunks, c);
         cd[c - c0] = make_int4(K.kind, K.ntasks, K.v0, K.nv);
     }
     __syncthreads();
-    if (c0 >= c1) return;
     float* buf0 = sm;
     float* buf1 = sm + CHI;
-    Chunk K1 = K0, N0 = K0, N1 = K0;
-    chunk_store(reinterpret_cast<float4*>(buf0), (K0.nv + 3) / 4, ra);
-    if (c0 + 1 < c1) {
-        N1 = chunk_desc(chunks, cd, c0, c0 + 1);
-        chunk_load(iv4 + N1.v0 / 4, (N1.nv + 3) / 4, ra);
-    }
+    // Loads and stores are unconditional: past the last chunk they repeat it
+    // into the buffer that is no longer read.  Conditional ones left the
+    // wait-count pass a path on which staged registers looked pending, and it
+    // then waited for every load in flight at the top of each phase.
+    chunk_store(reinterpret_cast<float4*>(buf0), ra);
+    Chunk N1 = chunk_desc(chunks, cd, c0, min(c0 + 1, last));
+    chunk_load(iv4 + N1.v0 / 4, (N1.nv + 3) / 4, ra);
+    Chunk K1 = N1;
     __syncthreads();
-    for (int32_t c = c0; c < c1; c += 2) {
+    // Pairs of chunks; an odd last one is computed after the loop (an exit
+    // in mid-loop gave the pass a path from it back to the loop top).
+    int32_t c = c0;
+    for (; c + 1 < c1; c += 2) {
         // chunk c in buffer 0, chunk c + 1 in ra
-        if (c + 2 < c1) {
-            N0 = chunk_desc(chunks, cd, c0, c + 2);
-            chunk_load(iv4 + N0.v0 / 4, (N0.nv + 3) / 4, rb);
-        }
+        const Chunk N0 = chunk_desc(chunks, cd, c0, min(c + 2, last));
+        chunk_load(iv4 + N0.v0 / 4, (N0.nv + 3) / 4, rb);
         compute(K0, buf0, buf1);
-        if (c + 1 < c1) {
-            chunk_store(reinterpret_cast<float4*>(buf1), (N1.nv + 3) / 4, ra);
-            K1 = N1;
-        }
+        chunk_store(reinterpret_cast<float4*>(buf1), ra);
+        K1 = N1;
         __syncthreads();
-        if (c + 1 >= c1) break;
         // chunk c + 1 in buffer 1, chunk c + 2 in rb
-        if (c + 3 < c1) {
-            N1 = chunk_desc(chunks, cd, c0, c + 3);
-            chunk_load(iv4 + N1.v0 / 4, (N1.nv + 3) / 4, ra);
-        }
+        N1 = chunk_desc(chunks, cd, c0, min(c + 3, last));
+        chunk_load(iv4 + N1.v0 / 4, (N1.nv + 3) / 4, ra);
         compute(K1, buf1, buf0);
-        if (c + 2 < c1) {
-            chunk_store(reinterpret_cast<float4*>(buf0), (N0.nv + 3) / 4, rb);
-            K0 = N0;
-        }
+        chunk_store(reinterpret_cast<float4*>(buf0), rb);
+        K0 = N0;
+        __syncthreads();
+    }
+    if (c < c1) {
+        // the last chunk, in buffer 0
+        compute(K0, buf0, buf1);
         __syncthreads();
     }
 }
@@ -830,11 +878,11 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
     float* Z = R + 3 * a.max_n;
     float* C = Z + 3 * a.max_n;
     const int32_t d = sl.lb;
-    const int32_t base = a.sub_off[d];
-    const int32_t n_loc = a.sub_off[d + 1] - base;
+    const int32_t base = as_global(a.sub_off)[d];
+    const int32_t n_loc = as_global(a.sub_off)[d + 1] - base;
     const int tid = threadIdx.x;
-    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)a.r[3 * base + i];
-    const int32_t c0 = a.sub_fwd_ch[d], c1 = a.sub_fwd_ch[d + 1];
+    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)as_global(a.r)[3 * base + i];
+    const int32_t c0 = as_global(a.sub_fwd_ch)[d], c1 = as_global(a.sub_fwd_ch)[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
@@ -881,16 +929,21 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
                     s2 += v * x[3 * k + 2];
                     co += stride0 - k;
                 }
-                float* op = (i < n) ? Z + 3 * (col0 + i)
-                                    : (i < n + mi) ? C + 3 * (q[4] + i - n)
-                                                   : a.cgf + 3 * (size_t)(q[5] + i - n - mi);
-                op[0] = s0;
-                op[1] = s1;
-                op[2] = s2;
+                if (i < n + mi) {
+                    float* op = (i < n) ? Z + 3 * (col0 + i) : C + 3 * (q[4] + i - n);
+                    op[0] = s0;
+                    op[1] = s1;
+                    op[2] = s2;
+                } else {
+                    VH_GLOBAL float* op = as_global(a.cgf) + 3 * (size_t)(q[5] + i - n - mi);
+                    op[0] = s0;
+                    op[1] = s1;
+                    op[2] = s2;
+                }
             }
         }
     });
-    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) a.zf[3 * base + i] = Z[i];
+    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) as_global(a.zf)[3 * base + i] = Z[i];
 }
 
 // Interface phases, one group of G lanes per task (FP64).
@@ -907,41 +960,47 @@ __global__ __launch_bounds__(BLK) void k_coarse(const DevMesh* __restrict__ GM, 
     const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int32_t t = sl.lb * (BLK / G) + grp;
     if (t >= ntasks) return;
-    const CTask T = a.ctasks[task0 + t];
+    CTask T;
+    {
+        const VH_GLOBAL i32x4* tp = reinterpret_cast<const VH_GLOBAL i32x4*>(as_global(a.ctasks + task0 + t));
+        const i32x4 lo = tp[0], hi = tp[1];
+        T.a[0] = lo.x; T.a[1] = lo.y; T.a[2] = lo.z; T.a[3] = lo.w;
+        T.a[4] = hi.x; T.a[5] = hi.y; T.a[6] = hi.z; T.a[7] = hi.w;
+    }
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     if (kind == PULLSUM) {
-        const int32_t* lf = a.cslots + T.a[1];
+        const VH_GLOBAL int32_t* lf = as_global(a.cslots) + T.a[1];
         for (int32_t k = lane; k < T.a[2]; k += G) {
-            const float* cp = a.cgf + 3 * (size_t)lf[k];
+            const VH_GLOBAL float* cp = as_global(a.cgf) + 3 * (size_t)lf[k];
             s0 += (double)cp[0];
             s1 += (double)cp[1];
             s2 += (double)cp[2];
         }
-        const int32_t* ld = a.cslots + T.a[3];
+        const VH_GLOBAL int32_t* ld = as_global(a.cslots) + T.a[3];
         for (int32_t k = lane; k < T.a[4]; k += G) {
-            const double* cp = a.cgd + 3 * (size_t)ld[k];
+            const VH_GLOBAL double* cp = as_global(a.cgd) + 3 * (size_t)ld[k];
             s0 += cp[0];
             s1 += cp[1];
             s2 += cp[2];
         }
     } else if (kind == GEMV) {
-        const double* vp = a.dvals + T.a[2];
-        const double* xb = a.rg + 3 * T.a[4];
+        const VH_GLOBAL double* vp = as_global(a.dvals) + T.a[2];
+        const VH_GLOBAL double* xb = as_global(a.rg) + 3 * T.a[4];
         const int32_t len = T.a[3];
         int32_t k = lane;
         for (; k + 3 * G < len; k += 4 * G) {
             const double v0 = vp[k], v1 = vp[k + G], v2 = vp[k + 2 * G], v3 = vp[k + 3 * G];
-            const double* x0 = xb + 3 * k;
-            const double* x1 = x0 + 3 * G;
-            const double* x2 = x1 + 3 * G;
-            const double* x3 = x2 + 3 * G;
+            const VH_GLOBAL double* x0 = xb + 3 * k;
+            const VH_GLOBAL double* x1 = x0 + 3 * G;
+            const VH_GLOBAL double* x2 = x1 + 3 * G;
+            const VH_GLOBAL double* x3 = x2 + 3 * G;
             s0 += v0 * x0[0] + v1 * x1[0] + v2 * x2[0] + v3 * x3[0];
             s1 += v0 * x0[1] + v1 * x1[1] + v2 * x2[1] + v3 * x3[1];
             s2 += v0 * x0[2] + v1 * x1[2] + v2 * x2[2] + v3 * x3[2];
         }
         for (; k < len; k += G) {
             const double v = vp[k];
-            const double* xp = xb + 3 * k;
+            const VH_GLOBAL double* xp = xb + 3 * k;
             s0 += v * xp[0];
             s1 += v * xp[1];
             s2 += v * xp[2];
@@ -949,44 +1008,45 @@ __global__ __launch_bounds__(BLK) void k_coarse(const DevMesh* __restrict__ GM, 
     } else {
         // four independent elements per lane and round keep enough loads in
         // flight; the per-lane summation order is fixed by the lane index
-        const double* vp = a.dvals + T.a[1];
+        const VH_GLOBAL double* vp = as_global(a.dvals) + T.a[1];
         const int32_t len1 = T.a[2], len2 = T.a[4];
-        const double* zb = a.zg + 3 * T.a[3];
+        const VH_GLOBAL double* zb = as_global(a.zg) + 3 * T.a[3];
         int32_t k = lane;
         for (; k + 3 * G < len1; k += 4 * G) {
             const double v0 = vp[k], v1 = vp[k + G], v2 = vp[k + 2 * G], v3 = vp[k + 3 * G];
-            const double* x0 = zb + 3 * k;
-            const double* x1 = x0 + 3 * G;
-            const double* x2 = x1 + 3 * G;
-            const double* x3 = x2 + 3 * G;
+            const VH_GLOBAL double* x0 = zb + 3 * k;
+            const VH_GLOBAL double* x1 = x0 + 3 * G;
+            const VH_GLOBAL double* x2 = x1 + 3 * G;
+            const VH_GLOBAL double* x3 = x2 + 3 * G;
             s0 += v0 * x0[0] + v1 * x1[0] + v2 * x2[0] + v3 * x3[0];
             s1 += v0 * x0[1] + v1 * x1[1] + v2 * x2[1] + v3 * x3[1];
             s2 += v0 * x0[2] + v1 * x1[2] + v2 * x2[2] + v3 * x3[2];
         }
         for (; k < len1; k += G) {
             const double v = vp[k];
-            const double* xp = zb + 3 * k;
+            const VH_GLOBAL double* xp = zb + 3 * k;
             s0 += v * xp[0];
             s1 += v * xp[1];
             s2 += v * xp[2];
         }
-        const double* v2p = vp + len1;
-        const int32_t* gi = a.cgidx + T.a[5];
+        const VH_GLOBAL double* v2p = vp + len1;
+        const VH_GLOBAL int32_t* gi = as_global(a.cgidx) + T.a[5];
+        const VH_GLOBAL double* dgv = as_global(a.dg);
         k = lane;
         for (; k + 3 * G < len2; k += 4 * G) {
             const int32_t g0 = gi[k], g1 = gi[k + G], g2 = gi[k + 2 * G], g3 = gi[k + 3 * G];
             const double v0 = v2p[k], v1 = v2p[k + G], v2 = v2p[k + 2 * G], v3 = v2p[k + 3 * G];
-            const double* x0 = a.dg + 3 * g0;
-            const double* x1 = a.dg + 3 * g1;
-            const double* x2 = a.dg + 3 * g2;
-            const double* x3 = a.dg + 3 * g3;
+            const VH_GLOBAL double* x0 = dgv + 3 * g0;
+            const VH_GLOBAL double* x1 = dgv + 3 * g1;
+            const VH_GLOBAL double* x2 = dgv + 3 * g2;
+            const VH_GLOBAL double* x3 = dgv + 3 * g3;
             s0 += v0 * x0[0] + v1 * x1[0] + v2 * x2[0] + v3 * x3[0];
             s1 += v0 * x0[1] + v1 * x1[1] + v2 * x2[1] + v3 * x3[1];
             s2 += v0 * x0[2] + v1 * x1[2] + v2 * x2[2] + v3 * x3[2];
         }
         for (; k < len2; k += G) {
             const double v = v2p[k];
-            const double* xp = a.dg + 3 * gi[k];
+            const VH_GLOBAL double* xp = dgv + 3 * gi[k];
             s0 += v * xp[0];
             s1 += v * xp[1];
             s2 += v * xp[2];
@@ -996,18 +1056,18 @@ __global__ __launch_bounds__(BLK) void k_coarse(const DevMesh* __restrict__ GM, 
     s1 = group_sum<G>(s1);
     s2 = group_sum<G>(s2);
     if (lane == 0) {
-        double* op;
+        VH_GLOBAL double* op;
         if (kind == PULLSUM) {
-            const double* rp = a.r + 3 * ((size_t)a.n_int + T.a[0]);
-            op = a.rg + 3 * T.a[0];
+            const VH_GLOBAL double* rp = as_global(a.r) + 3 * ((size_t)a.n_int + T.a[0]);
+            op = as_global(a.rg) + 3 * T.a[0];
             op[0] = rp[0] - s0;
             op[1] = rp[1] - s1;
             op[2] = rp[2] - s2;
             return;
         }
-        if (kind == GEMV) op = (T.a[0] == 0) ? a.zg + 3 * T.a[1]
-                               : (T.a[0] == 1) ? a.cgd + 3 * (size_t)T.a[1] : a.dg + 3 * T.a[1];
-        else op = a.dg + 3 * T.a[0];
+        if (kind == GEMV) op = (T.a[0] == 0) ? as_global(a.zg) + 3 * T.a[1]
+                               : (T.a[0] == 1) ? as_global(a.cgd) + 3 * (size_t)T.a[1] : as_global(a.dg) + 3 * T.a[1];
+        else op = as_global(a.dg) + 3 * T.a[0];
         op[0] = s0;
         op[1] = s1;
         op[2] = s2;
@@ -1033,22 +1093,22 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
     float* Z = sm + 2 * CHI + 4 * CHD;
     float* DL = Z + 3 * a.max_n;
     const int32_t d = sl.lb;
-    const int32_t base = a.sub_off[d];
-    const int32_t n_loc = a.sub_off[d + 1] - base;
-    const int32_t b0 = a.bnd_off[d], nb = a.bnd_off[d + 1] - b0;
+    const int32_t base = as_global(a.sub_off)[d];
+    const int32_t n_loc = as_global(a.sub_off)[d + 1] - base;
+    const int32_t b0 = as_global(a.bnd_off)[d], nb = as_global(a.bnd_off)[d + 1] - b0;
     const int tid = threadIdx.x;
-    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) Z[i] = a.zf[3 * base + i];
+    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) Z[i] = as_global(a.zf)[3 * base + i];
     for (int32_t i = tid; i < 3 * nb; i += BLKI) {
         const int32_t k = i / 3, c = i - 3 * k;
-        DL[3 * n_loc + i] = (float)a.dg[3 * (a.bnd[b0 + k] - a.n_int) + c];
+        DL[3 * n_loc + i] = (float)as_global(a.dg)[3 * (as_global(a.bnd)[b0 + k] - a.n_int) + c];
     }
     // this thread's first interior row: x and X fetched now for the update at the end
     double px[3] = {0.0, 0.0, 0.0}, pX[3] = {0.0, 0.0, 0.0};
     if (apply && tid < n_loc) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            px[c] = a.x[3 * (size_t)(base + tid) + c];
-            pX[c] = a.X[3 * (size_t)(base + tid) + c];
+            px[c] = as_global(a.x)[3 * (size_t)(base + tid) + c];
+            pX[c] = as_global(a.X)[3 * (size_t)(base + tid) + c];
         }
     }
     // a slice of the interface rows (their values are final): updated first,
@@ -1058,21 +1118,30 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
         const int32_t g0 = d * chunk, g1 = min(a.n_gamma, g0 + chunk);
         for (int32_t i = g0 + tid; i < g1; i += BLKI) {
             const int32_t gi = a.n_int + i;
+            // all loads before the first store, which they could otherwise not pass
+            double dv[3], xo[3] = {0.0, 0.0, 0.0}, Xo[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dv[c] = as_global(a.dg)[3 * i + c];
+                if (apply) {
+                    xo[c] = as_global(a.x)[3 * gi + c];
+                    Xo[c] = as_global(a.X)[3 * gi + c];
+                }
+            }
             float du[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double dv = a.dg[3 * i + c];
-                if (keep_delta) a.delta[3 * gi + c] = dv;
+                if (keep_delta) as_global(a.delta)[3 * gi + c] = dv[c];
                 if (apply) {
-                    const double xn = a.x[3 * gi + c] + dv;
-                    a.x[3 * gi + c] = xn;
-                    du[c] = (float)(xn - a.X[3 * gi + c]);
+                    const double xn = xo[c] + dv[c];
+                    as_global(a.x)[3 * gi + c] = xn;
+                    du[c] = (float)(xn - Xo[c]);
                 }
             }
-            if (apply) a.u[gi] = make_float4(du[0], du[1], du[2], 0.0f);
+            if (apply) store_global4(a.u + gi, du[0], du[1], du[2], 0.0f);
         }
     }
-    const int32_t c0 = a.sub_bwd_ch[d], c1 = a.sub_bwd_ch[d + 1];
+    const int32_t c0 = as_global(a.sub_bwd_ch)[d], c1 = as_global(a.sub_bwd_ch)[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
@@ -1163,16 +1232,16 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double dv = (double)DL[3 * i + c];
-            if (keep_delta) a.delta[3 * gi + c] = dv;
+            if (keep_delta) as_global(a.delta)[3 * gi + c] = dv;
             if (apply) {
-                const double xo = first ? px[c] : a.x[3 * gi + c];
-                const double Xo = first ? pX[c] : a.X[3 * gi + c];
+                const double xo = first ? px[c] : as_global(a.x)[3 * gi + c];
+                const double Xo = first ? pX[c] : as_global(a.X)[3 * gi + c];
                 const double xn = xo + dv;
-                a.x[3 * gi + c] = xn;
+                as_global(a.x)[3 * gi + c] = xn;
                 du[c] = (float)(xn - Xo);
             }
         }
-        if (apply) a.u[gi] = make_float4(du[0], du[1], du[2], 0.0f);
+        if (apply) store_global4(a.u + gi, du[0], du[1], du[2], 0.0f);
     }
 }
 
