@@ -47,6 +47,12 @@ void vhp_info(void* h, long long* out) {
     out[7] = P.nnz_coarse; out[8] = P.max_sub_phases; out[9] = (long long)P.chunks.size();
     out[10] = (long long)P.ctasks.size(); out[11] = (long long)P.cslots.size(); out[12] = P.max_sub_n;
     out[13] = P.max_cint; out[14] = P.max_nb;
+    long long mf = 0, mb = 0;   // most chunks of one subdomain's forward / backward program
+    for (int d = 0; d < P.D; ++d) {
+        mf = std::max<long long>(mf, P.sub_fwd_ch[d + 1] - P.sub_fwd_ch[d]);
+        mb = std::max<long long>(mb, P.sub_bwd_ch[d + 1] - P.sub_bwd_ch[d]);
+    }
+    out[15] = mf; out[16] = mb;
 }
 
 void vhp_perm(void* h, int* perm) {

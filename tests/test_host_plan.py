@@ -35,11 +35,11 @@ def _build(hl, p, D, leaf=32, pinned=None):
     h = hl.vhp_build(keep[0].ctypes.data, p.nv, keep[1].ctypes.data, p.nt, keep[2].ctypes.data,
                      keep[3].ctypes.data, keep[4].ctypes.data, keep[5].ctypes.data, keep[6].ctypes.data,
                      p.dt, p.pd_iters, D, 0, leaf, ctypes.byref(rc), msg, 256)
-    info = np.zeros(15, dtype=np.int64)
+    info = np.zeros(17, dtype=np.int64)
     if h:
         hl.vhp_info(h, info.ctypes.data)
     keys = ("n_free n_int n_gamma D n_sn n_clevels nnz_int nnz_coarse max_sub_phases n_chunks n_ctasks n_cslots "
-            "max_sub_n max_cint max_nb")
+            "max_sub_n max_cint max_nb max_fwd_chunks max_bwd_chunks")
     return h, rc.value, msg.value.decode(), dict(zip(keys.split(), info.tolist()))
 
 
@@ -63,6 +63,28 @@ def test_emulated_solve_matches_exact(hl, name, D, leaf):
         # interior factor blocks are stored in FP32
         assert np.linalg.norm(d[sim.free] - xe) <= 2e-7 * np.linalg.norm(xe)
         assert np.all(d[sim.fixed] == 0)
+    finally:
+        hl.vhp_free(h)
+
+
+def test_long_interior_program(hl):
+    """A 10 x 10 x 22 hex box as one subdomain: its forward program has more
+    chunks (65) than the interior kernels' 64-entry LDS table of chunk
+    descriptors. The programs past the table still solve exactly. (The GPU
+    refuses this subdomain: its contribution slots need more LDS than a CU has;
+    no subdomain that fits LDS has reached 64 chunks in the meshes tried, so the
+    kernels' global descriptor reads are not exercised on the GPU.)"""
+    p = synth.meshes.make_box_problem(nx=10, ny=10, nz=22, name="box_long")
+    h, rc, msg, info = _build(hl, p, 1)
+    assert rc == 0, msg
+    try:
+        assert info["max_fwd_chunks"] > 64
+        sim = oracle.OracleSim.from_problem(p)
+        rhs = np.random.default_rng(5).standard_normal((p.nv, 3))
+        d = np.zeros((p.nv, 3))
+        hl.vhp_solve(h, rhs.ctypes.data, d.ctypes.data)
+        xe = sim._solve(rhs[sim.free])
+        assert np.linalg.norm(d[sim.free] - xe) <= 2e-7 * np.linalg.norm(xe)
     finally:
         hl.vhp_free(h)
 
