@@ -159,88 +159,119 @@ def _plus_branch(sig, logc=0.0):
     return s, mu, ok
 
 
-def _squash_candidates(sig):
-    """Stationary points of Eq. (vol_pre) with one axis on the minus root.
+def _squash_candidates(sig, logc=0.0):
+    """Stationary points of Eq. (vol_pre) with one axis on the minus root, for
+    the free axes ``sig`` (1-D) and the product target exp(logc).
 
-    For det F > 1 the Lagrange condition s_i (s_i - sig_i) = mu < 0 also admits
-    s_k = (sig_k - sqrt(sig_k^2 + 4 mu))/2 on one axis k.  These exist only when
-    det F >= 2 (then s_k <= sig_k/2 and s_j <= sig_j).  Scalar search: dense
-    bracketing in mu, then bisection.  Returns a list of candidate s vectors.
+    For mu < 0 the Lagrange condition s_i (s_i - sig_i) = mu also admits
+    s_k = (sig_k - sqrt(sig_k^2 + 4 mu))/2 on one axis k (positive only when
+    sig_k > 0).  Then s_k <= sig_k/2 and s_j <= sig_j, so such points exist
+    only when every sig_i > 0 and prod sig >= 2 exp(logc).  Two axes on the
+    minus root give saddle points of the Lagrangian (on the constraint's
+    tangent space its Hessian weighs axis i by s_i (2 s_i - sig_i), negative
+    on a minus root), so they cannot be the nearest point and are not
+    searched.  Scalar search per
+    axis: dense bracketing of mu in [-min sig^2/4, 0), then bisection.  Returns
+    a list of candidate s vectors in axis order, roots of one axis by
+    increasing |mu|.
     """
     sig = np.asarray(sig, dtype=np.float64)
-    if sig.min() <= 0 or np.prod(sig) < 2.0:
+    if sig.size < 2 or sig.min() <= 0 or np.log(sig).sum() < logc + math.log(2.0):
         return []
     lo = -0.25 * sig.min() ** 2
-    out = []
-    for k in range(3):
-        def lnp(mu):
-            d = np.sqrt(np.maximum(sig * sig + 4.0 * mu, 0.0))
-            s = 0.5 * (sig + d)
-            s[k] = -2.0 * mu / (sig[k] + d[k])
-            return float(np.log(s).sum()), s
+    mus = lo * np.geomspace(1e-14, 1.0, 4000)          # from just below 0 down to lo
 
-        ts = np.concatenate([np.geomspace(1e-14, 1.0, 4000)])
-        mus = lo * ts
-        vals = np.array([lnp(m)[0] for m in mus])
+    def branch(mu, k):
+        """s on the mixed branch (axis k minus) for an array of mu."""
+        mu = np.atleast_1d(mu)
+        d = np.sqrt(np.maximum(sig[None, :] ** 2 + 4.0 * mu[:, None], 0.0))
+        s = 0.5 * (sig[None, :] + d)
+        s[:, k] = -2.0 * mu / (sig[k] + d[:, k])       # minus root without cancellation
+        return s
+
+    out = []
+    for k in range(sig.size):
+        with np.errstate(divide="ignore"):
+            vals = np.log(branch(mus, k)).sum(axis=1) - logc
         for i in range(len(mus) - 1):
-            if np.sign(vals[i]) != np.sign(vals[i + 1]) and np.isfinite(vals[i]) and np.isfinite(vals[i + 1]):
-                a, b = mus[i], mus[i + 1]
-                fa = vals[i]
-                for _ in range(200):
-                    m = 0.5 * (a + b)
-                    fm = lnp(m)[0]
-                    if np.sign(fm) == np.sign(fa):
-                        a, fa = m, fm
-                    else:
-                        b = m
-                out.append(lnp(0.5 * (a + b))[1].copy())
+            if not (np.isfinite(vals[i]) and np.isfinite(vals[i + 1])):
+                continue
+            if np.sign(vals[i]) == np.sign(vals[i + 1]):
+                continue
+            a, b, fa = mus[i], mus[i + 1], vals[i]
+            for _ in range(200):
+                m = 0.5 * (a + b)
+                fm = float(np.log(branch(m, k)).sum() - logc)
+                if np.sign(fm) == np.sign(fa):
+                    a, fa = m, fm
+                else:
+                    b = m
+            out.append(branch(0.5 * (a + b), k)[0].copy())
     return out
 
 
-def proj_sl3(sigma):
-    """Nearest point on {s : s1 s2 s3 = 1, s_i > 0} to the signed singular values
-    (Eq. vol_pre), then the paper's clamp of any component to [0.01, inf) with
-    that component frozen and the rest re-solved (Sec. 7.1).
+def _nearest_on_product(sig, logc=0.0):
+    """Nearest point to ``sig`` (the free axes, 1-D) on {prod s = exp(logc), s > 0}.
 
-    Returns (s, info) with info counting elements where the + branch had no
-    root, where a squash candidate was nearer, and where the clamp fired.
+    The candidates are the + branch root (when it exists) and the mixed-branch
+    roots of ``_squash_candidates``; the nearest wins, ties going to the +
+    branch, then to the lower axis.  Returns (s, plus_ok, squash_won).
+    """
+    sig = np.asarray(sig, dtype=np.float64)
+    if sig.size == 1:
+        return np.array([math.exp(logc)]), True, False
+    sp_, _, ok = _plus_branch(sig[None, :], logc=logc)
+    cands = [sp_[0].copy()] if ok[0] else []
+    cands += _squash_candidates(sig, logc)
+    d = [float(((c - sig) ** 2).sum()) for c in cands]
+    best = int(np.argmin(d))
+    return cands[best], bool(ok[0]), (best != 0 or not ok[0])
+
+
+def proj_sl3(sigma):
+    """Projection of Eq. (vol_pre) with the clamp of Sec. 7.1.
+
+    1. The nearest point on {s1 s2 s3 = 1, s_i > 0} to the signed singular
+       values (the KKT problem with the equality constraint only): the + branch
+       root, or, when det F >= 2, the nearest of it and the mixed-branch
+       stationary points.
+    2. The clamp: any component below 0.01 is set to 0.01 and frozen, and the
+       remaining free components are re-solved as the nearest point with
+       prod s_free = 1 / 0.01^(number frozen); repeated until no free
+       component is below 0.01 (at most twice).  The result always has
+       s1 s2 s3 = 1 and s_i >= 0.01.
+
+    Returns (s, info) with info counting elements: inverted (sigma_3 <= 0),
+    det_ge2 (all sigma > 0 and det F >= 2: the regime where mixed-branch
+    stationary points exist), no_plus_root, squash (a mixed-branch point was
+    taken, at step 1 or in a re-solve) and clamped (the clamp fired).
     """
     sigma = np.atleast_2d(np.asarray(sigma, dtype=np.float64))
     s, _, ok = _plus_branch(sigma)
-    n_noroot = int((~ok).sum())
-    n_squash = 0
-    big = np.nonzero((~ok) | ((sigma.min(axis=1) > 0) & (np.prod(sigma, axis=1) >= 2.0)))[0]
-    for e in big:
-        cands = []
-        if ok[e]:
-            cands.append(s[e].copy())
-        cands += _squash_candidates(sigma[e])
-        if not cands:
-            continue
-        d = [float(((c - sigma[e]) ** 2).sum()) for c in cands]
-        best = int(np.argmin(d))          # ties: first (the + branch, then lowest axis)
-        if best != 0 or not ok[e]:
-            n_squash += 1
-        s[e] = cands[best]
-    n_clamp = 0
-    low = np.nonzero((s < SL3_CLAMP).any(axis=1))[0]
-    for e in low:
-        n_clamp += 1
+    det_ge2 = (sigma.min(axis=1) > 0) & (np.prod(sigma, axis=1) >= 2.0)
+    info = {"inverted": int((sigma[:, 2] <= 0).sum()), "det_ge2": int(det_ge2.sum()),
+            "no_plus_root": int((~ok).sum()), "squash": 0, "clamped": 0}
+    squashed = np.zeros(sigma.shape[0], dtype=bool)
+    for e in np.nonzero((~ok) | det_ge2)[0]:
+        s[e], _, won = _nearest_on_product(sigma[e], 0.0)
+        squashed[e] = won
+    for e in np.nonzero((s < SL3_CLAMP).any(axis=1))[0]:
+        info["clamped"] += 1
         frozen = np.zeros(3, dtype=bool)
         se = s[e].copy()
-        for _ in range(3):
+        while True:
             newly = (~frozen) & (se < SL3_CLAMP)
             if not newly.any():
                 break
             frozen |= newly
             se[frozen] = SL3_CLAMP
             free = ~frozen
-            if free.any():
-                logc = -math.log(SL3_CLAMP) * frozen.sum()
-                sub, _, _ = _plus_branch(sigma[e, free][None, :], logc=logc)
-                se[free] = sub[0]
+            logc = -math.log(SL3_CLAMP) * int(frozen.sum())
+            se[free], _, won = _nearest_on_product(sigma[e, free], logc)
+            squashed[e] |= won
         s[e] = se
-    return s, {"no_plus_root": n_noroot, "squash": n_squash, "clamped": n_clamp}
+    info["squash"] = int(squashed.sum())
+    return s, info
 
 
 def local_step(x, tets, grads, w_s, w_v):
@@ -340,7 +371,7 @@ class OracleSim:
         v = np.asarray(v, dtype=np.float64)
         y = self.predictor(x, v)
         xk = y.copy()
-        info = {"no_plus_root": 0, "squash": 0, "clamped": 0}
+        info = {"inverted": 0, "det_ge2": 0, "no_plus_root": 0, "squash": 0, "clamped": 0}
         self.energies = []
         for _ in range(self.pd_iters):
             if track_energy:

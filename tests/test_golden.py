@@ -38,7 +38,9 @@ def test_sl3_fixture():
     s2, _ = oracle.proj_sl3(sig)
     assert np.abs(s2 - s).max() < 1e-13
     free = s.min(axis=1) > 0.0100001                      # no clamp fired
-    assert np.abs(s.prod(axis=1) - 1.0)[free].max() < 1e-12
+    assert np.abs(s.prod(axis=1) - 1.0).max() < 1e-12      # clamped rows re-solve the rest
+    clamped = ~free
+    assert clamped.sum() >= 4 and (s[clamped].min(axis=1) == 0.01).all()
     mu = s * (s - sig)                                    # the Lagrange multiplier, equal on every axis
     spread = (mu.max(axis=1) - mu.min(axis=1)) / np.maximum(np.abs(mu).max(axis=1), 1e-300)
     assert spread[free].max() < 1e-9

@@ -131,7 +131,7 @@ def test_sl3_kkt_and_det():
     # the + branch covers every det F < 2 (a squash point needs det F >= 2)
     small = np.prod(sig, axis=1) < 2.0
     _, info = oracle.proj_sl3(sig[small])
-    assert info == {"no_plus_root": 0, "squash": 0, "clamped": 0}
+    assert info == {"inverted": 0, "det_ge2": 0, "no_plus_root": 0, "squash": 0, "clamped": 0}
 
 
 def test_sl3_special_cases():
@@ -185,6 +185,78 @@ def test_sl3_squash_regime():
     U1, U2 = np.meshgrid(np.linspace(1.5, 3, 801), np.linspace(1.5, 3, 801), indexing="ij")
     cand = np.stack([np.exp(U1), np.exp(U2), np.exp(-U1 - U2)], -1).reshape(-1, 3)
     assert d_sq <= ((cand - 10) ** 2).sum(axis=1).min() + 1e-6
+
+
+def _pair_quartic_nearest(a, b, c):
+    """Nearest point to (a, b) on the hyperbola {s_i s_j = c, s > 0}, from the
+    stationary condition of f(t) = (t - a)^2 + (c/t - b)^2 in t = s_i:
+    t^4 - a t^3 + b c t - c^2 = 0 (numpy.roots), best real positive root."""
+    r = np.roots([1.0, -a, 0.0, b * c, -c * c])
+    r = r[(np.abs(r.imag) <= 1e-9 * np.abs(r)) & (r.real > 0)].real
+    d = (r - a) ** 2 + (c / r - b) ** 2
+    t = r[int(np.argmin(d))]
+    return np.array([t, c / t]), float(d.min())
+
+
+def test_sl3_clamp_bruteforce():
+    """sigma = (50, 40, 1e-4): the KKT point has s_3 ~ 5e-4 < 0.01, so s_3 is
+    clamped to 0.01 and frozen, and (s_1, s_2) is the nearest point to (50, 40)
+    on s_1 s_2 = 100.  That pair has no + branch root (at mu = -400 the + branch
+    product is 40 * 20 = 800 > 100): the nearest point squashes s_2."""
+    s, info = oracle.proj_sl3([[50.0, 40.0, 1e-4]])
+    s = s[0]
+    assert s[2] == 0.01
+    assert abs(np.prod(s) - 1.0) < 1e-13 and s.min() >= 0.01
+    assert info["clamped"] == 1 and info["squash"] == 1
+    # brute force over the hyperbola
+    t = np.geomspace(1e-3, 1e5, 2_000_001)
+    dmin = ((t - 50.0) ** 2 + (100.0 / t - 40.0) ** 2).min()
+    d = (s[0] - 50.0) ** 2 + (s[1] - 40.0) ** 2
+    assert d <= dmin + 1e-9 and d >= dmin - 1e-3
+    # closed form of the pair problem
+    pq, _ = _pair_quartic_nearest(50.0, 40.0, 100.0)
+    assert np.abs(s[:2] - pq).max() < 1e-9 * 50
+
+
+def test_sl3_clamp_random_pairs_and_double_clamp():
+    """Clamped rows: feasible (product 1, every s >= 0.01), the clamped axis is
+    exactly 0.01, and the other two are the nearest point on their hyperbola
+    (quartic closed form).  Two clamps leave the third axis at 1e4."""
+    rng = np.random.default_rng(13)
+    n = 40
+    big = np.exp(rng.uniform(np.log(12.0), np.log(80.0), (n, 2)))
+    s3 = np.where(rng.random(n) < 0.5, 1.0, -1.0) * np.exp(rng.uniform(np.log(1e-5), np.log(3e-3), n))
+    sig = np.column_stack([np.sort(big, axis=1)[:, ::-1], s3])
+    s, info = oracle.proj_sl3(sig)
+    assert np.abs(np.prod(s, axis=1) - 1.0).max() < 1e-12
+    assert s.min() >= 0.01
+    assert info["clamped"] == n and info["inverted"] == int((s3 < 0).sum())
+    for e in range(n):
+        assert s[e, 2] == 0.01
+        pq, _ = _pair_quartic_nearest(sig[e, 0], sig[e, 1], 100.0)
+        assert np.abs(s[e, :2] - pq).max() < 1e-8 * sig[e, 0], e
+    s, info = oracle.proj_sl3([[1e5, 1e-3, 1e-3]])
+    assert np.array_equal(s[0], [1e4, 0.01, 0.01]) or np.abs(s[0] - [1e4, 0.01, 0.01]).max() < 1e-9
+    assert info["clamped"] == 1
+
+
+def test_sl3_squash_against_bruteforce_random():
+    """det F >= 2: the result is the nearest point of the whole surface
+    {s1 s2 s3 = 1} (dense grid in log coordinates), whichever branch it is on,
+    unless a clamp fired."""
+    rng = np.random.default_rng(14)
+    u = np.linspace(-7.0, 5.0, 2401)
+    U1, U2 = np.meshgrid(u, u, indexing="ij")
+    cand = np.stack([np.exp(U1), np.exp(U2), np.exp(-U1 - U2)], -1).reshape(-1, 3)
+    sig = np.sort(np.exp(rng.uniform(np.log(0.6), np.log(9.0), (12, 3))), axis=1)[:, ::-1]
+    s, info = oracle.proj_sl3(sig)
+    assert info["det_ge2"] >= 6 and info["squash"] >= 1
+    for e in range(len(sig)):
+        if s[e].min() <= 0.01:
+            continue
+        d = ((s[e] - sig[e]) ** 2).sum()
+        dgrid = ((cand - sig[e]) ** 2).sum(axis=1).min()
+        assert d <= dgrid + 1e-9 * max(1.0, dgrid), e
 
 
 # --- local step ------------------------------------------------------------------
