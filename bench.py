@@ -106,8 +106,20 @@ def run(args):
     prefactor_s = time.perf_counter() - t0
     info = mesh.info()
     print(f"# prefactor {prefactor_s:.2f} s, info {info}", file=sys.stderr, flush=True)
+    # the interface factor's entries without the merge of odd-depth separators
+    # into their parents (the merge adds stored values to save launches): the
+    # method's count of what the interface sweeps must read
+    keep_cfg = ctx.config()
+    ctx.set_config(iface_merge_max_cols=0)
+    m_count = vhpd.Mesh(ctx, p.X, p.tets)
+    m_count.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
+    m_count.prefactor(p.n_subdomains, args.refine)
+    nnz_coarse_unmerged = m_count.info()["nnz_coarse"]
+    m_count.close()
+    ctx.set_config(**keep_cfg)
 
     # first frame from rest, kept for the error against the oracle
+    mesh.regime_counts(reset=True, stream=stream)
     mesh.step(1, stream)
     x1, v1 = mesh.read_state(stream)
     mesh.step(max(0, args.warmup - 1), stream)
@@ -123,6 +135,9 @@ def run(args):
     torch.cuda.synchronize()
     ms_per_frame = ev0.elapsed_time(ev1) / args.steps
 
+    # projection regimes met by every local step since the first frame (Eq.
+    # vol_pre): the workload stays on the plain + branch root
+    regimes = mesh.regime_counts(stream=stream)
     info = mesh.info()
     classes = ("local", "residual", "interior_fwd", "interface", "interior_bwd")
     nbytes = {"local": info["bytes_local"], "residual": info["bytes_residual"],
@@ -157,29 +172,39 @@ def run(args):
         iso_us[k] = e0.elapsed_time(e1) / n * 1e3
 
     traffic = committed_traffic()
+    mbytes = method_bytes(p, info, nnz_coarse_unmerged)
     rooflines = {}
     for k in classes:
-        gbs = nbytes[k] / (group_us[k] * 1e-6) / 1e9
-        iso = nbytes[k] / (iso_us[k] * 1e-6) / 1e9
+        gbs = mbytes[k] / (group_us[k] * 1e-6) / 1e9
+        iso = mbytes[k] / (iso_us[k] * 1e-6) / 1e9
         t = traffic.get(k)
         rooflines[k] = {"kernel": kname[k], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                        "traffic": t, "bytes_per_launch": int(nbytes[k] / launches[k]),
+                        "traffic": t, "bytes_per_launch": int(mbytes[k] / launches[k]),
+                        "representation_bytes_per_launch": int(nbytes[k] / launches[k]),
+                        "representation_over_method": round(nbytes[k] / mbytes[k], 3),
+                        "representation_frac": round(nbytes[k] / (group_us[k] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                         "avg_launch_us": round(group_us[k] / launches[k], 3),
                         "launches_per_group": launches[k],
                         "us_per_frame": round(breakdown[k] * 1e3, 1),
                         "isolated_avg_launch_us": round(iso_us[k] / launches[k], 3),
                         "isolated_achieved": round(iso, 1), "isolated_frac": round(iso / HBM_PEAK_GBS, 4)}
+    rooflines["interface"]["nnz_factor_unmerged"] = int(nnz_coarse_unmerged)
+    rooflines["interface"]["nnz_factor_stored"] = int(info["nnz_coarse"])
     dominant = max(classes, key=lambda k: breakdown[k])
     roofline = dict(rooflines[dominant])
-    ls_b = nbytes["local"] + nbytes["residual"]
+    ls_b = mbytes["local"] + mbytes["residual"]
+    ls_us = group_us["local"] + group_us["residual"]
+    ls_iso = iso_us["local"] + iso_us["residual"]
     local_scatter = {
         "kernels": "k_local + k_residual",
         "bytes_per_iteration": ls_b,
-        "us_per_iteration": round(group_us["local"] + group_us["residual"], 3),
-        "achieved": round(ls_b / ((group_us["local"] + group_us["residual"]) * 1e-6) / 1e9, 1),
-        "isolated_us_per_iteration": round(iso_us["local"] + iso_us["residual"], 3),
-        "isolated_achieved": round(ls_b / ((iso_us["local"] + iso_us["residual"]) * 1e-6) / 1e9, 1),
+        "representation_bytes_per_iteration": nbytes["local"] + nbytes["residual"],
+        "us_per_iteration": round(ls_us, 3),
+        "target_us_per_iteration": round(ls_b / (0.6 * HBM_PEAK_GBS * 1e9) * 1e6, 2),
+        "achieved": round(ls_b / (ls_us * 1e-6) / 1e9, 1),
+        "isolated_us_per_iteration": round(ls_iso, 3),
+        "isolated_achieved": round(ls_b / (ls_iso * 1e-6) / 1e9, 1),
     }
     local_scatter["frac"] = round(local_scatter["achieved"] / HBM_PEAK_GBS, 4)
     local_scatter["isolated_frac"] = round(local_scatter["isolated_achieved"] / HBM_PEAK_GBS, 4)
@@ -209,6 +234,7 @@ def run(args):
         "breakdown_ms_per_frame": breakdown,
         "hbm_copy_calibration": copy_cal,
         "prefactor_s": round(prefactor_s, 3),
+        "projection_regimes": dict(regimes, element_evaluations=nt * p.pd_iters * (args.warmup + args.steps)),
     }
 
     if not args.no_embed:
@@ -224,6 +250,28 @@ def run(args):
     if args.adjoint:
         out["adjoint"] = adjoint_timing(args)
     print(json.dumps(out), flush=True)
+
+
+def method_bytes(p, info, nnz_coarse_unmerged):
+    """Bytes each kernel class must move per launch group by the method's own
+    count, independent of this library's storage:
+      local step   per tet: 4 vertex ids (16 B), Dm^{-1} (36 B), two weights
+                   (8 B), four corner forces out (48 B); each vertex's
+                   displacement read once (12 B per vertex);
+      scatter      per (tet, corner) incidence: a 4-byte slot index and the
+                   12-byte force; per vertex 32 B (inertia term and the
+                   residual out);
+      interior     every FP32 entry of the interior factors once per sweep
+                   (4 B), the interior rows' vectors in and out;
+      interface    every entry of the interface factor once per sweep, with
+                   its index (8 + 4 B), two sweeps; the entries counted without
+                   the merge fill."""
+    nt, nv, nf, ni = p.nt, p.nv, info["n_free"], info["n_interior"]
+    return {"local": nt * (16 + 36 + 8 + 48) + nv * 12,
+            "residual": 4 * nt * (4 + 12) + nv * 32,
+            "interior_fwd": 4 * info["nnz_interior"] + ni * (24 + 12),
+            "interface": 2 * 12 * nnz_coarse_unmerged,
+            "interior_bwd": 4 * info["nnz_interior"] + ni * 12 + nf * (24 + 24)}
 
 
 def embed_timing(mesh, p, stream, torch, per_tet=4, reps=20):

@@ -75,6 +75,37 @@ int vh_ctx_hbm_in_use(const vh_ctx* ctx, size_t* bytes);
  * allocations and admissions are checked against the new value. */
 int vh_ctx_set_hbm_budget(vh_ctx* ctx, size_t hbm_budget_bytes);
 
+/* Execution settings of a context (no process-wide switches exist).
+ *   use_graphs:        1 (default): a mesh replays its frame as a captured HIP
+ *                      graph, and a server launches captured frame graphs;
+ *                      0: every launch of a frame is enqueued directly
+ *                      (the same kernels and arguments, hence the same results);
+ *   iface_lanes32_min, iface_lanes64_min (defaults 96, 384, both >= 1):
+ *                      an interface-solve phase whose mean task length (rows
+ *                      of the factor block a task sweeps) reaches these values
+ *                      runs 32 / 64 lanes per task, else 16.  Results do not
+ *                      depend on the lane count beyond FP64 summation order;
+ *   thin_separators:   1 (default): a separator vertex whose neighbours lie
+ *                      under one side of its separator only is eliminated on
+ *                      that side (a smaller interface); 0: every vertex shared
+ *                      by elements of two subdomains is an interface vertex;
+ *   iface_merge_max_cols (default 3000, >= 0): a separator at odd depth of the
+ *                      bisection tree joins its parent's block when the merged
+ *                      block has at most this many columns (fewer interface
+ *                      launches, more stored values); 0: no merging.
+ * The last four change the plan, hence rounding, not the solution.
+ * vh_ctx_set_config validates and copies *cfg (VH_EINVAL on out-of-range
+ * values); it applies to meshes prefactored and servers opened afterwards, and
+ * use_graphs also to later vh_mesh_step calls of meshes already resident. */
+typedef struct vh_config {
+    int32_t use_graphs;
+    int32_t iface_lanes32_min, iface_lanes64_min;
+    int32_t thin_separators;
+    int32_t iface_merge_max_cols;
+} vh_config;
+int vh_ctx_get_config(const vh_ctx* ctx, vh_config* cfg);
+int vh_ctx_set_config(vh_ctx* ctx, const vh_config* cfg);
+
 /* Mesh: rest positions X [nv][3] (metres) and tets [nt][4].  Every tet must
  * have positive rest volume det([X1-X0, X2-X0, X3-X0])/6 > 0 (VH_EINVAL
  * otherwise; tets are never reoriented silently).  Sec. 5 defines the per-tet
@@ -93,14 +124,22 @@ int vh_mesh_set_params(vh_mesh* mesh, const double* gamma_s, const double* gamma
                        const double* mass, const uint8_t* pinned, const double* gravity,
                        double dt, int32_t pd_iters);
 
+/* Arithmetic of the step (precision_mode of vh_mesh_prefactor).  The one
+ * mode: local step and interior subdomain solves in FP32 with FP32
+ * accumulation; factorizations, interface (Schur complement) solve, residual
+ * and refinement in FP64; state x, v in FP64. */
+enum { VH_PRECISION_MIXED = 0 };
+
 /* Prefactor (host FP64): partitions the elements into n_subdomains (a power of
  * two, >= 1) by recursive breadth-first bisection, orders each subdomain's
  * interior by nested dissection and the interface by the bisection tree,
  * factors the global matrix (interior Cholesky factors and the interface
  * Schur complement), and uploads it.  refine_steps (>= 0) extra solves of the
  * global system against its FP64 residual are done every PD iteration.
+ * precision_mode must be VH_PRECISION_MIXED (VH_EINVAL otherwise).
  * VH_ENOTSPD on a non-positive pivot, VH_ENOMEM over the HBM budget. */
-int vh_mesh_prefactor(vh_mesh* mesh, int32_t n_subdomains, int32_t refine_steps);
+int vh_mesh_prefactor(vh_mesh* mesh, int32_t n_subdomains, int32_t refine_steps,
+                      int32_t precision_mode);
 
 /* Advance n_frames time steps on `stream` (asynchronous). */
 int vh_mesh_step(vh_mesh* mesh, int32_t n_frames, void* stream);
@@ -132,6 +171,24 @@ typedef struct vh_mesh_info {
     int32_t interface_launches;   /* kernel launches per interface solve */
 } vh_mesh_info;
 int vh_mesh_get_info(const vh_mesh* mesh, vh_mesh_info* info);
+
+/* Projection regimes met by the local step (Sec. 7.1, Eq. vol_pre), counted
+ * per element evaluation (one element in one PD iteration; the adjoint's
+ * re-evaluations count too) since the last reset (prefactor resets them):
+ *   clamped       a projected singular value fell below 0.01: it was set to
+ *                 0.01, frozen, and the other axes solved again for the
+ *                 remaining product;
+ *   inverted      sigma_3 <= 0 (det F <= 0);
+ *   det_ge2       every sigma_i > 0 and det F >= 2, where stationary points
+ *                 with one axis on the minus root of the Lagrange condition
+ *                 exist and are searched;
+ *   squash        such a point was the nearest one (also in a clamp re-solve);
+ *   no_plus_root  the branch with every axis on its plus root had no root.
+ * Synchronises `stream`; reset != 0 zeroes the counters after reading. */
+typedef struct vh_regime_counts {
+    uint64_t clamped, inverted, det_ge2, squash, no_plus_root;
+} vh_regime_counts;
+int vh_mesh_regime_counts(vh_mesh* mesh, vh_regime_counts* out, int32_t reset, void* stream);
 
 /* Per-kernel timing with HIP events recorded on the step's stream around each
  * launch group of a kernel class (bit c of class_mask enables class c):
@@ -182,9 +239,9 @@ int vh_mesh_embed_device(vh_mesh* mesh, double* out_dev, void* stream);
  * and K both depend on gamma_s, Sec. 7.1) and xbar^(k) = sum_e G_e^T
  * J_P(F_e(x^(k))) [G_e lambda], the derivative of the projections of Eq.
  * pd_local and Eq. vol_pre (FP32, like the local step); then the predictor and
- * the BDF1 velocity are reversed.  Out-of-regime projections (clamped
- * singular values) are not differentiated through; they are counted like in
- * the forward step. ---- */
+ * the BDF1 velocity are reversed.  A singular value frozen by the clamp has
+ * zero derivative and the others follow their re-solved product; the
+ * projections are counted like in the forward step. ---- */
 
 /* Run n_frames (>= 1) steps from the host state x0, v0 [nv][3] (user order)
  * on `stream`, keeping (x, v) on the device every ckpt_every (>= 1) frames

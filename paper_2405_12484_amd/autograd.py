@@ -8,9 +8,11 @@ its checkpoints and the discrete adjoint run in libvhpd).
     loss = 0.5 * ((x - target) ** 2).sum()
     loss.backward()              # gamma_s.grad via vh_mesh_adjoint_backward
 
-The stiffness enters the global matrix, so every forward refactors it (host
-FP64).  One trajectory holds one set of checkpoints: call backward before the
-next forward.
+The stiffness enters the global matrix, so a forward at a new gamma_s
+refactors it (host FP64); a forward at the gamma_s already factored reuses the
+factorization.  One trajectory holds one set of checkpoints (those of its
+latest forward); the backward of an earlier output replays that output's
+forward first, so every gradient belongs to its own gamma_s.
 """
 
 from __future__ import annotations
@@ -24,13 +26,18 @@ from . import vhpd
 class _TrajectoryFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, gamma_s, traj):
-        xf = traj._run(gamma_s.detach().cpu().numpy().astype(np.float64))
-        ctx.traj = traj
+        gs = gamma_s.detach().cpu().numpy().astype(np.float64)
+        xf = traj._run(gs)
+        ctx.traj, ctx.gamma_s, ctx.generation = traj, gs, traj.generation
         return torch.as_tensor(xf, dtype=torch.float64, device=gamma_s.device)
 
     @staticmethod
     def backward(ctx, grad_x):
-        g = ctx.traj.mesh.adjoint_backward(grad_x.detach().cpu().numpy().astype(np.float64))
+        traj = ctx.traj
+        if traj.generation != ctx.generation:       # a later forward replaced the checkpoints
+            traj._run(ctx.gamma_s)
+            ctx.generation = traj.generation
+        g = traj.mesh.adjoint_backward(grad_x.detach().cpu().numpy().astype(np.float64))
         return torch.as_tensor(g, dtype=grad_x.dtype, device=grad_x.device), None
 
 
@@ -48,11 +55,16 @@ class Trajectory:
         self.n_subdomains, self.refine_steps = int(n_subdomains), int(refine_steps)
         self.frames, self.ckpt_every = int(frames), int(ckpt_every)
         self.X = self.mesh.X
+        self.generation = 0          # forwards run so far (each replaces the checkpoints)
+        self._factored_gs = None     # the gamma_s of the current factorization
 
     def _run(self, gamma_s):
         m = self.mesh
-        m.set_params(gamma_s, self.gamma_v, self.mass, self.pinned, self.gravity, self.dt, self.pd_iters)
-        m.prefactor(self.n_subdomains, self.refine_steps)
+        if self._factored_gs is None or not np.array_equal(self._factored_gs, gamma_s):
+            m.set_params(gamma_s, self.gamma_v, self.mass, self.pinned, self.gravity, self.dt, self.pd_iters)
+            m.prefactor(self.n_subdomains, self.refine_steps)
+            self._factored_gs = np.array(gamma_s, dtype=np.float64)
+        self.generation += 1
         return m.adjoint_forward(self.X, np.zeros_like(self.X), self.frames, self.ckpt_every)
 
     def __call__(self, gamma_s: torch.Tensor) -> torch.Tensor:

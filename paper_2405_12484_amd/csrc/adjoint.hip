@@ -55,7 +55,7 @@ struct Scratch {
 };
 
 int one_frame(vh_mesh* m, hipStream_t s) {
-    if (m->use_graph) {
+    if (m->ctx->cfg.use_graphs) {
         VH_TRY(ensure_graph(m));
         VH_HIP(hipGraphLaunch(m->gexec, s));
         return VH_OK;

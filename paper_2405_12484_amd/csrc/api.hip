@@ -161,6 +161,7 @@ int alloc_plan(vh_mesh* m) {
     chk(upload(m, &d.K_col, P.K_col));
     chk(upload(m, &d.K_val, P.K_val));
     chk(dalloc(m, &d.flags, 4));
+    chk(dalloc(m, &d.regime, 8));
     return r;
 }
 
@@ -176,40 +177,40 @@ size_t launch_set_bytes(const vh::Plan& P) {
 
 }  // namespace
 
-int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta) {
+int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta, const vh::DevMesh* G) {
     {
         ProfScope ps(m, s, 3);
-        VH_HIP(vh::launch_interior_fwd(L.ifwd, L.lds_fwd, s));
+        VH_HIP(vh::launch_interior_fwd(with_record(L.ifwd, G), L.lds_fwd, s));
     }
     {
         ProfScope ps(m, s, 4);
-        for (const auto& c : L.cfwd) VH_HIP(vh::launch_coarse(c.ref, c.kind, c.group, s));
-        for (const auto& c : L.cbwd) VH_HIP(vh::launch_coarse(c.ref, c.kind, c.group, s));
+        for (const auto& c : L.cfwd) VH_HIP(vh::launch_coarse(with_record(c.ref, G), c.kind, c.group, s));
+        for (const auto& c : L.cbwd) VH_HIP(vh::launch_coarse(with_record(c.ref, G), c.kind, c.group, s));
     }
     {
         ProfScope ps(m, s, 5);
-        VH_HIP(vh::launch_interior_bwd(L.ibwd, L.lds_bwd, s, apply, keep_delta));
+        VH_HIP(vh::launch_interior_bwd(with_record(L.ibwd, G), L.lds_bwd, s, apply, keep_delta));
     }
     return VH_OK;
 }
 
-int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s) {
+int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s, const vh::DevMesh* G) {
     {
         ProfScope ps(m, s, 1);
-        VH_HIP(vh::launch_local(L.local, s, false));
+        VH_HIP(vh::launch_local(with_record(L.local, G), s, false));
     }
     {
         ProfScope ps(m, s, 2);
-        VH_HIP(vh::launch_residual(L.residual, s));
+        VH_HIP(vh::launch_residual(with_record(L.residual, G), s));
     }
     const bool refine = L.refine_steps > 0;
-    VH_TRY(solve(m, L, s, true, refine));
+    VH_TRY(solve(m, L, s, true, refine, G));
     for (int32_t k = 0; k < L.refine_steps; ++k) {
         {
             ProfScope ps(m, s, 6);
-            VH_HIP(vh::launch_refine_residual(L.refine, s));
+            VH_HIP(vh::launch_refine_residual(with_record(L.refine, G), s));
         }
-        VH_TRY(solve(m, L, s, true, k + 1 < L.refine_steps));
+        VH_TRY(solve(m, L, s, true, k + 1 < L.refine_steps, G));
     }
     return VH_OK;
 }
@@ -382,13 +383,6 @@ int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSe
         if (lds_need > (size_t)lds_limit)
             return fail(VH_EINVAL, "a subdomain needs " + std::to_string(lds_need) + " bytes of LDS (limit " +
                                        std::to_string(lds_limit) + "); use more subdomains");
-        // the attribute only grows, so launches of smaller sets stay valid
-        static size_t lds_set[64] = {};
-        size_t& cur = lds_set[ctx->device & 63];
-        if (lds_need > std::max<size_t>(cur, 65536)) {
-            VH_HIP(vh::interior_set_lds_limit(lds_need));
-            cur = lds_need;
-        }
     }
     const size_t need = sizeof(vh::DevMesh) * ng + sizeof(int32_t) * (tab.size() + ng);
     if (check_budget && ctx->budget && ctx->in_use + need > ctx->budget)
@@ -411,15 +405,15 @@ int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSe
     return VH_OK;
 }
 
-int frame_direct(vh_mesh* m, const LaunchSet& L, hipStream_t s) {
+int frame_direct(vh_mesh* m, const LaunchSet& L, hipStream_t s, const vh::DevMesh* G) {
     {
         ProfScope ps(m, s, 0);
-        VH_HIP(vh::launch_predictor(L.predict, s));
+        VH_HIP(vh::launch_predictor(with_record(L.predict, G), s));
     }
-    for (int32_t k = 0; k < L.pd_iters; ++k) VH_TRY(pd_iteration(m, L, s));
+    for (int32_t k = 0; k < L.pd_iters; ++k) VH_TRY(pd_iteration(m, L, s, G));
     {
         ProfScope ps(m, s, 7);
-        VH_HIP(vh::launch_velocity(L.velocity, s));
+        VH_HIP(vh::launch_velocity(with_record(L.velocity, G), s));
     }
     return VH_OK;
 }
@@ -471,9 +465,14 @@ int host_factor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     if (refine_steps < 0) return fail(VH_EINVAL, "refine_steps must be >= 0");
     m->planned = false;
     std::string msg;
+    vh::PlanOptions opt;
+    opt.lanes32_min = m->ctx->cfg.iface_lanes32_min;
+    opt.lanes64_min = m->ctx->cfg.iface_lanes64_min;
+    opt.thin_separators = m->ctx->cfg.thin_separators != 0;
+    opt.merge_max_cols = m->ctx->cfg.iface_merge_max_cols;
     int rc = vh::build_plan(m->X.data(), m->nv, m->tets.data(), m->nt, m->gs.data(), m->gv.data(),
                             m->mass.data(), m->pinned.data(), m->g, m->dt, m->iters, n_subdomains,
-                            refine_steps, 32, vh::interior_chunk_words(), m->plan, msg);
+                            refine_steps, 32, vh::interior_chunk_words(), opt, m->plan, msg);
     if (rc != 0) return fail(rc, msg);
     // the interior kernels hold two LDS chunks (48 KB each) next to the
     // subdomain's vectors: gfx950 gives a workgroup up to 160 KB
@@ -528,6 +527,7 @@ int upload_device(vh_mesh* m) {
     const size_t nv3 = (size_t)P.nv * 3;
     VH_HIP(hipMemset(d.v, 0, nv3 * sizeof(double)));
     VH_HIP(hipMemset(d.flags, 0, 4 * sizeof(uint32_t)));
+    VH_HIP(hipMemset(d.regime, 0, 8 * sizeof(unsigned long long)));
     VH_HIP(hipMemset(d.delta, 0, (size_t)P.n_free * 3 * sizeof(double)));
     {
         std::vector<vh_mesh*> one{m};
@@ -537,8 +537,6 @@ int upload_device(vh_mesh* m) {
             return lrc;
         }
     }
-    const char* ng = std::getenv("VHPD_NO_GRAPH");
-    m->use_graph = !(ng && ng[0] == '1');
     VH_HIP(vh::launch_refresh_u(d, nullptr));
     VH_HIP(hipDeviceSynchronize());
     m->has_saved = false;
@@ -561,10 +559,34 @@ int vh_ctx_create(vh_ctx** out, int device, size_t hbm_budget_bytes) {
     VH_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(VH_EINVAL, "device id out of range");
     VH_HIP(hipSetDevice(device));
+    // the interior solves may use up to the whole LDS of a workgroup: the
+    // device limit is set once here (a kernel attribute of this device), so a
+    // launch never depends on which meshes were prefactored before it
+    int lds_limit = 0;
+    VH_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    VH_HIP(vh::interior_set_lds_limit((size_t)lds_limit));
     vh_ctx* c = new vh_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;
     *out = c;
+    return VH_OK;
+}
+
+int vh_ctx_get_config(const vh_ctx* ctx, vh_config* cfg) {
+    if (!ctx || !cfg) return fail(VH_EINVAL, "null argument");
+    *cfg = ctx->cfg;
+    return VH_OK;
+}
+
+int vh_ctx_set_config(vh_ctx* ctx, const vh_config* cfg) {
+    if (!ctx || !cfg) return fail(VH_EINVAL, "null argument");
+    if (cfg->use_graphs != 0 && cfg->use_graphs != 1) return fail(VH_EINVAL, "use_graphs must be 0 or 1");
+    if (cfg->iface_lanes32_min < 1 || cfg->iface_lanes64_min < 1)
+        return fail(VH_EINVAL, "interface lane thresholds must be >= 1");
+    if (cfg->thin_separators != 0 && cfg->thin_separators != 1)
+        return fail(VH_EINVAL, "thin_separators must be 0 or 1");
+    if (cfg->iface_merge_max_cols < 0) return fail(VH_EINVAL, "iface_merge_max_cols must be >= 0");
+    ctx->cfg = *cfg;
     return VH_OK;
 }
 
@@ -655,8 +677,9 @@ int vh_mesh_set_params(vh_mesh* m, const double* gamma_s, const double* gamma_v,
     return VH_OK;
 }
 
-int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
+int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps, int32_t precision_mode) {
     if (!m) return fail(VH_EINVAL, "null mesh");
+    if (precision_mode != VH_PRECISION_MIXED) return fail(VH_EINVAL, "unknown precision_mode");
     if (m->srv_id >= 0 && m->ctx->srv) return fail(VH_ESTATE, "mesh is in the server; release it first");
     VH_TRY(set_device(m));
     free_device(m);
@@ -669,7 +692,7 @@ int vh_mesh_step(vh_mesh* m, int32_t n_frames, void* stream) {
     if (n_frames < 0) return fail(VH_EINVAL, "n_frames must be >= 0");
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (m->prof_mask || !m->use_graph) {
+    if (m->prof_mask || !m->ctx->cfg.use_graphs) {
         for (int32_t f = 0; f < n_frames; ++f) VH_TRY(frame_direct(m, m->ls, s));
         return VH_OK;
     }
@@ -729,6 +752,26 @@ int vh_mesh_write_state_device(vh_mesh* m, const double* x_dev, const double* v_
     VH_HIP(vh::launch_from_user(m->dm.nv, m->dm.n_free, m->dm.perm, v_dev, nullptr, m->dm.v, s));
     VH_HIP(vh::launch_refresh_u(m->dm, s));
     if (m->srv_id >= 0) VH_HIP(hipStreamSynchronize(s));   // ordered before the server's next frame
+    return VH_OK;
+}
+
+int vh_mesh_regime_counts(vh_mesh* m, vh_regime_counts* out, int32_t reset, void* stream) {
+    if (!m || !out) return fail(VH_EINVAL, "null argument");
+    VH_TRY(check_quiet(m));
+    VH_TRY(set_device(m));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned long long c[8];
+    VH_HIP(hipMemcpyAsync(c, m->dm.regime, sizeof(c), hipMemcpyDeviceToHost, s));
+    VH_HIP(hipStreamSynchronize(s));
+    out->clamped = c[0];
+    out->inverted = c[1];
+    out->det_ge2 = c[2];
+    out->squash = c[3];
+    out->no_plus_root = c[4];
+    if (reset) {
+        VH_HIP(hipMemsetAsync(m->dm.regime, 0, sizeof(c), s));
+        VH_HIP(hipStreamSynchronize(s));
+    }
     return VH_OK;
 }
 

@@ -42,10 +42,6 @@ constexpr int OK = 0, EINVAL_ = -1, ENOMEM_ = -2, ENOTSPD_ = -3;
 constexpr int32_t kMaxInteriorCols = 32;
 // tets per local-step workgroup (one thread per tet)
 constexpr int32_t kLocalBlock = 256;
-// largest interface supernode formed by merging a separator with its children's
-constexpr int64_t kMaxMergedCols = 3000;
-// interface tasks use 32 / 64 lanes from these mean lengths (16 below)
-constexpr int64_t kIfaceG32Min = 96, kIfaceG64Min = 384;
 
 inline void tet_dm(const double* X, const int32_t* t, double Dm[9]) {
     // Dm[r][k] = X[t[k+1]][r] - X[t[0]][r]
@@ -359,8 +355,8 @@ int check_mesh(const double* X, int32_t nv, const int32_t* tets, int32_t nt, std
 int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                const double* gamma_s, const double* gamma_v, const double* mass,
                const uint8_t* pinned, const double* gravity, double dt, int32_t pd_iters,
-               int32_t D, int32_t refine_steps, int32_t leaf_max, int32_t chunk_floats, Plan& P,
-               std::string& msg) {
+               int32_t D, int32_t refine_steps, int32_t leaf_max, int32_t chunk_floats,
+               const PlanOptions& opt, Plan& P, std::string& msg) {
     auto t_start = std::chrono::steady_clock::now();
     if (D < 1 || (D & (D - 1))) {
         msg = "n_subdomains must be a power of two >= 1";
@@ -408,28 +404,6 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             msg = "free vertex " + std::to_string(v) + " belongs to no element";
             return EINVAL_;
         }
-    // Every interface tree level costs the solve a fixed latency per phase
-    // (three launches), while the separators are small: the separators at odd
-    // depths (1, 3, 5, ... from the root) join their parent's, halving the
-    // levels, as long as the merged supernode stays within kMaxMergedCols
-    // columns (a merge replaces three sparse blocks by one denser block).
-    if (D > 1) {
-        auto depth_of = [](int32_t h) { return 31 - __builtin_clz((uint32_t)h); };
-        std::vector<int64_t> cnt(D, 0);
-        for (int32_t v = 0; v < nv; ++v)
-            if (node[v] >= 1 && node[v] < D) cnt[node[v]]++;
-        std::vector<int32_t> into(D);
-        for (int32_t h = 1; h < D; ++h) into[h] = h;
-        for (int32_t h = 2; h < D; ++h) {
-            if (depth_of(h) % 2 == 0) continue;
-            const int32_t par = h >> 1, sib = h ^ 1;
-            const int64_t merged = cnt[par] + cnt[h] + ((sib < D) ? cnt[sib] : 0);
-            if (merged <= kMaxMergedCols) into[h] = par;
-        }
-        for (int32_t v = 0; v < nv; ++v)
-            if (node[v] >= 1 && node[v] < D) node[v] = into[node[v]];
-    }
-
     // ---- vertex adjacency ------------------------------------------------------
     std::vector<int32_t> vptr(nv + 1, 0), vadj;
     {
@@ -447,6 +421,111 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             vadj[i] = pr[i].second;
         }
         for (int32_t i = 0; i < nv; ++i) vptr[i + 1] += vptr[i];
+    }
+
+    // ---- separator thinning ------------------------------------------------------
+    // A vertex of separator h whose neighbours (through K) lie only under one
+    // child of h, or in separators at h or above, need not wait for h: it can
+    // be eliminated inside that child's subtree, at the lowest node whose
+    // subtree holds every such neighbour (so no two subtrees couple).  The
+    // element partition leaves such vertices wherever its cut is jagged; per
+    // separator, top-down, the side that takes more of them takes them all
+    // (moving vertices to one side never gives another vertex a neighbour on
+    // the other side, so the choice stays valid as they move).
+    if (opt.thin_separators && D > 1) {
+        auto in_subtree = [](int32_t a, int32_t root) {
+            while (a > root) a >>= 1;
+            return a == root;
+        };
+        auto lca = [](int32_t a, int32_t b) {
+            while (a != b) {
+                if (a > b) a >>= 1;
+                else b >>= 1;
+            }
+            return a;
+        };
+        std::vector<std::vector<int32_t>> sep(D);
+        for (int32_t v = 0; v < nv; ++v)
+            if (node[v] >= 1 && node[v] < D) sep[node[v]].push_back(v);
+        std::vector<uint8_t> mark(nv, 0);
+        for (int32_t h = 1; h < D; ++h) {
+            std::vector<int32_t>& S = sep[h];
+            if (S.empty()) continue;
+            std::vector<uint8_t> has(S.size(), 0);       // bit 0: under 2h, bit 1: under 2h + 1
+            int32_t to_left = 0, to_right = 0;
+            for (size_t i = 0; i < S.size(); ++i) {
+                const int32_t v = S[i];
+                for (int32_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+                    const int32_t w = vadj[k];
+                    if (node[w] < 0 || node[w] <= h) continue;
+                    if (in_subtree(node[w], 2 * h)) has[i] |= 1;
+                    else if (in_subtree(node[w], 2 * h + 1)) has[i] |= 2;
+                }
+                if (!(has[i] & 2)) ++to_left;
+                if (!(has[i] & 1)) ++to_right;
+            }
+            const int32_t side = (to_left >= to_right) ? 2 * h : 2 * h + 1;
+            const uint8_t block = (side == 2 * h) ? 2 : 1;
+            std::vector<int32_t> moved, keep;
+            for (size_t i = 0; i < S.size(); ++i) (has[i] & block ? keep : moved).push_back(S[i]);
+            if (moved.empty()) continue;
+            // lowest node holding the neighbours already under `side` (the
+            // vertices moving with v are not looked at yet)
+            for (int32_t v : moved) mark[v] = 1;
+            std::vector<int32_t> dest(moved.size());
+            for (size_t i = 0; i < moved.size(); ++i) {
+                const int32_t v = moved[i];
+                int32_t n = -1;
+                for (int32_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+                    const int32_t w = vadj[k];
+                    if (node[w] < 0 || mark[w] || !in_subtree(node[w], side)) continue;
+                    n = (n < 0) ? node[w] : lca(n, node[w]);
+                }
+                dest[i] = (n < 0) ? side : n;
+            }
+            for (size_t i = 0; i < moved.size(); ++i) node[moved[i]] = dest[i];
+            // adjacent moved vertices must end on one root-to-leaf path: lift
+            // both to their common ancestor until no pair is on two branches
+            for (bool changed = true; changed;) {
+                changed = false;
+                for (int32_t v : moved)
+                    for (int32_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+                        const int32_t w = vadj[k];
+                        if (!mark[w]) continue;
+                        const int32_t c = lca(node[v], node[w]);
+                        if (c != node[v] && c != node[w]) {
+                            node[v] = node[w] = c;
+                            changed = true;
+                        }
+                    }
+            }
+            for (int32_t v : moved) mark[v] = 0;
+            for (int32_t v : moved)
+                if (node[v] < D) sep[node[v]].push_back(v);
+            S.swap(keep);
+        }
+    }
+
+    // Every interface tree level costs the solve a fixed latency per phase
+    // (three launches), while the separators are small: the separators at odd
+    // depths (1, 3, 5, ... from the root) join their parent's, halving the
+    // levels, as long as the merged supernode stays within opt.merge_max_cols
+    // columns (a merge replaces three sparse blocks by one denser block).
+    if (D > 1 && opt.merge_max_cols > 0) {
+        auto depth_of = [](int32_t h) { return 31 - __builtin_clz((uint32_t)h); };
+        std::vector<int64_t> cnt(D, 0);
+        for (int32_t v = 0; v < nv; ++v)
+            if (node[v] >= 1 && node[v] < D) cnt[node[v]]++;
+        std::vector<int32_t> into(D);
+        for (int32_t h = 1; h < D; ++h) into[h] = h;
+        for (int32_t h = 2; h < D; ++h) {
+            if (depth_of(h) % 2 == 0) continue;
+            const int32_t par = h >> 1, sib = h ^ 1;
+            const int64_t merged = cnt[par] + cnt[h] + ((sib < D) ? cnt[sib] : 0);
+            if (merged <= opt.merge_max_cols) into[h] = par;
+        }
+        for (int32_t v = 0; v < nv; ++v)
+            if (node[v] >= 1 && node[v] < D) node[v] = into[node[v]];
     }
 
     // ---- orderings ---------------------------------------------------------------
@@ -1104,16 +1183,8 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
     P.cgidx.clear();
     P.cfwd.clear();
     P.cbwd.clear();
-    // lanes per interface task by the phase's mean task length; VHPD_IFACE_G
-    // ("g32,g64": the mean lengths from which 32 and 64 lanes are used) overrides
-    int64_t g32_min = kIfaceG32Min, g64_min = kIfaceG64Min;
-    if (const char* ge = std::getenv("VHPD_IFACE_G")) {
-        long long a = 0, b = 0;
-        if (std::sscanf(ge, "%lld,%lld", &a, &b) == 2 && a > 0 && b > 0) {
-            g32_min = a;
-            g64_min = b;
-        }
-    }
+    // lanes per interface task by the phase's mean task length
+    const int64_t g32_min = opt.lanes32_min, g64_min = opt.lanes64_min;
     auto open_cphase = [&](int32_t kind) {
         CPhase ph;
         ph.kind = kind;

@@ -44,7 +44,11 @@ struct DevMesh {
     double* cgd = nullptr;          // [n_cgd][3]
     int32_t *K_ptr = nullptr, *K_col = nullptr;
     double* K_val = nullptr;
-    uint32_t* flags = nullptr;      // [0] non-finite seen, [1] out-of-regime projections, [2] inverted
+    uint32_t* flags = nullptr;      // [0] non-finite value seen in the state
+    // projection regime counters of the local step (element evaluations):
+    // [0] clamped, [1] inverted, [2] det F >= 2, [3] mixed-branch point taken,
+    // [4] no + branch root
+    unsigned long long* regime = nullptr;
     // debug outputs of the local step (allocated on demand)
     float *dbg_T = nullptr, *dbg_sig = nullptr, *dbg_s = nullptr;
 };

@@ -205,6 +205,204 @@ __device__ __forceinline__ float plus_delta(float sg, float mu, float& q) {
     return s - sg;
 }
 
+// Regime word of one projection: what happened beyond the plain + branch root.
+// Bits 4..6 hold the mask of axes frozen by the clamp.
+constexpr uint32_t kSl3Clamped = 1u, kSl3DetGe2 = 2u, kSl3Squash = 4u, kSl3NoPlus = 8u;
+constexpr int kSl3FrozenShift = 4;
+constexpr float kSl3Clamp = 0.01f;     // lower bound on a projected singular value (Sec. 7.1)
+
+// ---- The rare regimes of Eq. vol_pre -----------------------------------------
+// The Lagrange condition s_i (s_i - sigma_i) = mu has, per axis, the + root and,
+// for mu < 0, the - root.  For a product target c over n free axes:
+//   * the + branch (every axis on its + root) has at most one root of
+//     prod s_i(mu) = c, since the product increases with mu;
+//   * a mixed branch (axis k on its - root, mu in [-min sigma^2/4, 0)) can have
+//     roots only when every sigma_i > 0 and prod sigma >= 2 c (there
+//     s_k <= sigma_k / 2 and s_j <= sigma_j); two axes on the - root give
+//     saddle points of the Lagrangian, never the nearest point.
+// The nearest point is the candidate closest to sigma (ties: the + branch, then
+// the lower axis, then the smaller |mu|).  The clamp of Sec. 7.1 sets a
+// component below 0.01 to 0.01, freezes it, and solves the free axes again for
+// the product 1 / 0.01^(frozen count).
+
+// larger root of s^2 - sg s - mu = 0 without cancellation; q = sqrt(sg^2 + 4 mu)
+__device__ __forceinline__ float plus_root(float sg, float mu, float& q) {
+    q = sqrtf(fmaxf(sg * sg + 4.0f * mu, 0.0f));
+    if (sg >= 0.0f) return 0.5f * (sg + q);
+    return (q - sg > 0.0f) ? 2.0f * mu / (q - sg) : 0.0f;
+}
+
+// The free axes of a sub-problem are the set bits of `mask`.  s on the +
+// branch (k < 0) or on the mixed branch with axis k on the - root at mu, and
+// the product of its free components.
+__device__ __forceinline__ float branch_point(const float* sg, uint32_t mask, int k, float mu, float* s) {
+    float p = 1.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float q;
+        const float sp = plus_root(sg[i], mu, q);
+        s[i] = (i == k) ? -2.0f * mu / (sg[i] + q) : sp;
+        if (mask >> i & 1u) p *= s[i];
+    }
+    return p;
+}
+
+// + branch root of prod s_i = c over the free axes (bisection down to
+// adjacent floats); false when the branch has none
+__device__ __forceinline__ bool plus_branch(const float* sg, uint32_t mask, float c, float* s) {
+    float smin = INFINITY, det = 1.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (mask >> i & 1u) {
+            smin = fminf(smin, sg[i]);
+            det *= sg[i];
+        }
+    const bool grow = !(smin > 0.0f) || det <= c;          // root at mu >= 0
+    float lo = grow ? 0.0f : -0.25f * smin * smin, hi = grow ? 1.0f : 0.0f;
+    if (grow) {
+#pragma unroll 1
+        for (int k = 0; k < 260 && branch_point(sg, mask, -1, hi, s) <= c; ++k) hi = 2.0f * hi + 1.0f;
+    } else if (branch_point(sg, mask, -1, lo, s) >= c) {
+        return false;
+    }
+#pragma unroll 1
+    for (int k = 0; k < 300; ++k) {
+        const float mid = 0.5f * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (branch_point(sg, mask, -1, mid, s) > c) hi = mid;
+        else lo = mid;
+    }
+    branch_point(sg, mask, -1, 0.5f * (lo + hi), s);
+    return true;
+}
+
+// Roots of every mixed branch, found by a sign scan of prod s - c over mu at
+// kSl3Scan geometric points from -1e-14 min sigma^2/4 down to -min sigma^2/4,
+// then bisection of each sign change.  A root strictly nearer to sigma than
+// d2 replaces (best, d2) on the free axes; returns whether one did.
+constexpr int kSl3Scan = 1024;
+__device__ __forceinline__ bool mixed_roots(const float* sg, uint32_t mask, float c, float* best, float& d2) {
+    float smin = INFINITY, det = 1.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (mask >> i & 1u) {
+            smin = fminf(smin, sg[i]);
+            det *= sg[i];
+        }
+    if (!(smin > 0.0f) || det < 2.0f * c) return false;
+    const float lo = -0.25f * smin * smin;
+    const float ratio = 1.0320132f;        // 1e14^(1 / (kSl3Scan - 1))
+    bool took = false;
+    float s[3];
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k) {
+        if (!(mask >> k & 1u)) continue;
+        float t = 1e-14f, mu_a = lo * t;
+        float fa = branch_point(sg, mask, k, mu_a, s) - c;
+#pragma unroll 1
+        for (int j = 1; j < kSl3Scan; ++j) {
+            t = (j == kSl3Scan - 1) ? 1.0f : t * ratio;
+            const float mu_b = lo * t;
+            const float fb = branch_point(sg, mask, k, mu_b, s) - c;
+            if ((fa < 0.0f) != (fb < 0.0f)) {
+                float a = mu_a, b = mu_b;
+                const bool neg_a = fa < 0.0f;
+#pragma unroll 1
+                for (int it = 0; it < 300; ++it) {
+                    const float m = 0.5f * (a + b);
+                    if (!(m != a && m != b)) break;
+                    if ((branch_point(sg, mask, k, m, s) - c < 0.0f) == neg_a) a = m;
+                    else b = m;
+                }
+                branch_point(sg, mask, k, 0.5f * (a + b), s);
+                float dd = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    if (mask >> i & 1u) dd += (s[i] - sg[i]) * (s[i] - sg[i]);
+                if (dd < d2) {
+                    d2 = dd;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        if (mask >> i & 1u) best[i] = s[i];
+                    took = true;
+                }
+            }
+            mu_a = mu_b;
+            fa = fb;
+        }
+    }
+    return took;
+}
+
+// nearest point to sg on {product over the free axes of s = c, s > 0}, written
+// to the free axes of s; adds kSl3NoPlus / kSl3Squash to *bits when the +
+// branch has no root / a mixed root is nearer
+__device__ __forceinline__ void nearest_on_product(const float* sg, uint32_t mask, float c, float* s,
+                                                   uint32_t* bits) {
+    if (__builtin_popcount(mask) == 1) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (mask >> i & 1u) s[i] = c;
+        return;
+    }
+    float sp[3];
+    const bool ok = plus_branch(sg, mask, c, sp);
+    float d2 = INFINITY;
+    if (ok) {
+        d2 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (mask >> i & 1u) {
+                s[i] = sp[i];
+                d2 += (sp[i] - sg[i]) * (sp[i] - sg[i]);
+            }
+    } else {
+        *bits |= kSl3NoPlus;
+    }
+    if (mixed_roots(sg, mask, c, s, d2)) *bits |= kSl3Squash;
+}
+
+// The projection outside the plain + branch: det F >= 2 (mixed stationary
+// points may be nearer) or a component below the clamp.  FP32 like the rest of
+// the local step, but by bracketing instead of a fixed count of Newton steps.
+// Writes ds = s - sigma and returns the regime word.
+__device__ __forceinline__ uint32_t proj_sl3_rare(const float* sg, float* ds) {
+    float s[3] = {sg[0], sg[1], sg[2]};
+    uint32_t bits = 0;
+    if (sg[2] > 0.0f && sg[0] * sg[1] * sg[2] >= 2.0f) {
+        bits |= kSl3DetGe2;
+        nearest_on_product(sg, 7u, 1.0f, s, &bits);
+    } else {
+        plus_branch(sg, 7u, 1.0f, s);
+    }
+    uint32_t frozen = 0;
+#pragma unroll 1
+    for (int round = 0; round < 3; ++round) {
+        uint32_t newly = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (!(frozen >> i & 1u) && s[i] < kSl3Clamp) newly |= 1u << i;
+        if (!newly) break;
+        frozen |= newly;
+        const uint32_t free_axes = 7u & ~frozen;
+        float c = 1.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (frozen >> i & 1u) {
+                s[i] = kSl3Clamp;
+                c *= 100.0f;               // 1 / kSl3Clamp
+            }
+        if (!free_axes) break;
+        uint32_t sub_bits = 0;
+        nearest_on_product(sg, free_axes, c, s, &sub_bits);
+        bits |= sub_bits & kSl3Squash;
+    }
+    if (frozen) bits |= kSl3Clamped | (frozen << kSl3FrozenShift);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ds[i] = s[i] - sg[i];
+    return bits;
+}
+
 // Nearest volume-preserving singular values (Eq. vol_pre): the Lagrange
 // condition gives s_i (s_i - sigma_i) = mu for all i; Newton on
 // h(mu) = ln(s1 s2 s3)(mu) from mu = 0, stop when |s1 s2 s3 - 1| is within
@@ -212,11 +410,12 @@ __device__ __forceinline__ float plus_delta(float sg, float mu, float& q) {
 // (p - 1)/p, which has the same root and slope.  Strains of a few percent take
 // 3-4 steps; strongly compressed, nearly flat or inverted elements (sigma_3
 // down to 1e-3, det F close to 2) take up to 10-12, and 16 leaves margin.
-// Returns ds_i = s_i - sigma_i.
+// Writes ds_i = s_i - sigma_i and returns false; returns true instead when
+// det F >= 2 or a component lands below the clamp, where proj_sl3_rare decides.
 constexpr int kSl3Steps = 16;
-__device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_of_regime) {
-    const float lo = (sg[2] > 0.0f) ? -0.25f * sg[2] * sg[2] : 0.0f;
+__device__ __forceinline__ bool proj_sl3_plus(const float* sg, float* ds) {
     float mu = (sg[2] > 0.0f) ? 0.0f : 0.25f;
+    const float lo = (sg[2] > 0.0f) ? -0.25f * sg[2] * sg[2] : 0.0f;
     float q[3], s[3];
 #pragma unroll 1
     for (int it = 0; it < kSl3Steps; ++it) {
@@ -245,13 +444,24 @@ __device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_o
             }
         }
     }
-    out_of_regime = (sg[0] * sg[1] * sg[2] >= 2.0f);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        if (s[i] < 0.01f) {
-            out_of_regime = true;
-            ds[i] = 0.01f - sg[i];
-        }
+    return (sg[2] > 0.0f && sg[0] * sg[1] * sg[2] >= 2.0f) || s[0] < kSl3Clamp || s[1] < kSl3Clamp ||
+           s[2] < kSl3Clamp;
+}
+
+// The projection of Eq. vol_pre with the clamp; returns the regime word.
+__device__ __forceinline__ uint32_t proj_sl3(const float* sg, float* ds) {
+    if (__builtin_expect(proj_sl3_plus(sg, ds), 0)) return proj_sl3_rare(sg, ds);
+    return 0u;
+}
+
+// Per-element regime counters (64-bit): [0] clamped, [1] inverted (sigma_3 <= 0),
+// [2] det F >= 2, [3] a mixed-branch point taken, [4] no + branch root.
+__device__ __forceinline__ void count_regime(unsigned long long* regime, uint32_t bits, bool inverted) {
+    if (bits & kSl3Clamped) atomicAdd(&regime[0], 1ull);
+    if (inverted) atomicAdd(&regime[1], 1ull);
+    if (bits & kSl3DetGe2) atomicAdd(&regime[2], 1ull);
+    if (bits & kSl3Squash) atomicAdd(&regime[3], 1ull);
+    if (bits & kSl3NoPlus) atomicAdd(&regime[4], 1ull);
 }
 
 // Local step, one thread per tet, 256 tets per workgroup.  Each tet reads
@@ -261,8 +471,44 @@ __device__ __forceinline__ void proj_sl3(const float* sg, float* ds, bool& out_o
 // a fixed order and stores one partial per (workgroup, vertex), coalesced.
 constexpr int LBLK = 256;
 
+// One tet's 64-byte record (vertex ids, Dm^{-1} rows, weights), its corner
+// LDS positions, the gathered displacements, F = I + Du Dm^{-1}, and the signed
+// SVD F = U diag(sg) W^T.
+struct TetSvd {
+    float G[9], ws, wv;
+    uint2 lp;
+    float U[9], W[9], sg[3];
+};
+
+__device__ __forceinline__ void tet_svd(const float4* __restrict__ trec, const uint2* __restrict__ lpos,
+                                        const float4* __restrict__ u, int32_t e, TetSvd& t) {
+    const float4 r0 = trec[4 * (size_t)e], r1 = trec[4 * (size_t)e + 1], r2 = trec[4 * (size_t)e + 2],
+                 r3 = trec[4 * (size_t)e + 3];
+    t.lp = lpos[e];
+    const int32_t i0 = __float_as_int(r0.x), i1 = __float_as_int(r0.y), i2 = __float_as_int(r0.z),
+                  i3 = __float_as_int(r0.w);
+    const float4 u0 = u[i0], u1 = u[i1], u2 = u[i2], u3 = u[i3];
+    const float G[9] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) t.G[k] = G[k];
+    t.ws = r3.y;
+    t.wv = r3.z;
+    // displacement differences, columns k = corners 1..3
+    const float Du[3][3] = {{u1.x - u0.x, u2.x - u0.x, u3.x - u0.x},
+                            {u1.y - u0.y, u2.y - u0.y, u3.y - u0.y},
+                            {u1.z - u0.z, u2.z - u0.z, u3.z - u0.z}};
+    float F[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            F[r * 3 + j] = (r == j ? 1.0f : 0.0f) + Du[r][0] * G[0 * 3 + j] + Du[r][1] * G[1 * 3 + j] +
+                           Du[r][2] * G[2 * 3 + j];
+    svd3(F, t.U, t.sg, t.W);
+}
+
 template <bool DBG>
-__global__ __launch_bounds__(LBLK) void k_local(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+__global__ __launch_bounds__(LBLK, 8) void k_local(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
                                                 const int32_t* __restrict__ active) {
     __shared__ float LF[3][4 * LBLK];
     Slot sl;
@@ -275,33 +521,26 @@ __global__ __launch_bounds__(LBLK) void k_local(const DevMesh* __restrict__ GM, 
     const int32_t* __restrict__ blk_part = M.blk_part;
     const int32_t* __restrict__ part_pack = M.part_pack;
     float4* __restrict__ part = M.part;
-    uint32_t* flags = M.flags;
     float *dT = M.dbg_T, *dsig = M.dbg_sig, *ds_out = M.dbg_s;
     const int32_t e = sl.lb * LBLK + threadIdx.x;
     if (e < nt) {
-        const float4 r0 = trec[4 * (size_t)e], r1 = trec[4 * (size_t)e + 1], r2 = trec[4 * (size_t)e + 2],
-                     r3 = trec[4 * (size_t)e + 3];
-        const uint2 lp = lpos[e];
-        const int32_t i0 = __float_as_int(r0.x), i1 = __float_as_int(r0.y), i2 = __float_as_int(r0.z),
-                      i3 = __float_as_int(r0.w);
-        const float4 u0 = u[i0], u1 = u[i1], u2 = u[i2], u3 = u[i3];
-        const float G[9] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
-        const float ws = r3.y, wv = r3.z;
-        // displacement differences, columns k = corners 1..3
-        const float Du[3][3] = {{u1.x - u0.x, u2.x - u0.x, u3.x - u0.x},
-                                {u1.y - u0.y, u2.y - u0.y, u3.y - u0.y},
-                                {u1.z - u0.z, u2.z - u0.z, u3.z - u0.z}};
-        float F[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                F[r * 3 + j] = (r == j ? 1.0f : 0.0f) + Du[r][0] * G[0 * 3 + j] + Du[r][1] * G[1 * 3 + j] +
-                               Du[r][2] * G[2 * 3 + j];
-        float U[9], W[9], sg[3], dsv[3];
-        svd3(F, U, sg, W);
-        bool oor = false;
-        proj_sl3(sg, dsv, oor);
+        TetSvd t;
+        tet_svd(trec, lpos, u, e, t);
+        float dsv[3];
+        uint32_t regime = 0;
+        if (__builtin_expect(proj_sl3_plus(t.sg, dsv), 0)) {
+            const float sg1[3] = {t.sg[0], t.sg[1], t.sg[2]};
+            regime = proj_sl3_rare(sg1, dsv);
+            // the record and the singular vectors are formed again (the same
+            // values), so that only sigma stays live across the bracketing
+            // and the kernel keeps the registers of the plain one
+            __asm__ volatile("" ::: "memory");
+            tet_svd(trec, lpos, u, e, t);
+        }
+        const float* G = t.G;
+        const float *U = t.U, *W = t.W, *sg = t.sg;
+        const float ws = t.ws, wv = t.wv;
+        const uint2 lp = t.lp;
         // residual stress T = U diag(ws (1 - sigma) + wv (s - sigma)) W^T = P - (ws + wv) F
         const float d0 = ws * (1.0f - sg[0]) + wv * dsv[0];
         const float d1 = ws * (1.0f - sg[1]) + wv * dsv[1];
@@ -336,10 +575,7 @@ __global__ __launch_bounds__(LBLK) void k_local(const DevMesh* __restrict__ GM, 
             LF[2][pos[0]] = -s2;
         }
         const bool inv = sg[2] <= 0.0f;
-        if (__builtin_expect(oor || inv, 0)) {
-            if (oor) atomicAdd(&flags[1], 1u);
-            if (inv) atomicAdd(&flags[2], 1u);
-        }
+        if (__builtin_expect(regime != 0u || inv, 0)) count_regime(M.regime, regime, inv);
         if (DBG) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) dT[(size_t)e * 9 + k] = T[k];
@@ -521,8 +757,8 @@ __global__ __launch_bounds__(LBLK) void k_adj_local(const DevMesh* __restrict__ 
         tet_F(lam, nullptr, id, G, false, Gl);
         float U[9], W[9], sg[3], dsv[3];
         svd3(F, U, sg, W);
-        bool oor = false;
-        proj_sl3(sg, dsv, oor);
+        const uint32_t regime = proj_sl3(sg, dsv);
+        const uint32_t frozen = regime >> kSl3FrozenShift;
         float s[3], q[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -557,12 +793,14 @@ __global__ __launch_bounds__(LBLK) void k_adj_local(const DevMesh* __restrict__ 
             float sq = 0.0f, sis = 0.0f;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
+                if (frozen >> i & 1u) continue;
                 sq += Mm[i * 4] * frcp(q[i]);
                 sis += frcp(q[i] * s[i]);
             }
             const float dmu = -sq * frcp(sis);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) Q[i * 4] = wv * (dmu + s[i] * Mm[i * 4]) * frcp(q[i]);
+            for (int i = 0; i < 3; ++i)
+                Q[i * 4] = (frozen >> i & 1u) ? 0.0f : wv * (dmu + s[i] * Mm[i * 4]) * frcp(q[i]);
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -573,7 +811,12 @@ __global__ __launch_bounds__(LBLK) void k_adj_local(const DevMesh* __restrict__ 
                 const float b = 0.5f * (Mm[i * 3 + j] - Mm[j * 3 + i]);
                 const float isum = frcp(sg[i] + sg[j]);
                 const float dR = 2.0f * b * isum;
-                const float dV = a * (0.5f + 0.5f * (sg[i] + sg[j]) * frcp(q[i] + q[j])) + b * (s[i] + s[j]) * isum;
+                // (s_i - s_j) / (sigma_i - sigma_j): at a common mu without the
+                // difference; across a frozen axis (mu differs) as written
+                float dd;
+                if (!((frozen >> i | frozen >> j) & 1u)) dd = 0.5f + 0.5f * (sg[i] + sg[j]) * frcp(q[i] + q[j]);
+                else dd = (sg[i] != sg[j]) ? (s[i] - s[j]) / (sg[i] - sg[j]) : 0.0f;
+                const float dV = a * dd + b * (s[i] + s[j]) * isum;
                 Q[i * 3 + j] = ws * dR + wv * dV;
             }
         // dP = U Q W^T
@@ -611,7 +854,8 @@ __global__ __launch_bounds__(LBLK) void k_adj_local(const DevMesh* __restrict__ 
             LF[1][pos[0]] = -s1;
             LF[2][pos[0]] = -s2;
         }
-        if (__builtin_expect(oor, 0)) atomicAdd(&M.flags[1], 1u);
+        const bool inv = sg[2] <= 0.0f;
+        if (__builtin_expect(regime != 0u || inv, 0)) count_regime(M.regime, regime, inv);
     }
     __syncthreads();
     const int32_t p0 = M.blk_part[blockIdx.x], np = M.blk_part[blockIdx.x + 1] - p0;

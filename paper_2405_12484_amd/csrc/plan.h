@@ -110,12 +110,24 @@ struct Plan {
     double seconds = 0;
 };
 
+// Plan options.  thin_separators: separator vertices whose neighbours lie
+// under one child only are eliminated inside that child's subtree.
+// merge_max_cols: the separators at odd depths join their parent's when the
+// merged block has at most this many columns (0: no merging).  Tuning of the
+// interface programs: a phase whose mean task length is at least lanes32_min
+// (lanes64_min) runs 32 (64) lanes per task, else 16.
+struct PlanOptions {
+    bool thin_separators = false;
+    int64_t merge_max_cols = 3000;
+    int64_t lanes32_min = 96, lanes64_min = 384;
+};
+
 // Build a plan; returns 0 or a negative VH_E* code with msg set.
 int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                const double* gamma_s, const double* gamma_v, const double* mass,
                const uint8_t* pinned, const double* gravity, double dt, int32_t pd_iters,
                int32_t n_subdomains, int32_t refine_steps, int32_t leaf_max,
-               int32_t chunk_floats, Plan& plan, std::string& msg);
+               int32_t chunk_floats, const PlanOptions& opt, Plan& plan, std::string& msg);
 
 // Rest-shape checks used at mesh creation: every tet has positive volume.
 int check_mesh(const double* X, int32_t nv, const int32_t* tets, int32_t nt, std::string& msg);

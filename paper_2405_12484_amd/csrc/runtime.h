@@ -56,6 +56,7 @@ struct Server;
 
 struct vh_ctx {
     int device = 0;
+    vh_config cfg{1, 96, 384, 0, 3000};
     size_t budget = 0;
     size_t in_use = 0, peak = 0;
     std::vector<vh_mesh*> meshes;
@@ -93,8 +94,8 @@ struct vh_mesh {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<size_t, int>> ev_pairs;   // start event index, class
-    // one frame captured as a HIP graph (replayed per frame on the caller's stream)
-    bool use_graph = true;
+    // one frame captured as a HIP graph (replayed per frame on the caller's
+    // stream while the context's use_graphs is set)
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec = nullptr;
     // adjoint: checkpoints of the last vh_mesh_adjoint_forward (device, owned)
@@ -134,8 +135,16 @@ int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSe
                      bool check_budget);
 void free_launch_set(vh_ctx* ctx, LaunchSet& L);
 
-// One frame over the launch set on s; prof (may be null) receives per-class timing.
-int frame_direct(vh_mesh* prof, const LaunchSet& L, hipStream_t s);
+// A launch of L's tables with the garment records at G instead (G null: L's own).
+inline vh::LaunchRef with_record(const vh::LaunchRef& r, const vh::DevMesh* G) {
+    vh::LaunchRef o = r;
+    if (G) o.G = G;
+    return o;
+}
+
+// One frame over the launch set on s; prof (may be null) receives per-class
+// timing; G (may be null) replaces the launch set's device records.
+int frame_direct(vh_mesh* prof, const LaunchSet& L, hipStream_t s, const vh::DevMesh* G = nullptr);
 // Capture frame_direct(L) on `cap` into an executable graph.
 int capture_frame(const LaunchSet& L, hipStream_t* cap, hipGraphExec_t* out);
 // the mesh's own frame graph, captured on first use
@@ -147,9 +156,10 @@ int get_user(vh_mesh* m, const double* dev_int, double* host, int32_t rows, hipS
 int put_user(vh_mesh* m, const double* host, double* dev_int, bool positions, hipStream_t s);
 
 // d = K^{-1} r on the mesh's device vectors (r -> delta; apply: x += d)
-int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta);
+int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta,
+          const vh::DevMesh* G = nullptr);
 // one local/global iteration (local step, residual, solve with refinement, x += d)
-int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s);
+int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s, const vh::DevMesh* G = nullptr);
 // VH_ESTATE unless the mesh is prefactored; check_solo: and not driven by a
 // server; check_quiet: and no server frames of it pending
 int check_ready(vh_mesh* m);

@@ -126,7 +126,7 @@ int admit(vh_ctx* ctx, Server& S) {
     for (int32_t g : S.pol.to_admit(ctx->in_use, ctx->budget)) {
         vh_mesh* m = S.mesh[g];
         VH_TRY(upload_device(m));
-        if (m->use_graph) VH_TRY(ensure_graph(m));
+        if (m->ctx->cfg.use_graphs) VH_TRY(ensure_graph(m));
         S.pol.admit(g);
         S.dirty = true;
     }
@@ -170,7 +170,7 @@ int take_event(Server& S, hipEvent_t* e) {
 int launch(Server& S, const std::vector<int32_t>& ids) {
     if (S.mode == VH_SERVE_SEQUENTIAL || ids.size() == 1) {
         vh_mesh* m = S.mesh[ids[0]];
-        if (m->use_graph) {
+        if (m->ctx->cfg.use_graphs) {
             VH_TRY(ensure_graph(m));
             VH_HIP(hipGraphLaunch(m->gexec, S.s));
         } else {
@@ -271,8 +271,7 @@ int vh_serve_open(vh_ctx* ctx, int32_t mode, int32_t max_in_flight, int32_t max_
     S->mode = mode;
     S->depth = max_in_flight;
     S->max_batch = max_batch;
-    const char* ng = std::getenv("VHPD_NO_GRAPH");
-    S->use_graph = !(ng && ng[0] == '1');
+    S->use_graph = ctx->cfg.use_graphs != 0;
     ctx->srv = S;
     auto bail = [&](hipError_t e, const char* what) {
         server_destroy(ctx);
@@ -344,7 +343,7 @@ int vh_serve_add(vh_ctx* ctx, vh_mesh* m, int32_t n_subdomains, int32_t refine_s
     S->pos.push_back(-1);
     m->srv_id = id;
     if (m->factored) {
-        if (m->use_graph) VH_TRY(ensure_graph(m));
+        if (m->ctx->cfg.use_graphs) VH_TRY(ensure_graph(m));
         S->pol.admit(id);
         S->dirty = true;
     }

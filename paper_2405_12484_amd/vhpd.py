@@ -54,16 +54,38 @@ class ServeStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Config(ctypes.Structure):
+    _fields_ = [("use_graphs", ctypes.c_int32), ("iface_lanes32_min", ctypes.c_int32),
+                ("iface_lanes64_min", ctypes.c_int32), ("thin_separators", ctypes.c_int32),
+                ("iface_merge_max_cols", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RegimeCounts(ctypes.Structure):
+    _fields_ = [("clamped", ctypes.c_uint64), ("inverted", ctypes.c_uint64), ("det_ge2", ctypes.c_uint64),
+                ("squash", ctypes.c_uint64), ("no_plus_root", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+VH_PRECISION_MIXED = 0
+
 SIGNATURES = {
     "vh_last_error": (ctypes.c_char_p, []),
     "vh_ctx_create": (ctypes.c_int, [_P(_vp), ctypes.c_int, _sz]),
     "vh_ctx_destroy": (ctypes.c_int, [_vp]),
     "vh_ctx_hbm_in_use": (ctypes.c_int, [_vp, _P(_sz)]),
     "vh_ctx_set_hbm_budget": (ctypes.c_int, [_vp, _sz]),
+    "vh_ctx_get_config": (ctypes.c_int, [_vp, _P(Config)]),
+    "vh_ctx_set_config": (ctypes.c_int, [_vp, _P(Config)]),
     "vh_mesh_create": (ctypes.c_int, [_vp, _P(_vp), _vp, _i32, _vp, _i32]),
     "vh_mesh_destroy": (ctypes.c_int, [_vp]),
     "vh_mesh_set_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32]),
-    "vh_mesh_prefactor": (ctypes.c_int, [_vp, _i32, _i32]),
+    "vh_mesh_prefactor": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
+    "vh_mesh_regime_counts": (ctypes.c_int, [_vp, _P(RegimeCounts), _i32, _vp]),
     "vh_mesh_step": (ctypes.c_int, [_vp, _i32, _vp]),
     "vh_mesh_read_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_mesh_write_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -161,6 +183,21 @@ class Context:
     def set_hbm_budget(self, nbytes: int):
         _check(_lib.vh_ctx_set_hbm_budget(self.h, int(nbytes)))
 
+    def config(self) -> dict:
+        c = Config()
+        _check(_lib.vh_ctx_get_config(self.h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_config(self, **kw):
+        """Change some of the fields of vh_config (see include/vhpd.h)."""
+        c = Config()
+        _check(_lib.vh_ctx_get_config(self.h, ctypes.byref(c)))
+        for k, v in kw.items():
+            if k not in dict(Config._fields_):
+                raise KeyError(k)
+            setattr(c, k, int(v))
+        _check(_lib.vh_ctx_set_config(self.h, ctypes.byref(c)))
+
     def close(self):
         """Destroy the context and every mesh still open on it."""
         if self.h:
@@ -205,8 +242,14 @@ class Mesh:
         _check(_lib.vh_mesh_set_params(self.h, _ptr(gs), _ptr(gv), _ptr(m), _ptr(pin), _ptr(g), float(dt),
                                        int(pd_iters)))
 
-    def prefactor(self, n_subdomains: int, refine_steps: int = 0):
-        _check(_lib.vh_mesh_prefactor(self.h, int(n_subdomains), int(refine_steps)))
+    def prefactor(self, n_subdomains: int, refine_steps: int = 0, precision_mode: int = VH_PRECISION_MIXED):
+        _check(_lib.vh_mesh_prefactor(self.h, int(n_subdomains), int(refine_steps), int(precision_mode)))
+
+    def regime_counts(self, reset: bool = False, stream=None) -> dict:
+        """Projection regime counters of the local step since the last reset."""
+        c = RegimeCounts()
+        _check(_lib.vh_mesh_regime_counts(self.h, ctypes.byref(c), 1 if reset else 0, _stream_ptr(stream)))
+        return c.as_dict()
 
     def step(self, n_frames: int = 1, stream=None):
         _check(_lib.vh_mesh_step(self.h, int(n_frames), _stream_ptr(stream)))

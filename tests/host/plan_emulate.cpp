@@ -27,7 +27,7 @@ void* vhp_build(const double* X, int nv, const int* tets, int nt, const double* 
                 int D, int refine, int leaf_max, int* rc, char* msg, int msglen) {
     Plan* P = new Plan();
     std::string m;
-    *rc = build_plan(X, nv, tets, nt, gs, gv, mass, pinned, g, dt, iters, D, refine, leaf_max, 12288, *P, m);
+    *rc = build_plan(X, nv, tets, nt, gs, gv, mass, pinned, g, dt, iters, D, refine, leaf_max, 12288, PlanOptions(), *P, m);
     std::snprintf(msg, msglen, "%s", m.c_str());
     if (*rc != 0) {
         delete P;

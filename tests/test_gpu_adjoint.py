@@ -87,6 +87,20 @@ def test_autograd_trajectory(vh):
     err = np.linalg.norm(gs.grad.numpy() - g_ref) / np.linalg.norm(g_ref)
     say(f"[adjoint] autograd box: rel L2 vs oracle adjoint {err:.2e}")
     assert err < 2e-3
+    # two outputs before their backwards: each gradient belongs to its own gamma_s
+    gs_b = torch.tensor(p.gamma_s * 1.5, dtype=torch.float64, requires_grad=True)
+    gs_a = torch.tensor(p.gamma_s, dtype=torch.float64, requires_grad=True)
+    xa = traj(gs_a)
+    xb = traj(gs_b)
+    la = 0.5 * (((xa - torch.tensor(xt)) ** 2).sum(dim=1) * free).sum()
+    lb = 0.5 * (((xb - torch.tensor(xt)) ** 2).sum(dim=1) * free).sum()
+    la.backward()
+    assert np.allclose(gs_a.grad.numpy(), gs.grad.numpy(), rtol=1e-10, atol=0)
+    lb.backward()
+    _, g_ref_b = loss_and_grad(p, p.gamma_s * 1.5, xt, frames)
+    err_b = np.linalg.norm(gs_b.grad.numpy() - g_ref_b) / np.linalg.norm(g_ref_b)
+    say(f"[adjoint] autograd box, second output at 1.5 gamma_s: rel L2 vs oracle adjoint {err_b:.2e}")
+    assert err_b < 2e-3
     with pytest.raises(vh.VHError):
         m = vh.Mesh(ctx, p.X, p.tets)
         m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)

@@ -52,16 +52,48 @@ def test_local_step_matches_oracle(vh, ctx, name):
     m.close()
 
 
-def _shared_regime(S, s_ref):
-    """Elements where the oracle's projection is the + branch root (Eq. vol_pre
-    has one: always when det F <= 1, else when h(-sigma_min^2 / 4) <= 0) and
-    the device keeps its Newton result (det F < 2, no clamp)."""
-    det = S.prod(axis=1)
-    smin = np.abs(S).min(axis=1)
-    arg = np.maximum(S * S - smin[:, None] ** 2, 0.0)
-    h_lo = np.log(np.maximum((S + np.sqrt(arg)) / 2, 1e-300)).sum(axis=1)
-    plus_root = (det <= 1.0) | (h_lo <= 0.0)
-    return plus_root & (det < 2.0) & (s_ref.min(axis=1) > 0.011)
+def _stress_scale(S, s):
+    """How much FP32 rounding of F moves the residual stress U diag(d) W^T per
+    unit weight: the rotation's sensitivity grows like 2 / (sigma_i + sigma_j),
+    and the volume projection's like the divided difference
+    |s_i - s_j| / |sigma_i - sigma_j| (bounded on the + branch, large where a
+    clamp or a minus-root axis separates two nearly equal singular values)."""
+    big = np.maximum(1.0, np.abs(S).max(axis=1))
+    rot = np.ones(len(S))
+    dd = np.ones(len(S))
+    for i, j in ((0, 1), (0, 2), (1, 2)):
+        rot = np.maximum(rot, 2.0 / np.maximum(np.abs(S[:, i] + S[:, j]), 1e-30))
+        dd = np.maximum(dd, np.abs(s[:, i] - s[:, j]) / np.maximum(np.abs(S[:, i] - S[:, j]), 1e-30))
+    return big * rot * dd
+
+
+def _check_projection(S, s_dev, tol=3e-6):
+    """The device's projected singular values s_dev (Eq. vol_pre with the clamp
+    of Sec. 7.1) against the FP64 oracle's projection of the same sigma S.
+
+    The distance |s - sigma| of the nearest point is unique; the point is not
+    where two stationary points lie at (nearly) equal distance, as for
+    sigma = (c, c, c) with c > 2, whose mixed-branch candidates are each other's
+    images under an axis swap.  So: the distance must agree everywhere; the
+    point must agree where the device's point is not an equally near
+    alternative; and every device point must be feasible (prod s = 1,
+    s >= 0.01) and stationary (s_i (s_i - sigma_i) equal over the axes the
+    clamp left free).  Returns the oracle's regime counts and the mask of
+    elements whose point was compared directly."""
+    s_ref, info = oracle.proj_sl3(S)
+    big = np.maximum(1.0, np.abs(S).max(axis=1))
+    d_dev = np.linalg.norm(s_dev - S, axis=1)
+    d_ref = np.linalg.norm(s_ref - S, axis=1)
+    assert (np.abs(d_dev - d_ref) / big).max() < tol, (np.abs(d_dev - d_ref) / big).max()
+    assert np.abs(np.log(s_dev).sum(axis=1)).max() < 5 * tol
+    assert s_dev.min() >= 0.01 * (1 - 1e-6)
+    free = s_dev > 0.01 * (1 + 1e-5)
+    mu = s_dev * (s_dev - S)
+    for e in np.nonzero(free.sum(axis=1) >= 2)[0]:
+        m = mu[e, free[e]]
+        assert np.ptp(m) <= 20 * tol * big[e] ** 2, (e, S[e], s_dev[e], m)
+    same = (np.abs(s_dev - s_ref) / big[:, None]).max(axis=1) < tol
+    return info, same
 
 
 @pytest.mark.parametrize("amp", [0.01, 0.02])
@@ -72,26 +104,107 @@ def test_local_step_large_strain_and_inverted(vh, ctx, amp):
     m = make_mesh(vh, ctx, p)
     sim = oracle.OracleSim.from_problem(p)
     x = deformed(p, amp=amp, seed=1)
+    m.regime_counts(reset=True)
     T, sig, s = m.debug_local_step(x)
+    counts = m.regime_counts()
     loc = oracle.local_step(x, sim.tets, sim.grads, sim.w_s, sim.w_v)
     S = loc["sigma"]
-    keep = _shared_regime(S, loc["s"])
+    big = np.maximum(1.0, np.abs(S).max(axis=1))[:, None]
+    assert (np.abs(sig - S) / big).max() < 4e-6
+    info, same = _check_projection(sig, s)
     n_inv = int((S[:, 2] < 0).sum())
-    say(f"[local] amp={amp}: {keep.sum()} of {len(S)} elements compared, {n_inv} inverted")
-    assert keep.sum() > 0.9 * len(S)
+    say(f"[local] amp={amp}: {same.sum()} of {len(S)} points compared directly, {n_inv} inverted, "
+        f"oracle {info}, device {counts}")
+    assert same.mean() > 0.99
+    for k in ("clamped", "inverted", "det_ge2", "squash", "no_plus_root"):
+        assert abs(counts[k] - info[k]) <= 1, (k, counts, info)
     if amp >= 0.02:
-        assert (keep & (S[:, 2] < 0)).sum() > 0      # inverted elements are in the comparison
+        assert counts["inverted"] > 0 and counts["det_ge2"] > 0
     Tref = loc["P"] - (sim.w_s + sim.w_v)[:, None, None] * loc["F"]
     w = (sim.w_s + sim.w_v)[:, None, None]
     err = (np.abs(T - Tref) / w).max(axis=(1, 2))
-    # the rotation's sensitivity to rounding of F grows like 2 / (sigma_i + sigma_j)
-    pair = np.minimum.reduce([S[:, 0] + S[:, 1], S[:, 0] + S[:, 2], S[:, 1] + S[:, 2]])
-    scale = np.maximum(1.0, np.abs(S).max(axis=1)) * np.maximum(1.0, 2.0 / np.abs(pair))
+    scale = _stress_scale(S, s)
+    keep = same & np.all(np.abs(s - loc["s"]) / big < 4e-6, axis=1)
     assert (err[keep] / scale[keep]).max() < 2e-5, (err[keep] / scale[keep]).max()
-    big = np.maximum(1.0, np.abs(S).max(axis=1))[:, None]
-    assert (np.abs(sig - S) / big)[keep].max() < 4e-6
-    assert (np.abs(s - loc["s"]) / big)[keep].max() < 4e-6
     m.close()
+
+
+# extreme affine deformations of a small box about its centre (plus seeded
+# noise): two axes stretched 12x and the third flattened (every element
+# clamped, then its pair re-solved on s1 s2 = 100), the same with the third
+# axis inverted, a stretch about x2 (det F = 6.8: no + branch root, mixed
+# points nearest) and (6, 3, 0.5) (det F = 9)
+REGIME_CASES = {"flat": ((12.0, 12.0, 0.001), 2e-5), "flat_inverted": ((12.0, 12.0, -0.002), 2e-5),
+                "stretch2": ((2.0, 1.9, 1.8), 1e-3), "mixed": ((6.0, 3.0, 0.5), 1e-3)}
+
+
+@pytest.mark.parametrize("case", list(REGIME_CASES))
+def test_local_step_projection_regimes(vh, ctx, case):
+    """Clamped, inverted-and-clamped and det F >= 2 elements: the projection of
+    Eq. vol_pre with Sec. 7.1's clamp and freeze, against the FP64 oracle, and
+    the regime counters against the oracle's counts."""
+    diag, noise = REGIME_CASES[case]
+    say(f"[local regimes] {case}")
+    p = synth.make_box_problem(seed=11, nx=4, ny=4, nz=2, n_subdomains=2, name="box_small")
+    m = make_mesh(vh, ctx, p)
+    sim = oracle.OracleSim.from_problem(p)
+    c = p.X.mean(axis=0)
+    rng = np.random.default_rng(5)
+    x = (p.X - c) * np.asarray(diag) + c + noise * 0.01 * rng.standard_normal(p.X.shape)
+    x[p.pinned.astype(bool)] = p.X[p.pinned.astype(bool)]      # the library keeps pinned rows at rest
+    m.regime_counts(reset=True)
+    T, sig, s = m.debug_local_step(x)
+    counts = m.regime_counts()
+    loc = oracle.local_step(x, sim.tets, sim.grads, sim.w_s, sim.w_v)
+    S = loc["sigma"]
+    big = np.maximum(1.0, np.abs(S).max(axis=1))[:, None]
+    assert (np.abs(sig - S) / big).max() < 4e-6
+    info, same = _check_projection(sig, s)
+    say(f"[local regimes] {case}: {same.sum()} of {len(S)} points compared directly; oracle {loc['info']}, "
+        f"device {counts}")
+    for k in ("clamped", "inverted", "det_ge2", "squash", "no_plus_root"):
+        assert abs(counts[k] - info[k]) <= 1, (k, counts, info)
+    # the elements of the pinned row's layer are distorted differently
+    if case.startswith("flat"):
+        assert counts["clamped"] >= 0.8 * p.nt
+    else:
+        assert counts["det_ge2"] >= 0.7 * p.nt and counts["squash"] >= 0.7 * p.nt
+    assert same.mean() >= 0.95
+    # residual stress where the device's point is the oracle's
+    keep = same & np.all(np.abs(s - loc["s"]) / big < 4e-6, axis=1)
+    assert keep.sum() > 0
+    Tref = loc["P"] - (sim.w_s + sim.w_v)[:, None, None] * loc["F"]
+    w = (sim.w_s + sim.w_v)[:, None, None]
+    err = (np.abs(T - Tref) / w).max(axis=(1, 2))
+    scale = _stress_scale(S, s)
+    assert (err[keep] / scale[keep]).max() < 2e-5, (err[keep] / scale[keep]).max()
+    m.close()
+
+
+def test_step_from_clamped_state_matches_oracle(vh, ctx):
+    """One frame of the PD step (10 iterations) from a flattened state in which
+    every element starts clamped: positions against the FP64 oracle, and the
+    clamped evaluations counted by both."""
+    say("[step regimes] flattened start")
+    p = synth.make_box_problem(seed=12, nx=3, ny=3, nz=2, n_subdomains=2, name="box_tiny")
+    m = make_mesh(vh, ctx, p)
+    sim = oracle.OracleSim.from_problem(p)
+    c = p.X.mean(axis=0)
+    x0 = (p.X - c) * np.array([12.0, 12.0, 0.001]) + c
+    x0[p.pinned.astype(bool)] = p.X[p.pinned.astype(bool)]
+    v0 = np.zeros_like(x0)
+    m.write_state(x0, v0)
+    m.regime_counts(reset=True)
+    m.step(1)
+    xg, _ = m.read_state()
+    counts = m.regime_counts()
+    xo, _ = sim.step(x0, v0)
+    info = sim.last_info
+    e = rel_l2(xg, xo)
+    say(f"[step regimes] rel L2 {e:.3e}, device {counts}, oracle {info}")
+    assert counts["clamped"] > 0
+    assert abs(counts["clamped"] - info["clamped"]) <= 2
+    assert e <= 1e-5
 
 
 def test_local_step_rigid_rotation_zero_stress(vh, ctx):
@@ -288,6 +401,17 @@ def test_errors_are_reported(vh, ctx):
     with pytest.raises(vh.VHError) as ei:
         m.read_state()
     assert ei.value.code == vh.VH_ENUMERIC
+    with pytest.raises(vh.VHError) as ei:
+        m.prefactor(4, 0, 1)                              # no such precision mode
+    assert ei.value.code == vh.VH_EINVAL
+    # M / dt^2 overflows: a pivot that is not a positive finite number
+    m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, 1e-160, 10)
+    with pytest.raises(vh.VHError) as ei:
+        m.prefactor(4)
+    assert ei.value.code == vh.VH_ENOTSPD
+    with pytest.raises(vh.VHError) as ei:
+        ctx.set_config(use_graphs=2)
+    assert ei.value.code == vh.VH_EINVAL
     m.close()
 
 
@@ -383,15 +507,13 @@ def test_budget_refuses(vh):
 def test_graph_replay_equals_direct_launches(vh, ctx):
     """The frame replayed as a HIP graph is bitwise equal to direct launches,
     on every replay."""
-    import os
     say("[graph vs direct]")
     p = synth.problem_by_name("shell_small")
     a = make_mesh(vh, ctx, p)
-    os.environ["VHPD_NO_GRAPH"] = "1"
-    try:
-        b = make_mesh(vh, ctx, p)
-    finally:
-        del os.environ["VHPD_NO_GRAPH"]
+    ctx_direct = vh.Context(0)
+    ctx_direct.set_config(use_graphs=0)
+    assert ctx_direct.config()["use_graphs"] == 0 and ctx.config()["use_graphs"] == 1
+    b = make_mesh(vh, ctx_direct, p)
     for _ in range(4):
         a.step(1)
         b.step(1)

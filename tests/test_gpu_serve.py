@@ -131,21 +131,19 @@ def test_mix_is_bitwise_alone(vh, probs, alone, in_flight, seed):
     assert st["mean_batch"] > 1.0            # frames of different garments shared launches
 
 
-# interface lane-group thresholds per garment ("g32,g64" mean task lengths):
-# the default, 32 lanes everywhere, 64 lanes everywhere
-LANE_GROUPS = {0: None, 1: "1,100000000", 2: "1,1"}
+# interface lane-group thresholds per garment (mean task lengths from which
+# 32 and 64 lanes are used): the default, 32 lanes everywhere, 64 everywhere
+LANE_GROUPS = {0: None, 1: (1, 100000000), 2: (1, 1)}
 
 
-def _add_with_groups(srv, m, p, spec):
-    old = os.environ.pop("VHPD_IFACE_G", None)
+def _add_with_groups(ctx, srv, m, p, spec):
+    keep = ctx.config()
     if spec:
-        os.environ["VHPD_IFACE_G"] = spec
+        ctx.set_config(iface_lanes32_min=spec[0], iface_lanes64_min=spec[1])
     try:
         srv.add(m, p.n_subdomains)
     finally:
-        os.environ.pop("VHPD_IFACE_G", None)
-        if old is not None:
-            os.environ["VHPD_IFACE_G"] = old
+        ctx.set_config(**keep)
 
 
 def test_mix_of_lane_groups_is_bitwise_alone(vh, probs):
@@ -157,7 +155,7 @@ def test_mix_of_lane_groups_is_bitwise_alone(vh, probs):
         ms = {}
         for g in which:
             ms[g] = new_mesh(vh, ctx, probs[g])
-            _add_with_groups(srv, ms[g], probs[g], LANE_GROUPS[g])
+            _add_with_groups(ctx, srv, ms[g], probs[g], LANE_GROUPS[g])
         rng = np.random.default_rng(seed)
         queues = {g: list(REQUESTS[g]) for g in which}
         while any(queues.values()):

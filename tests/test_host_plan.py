@@ -114,3 +114,13 @@ def test_unpinned_mesh(hl):
     assert rc == 0, msg
     assert info["n_free"] == p.nv
     hl.vhp_free(h)
+
+
+def test_non_finite_pivot_is_not_spd(hl):
+    """dt = 1e-160 passes the argument checks (finite, positive) but M / dt^2
+    overflows to inf, so the factorization meets a pivot that is not a positive
+    finite number: the plan fails with VH_ENOTSPD (-3) and no plan is returned."""
+    import dataclasses
+    p = dataclasses.replace(synth.problem_by_name("box"), dt=1e-160)
+    h, rc, msg, info = _build(hl, p, 4)
+    assert h is None and rc == -3 and "pivot" in msg
