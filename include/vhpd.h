@@ -144,6 +144,23 @@ int vh_mesh_prefactor(vh_mesh* mesh, int32_t n_subdomains, int32_t refine_steps,
 /* Advance n_frames time steps on `stream` (asynchronous). */
 int vh_mesh_step(vh_mesh* mesh, int32_t n_frames, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * n_frames steps as vh_mesh_step, with the same kernels and the same results,
+ * but the work buffers of those kernels (force partials, residual, interior
+ * and interface work vectors, contribution slots, the launch record) taken
+ * from one fixed device array of VH_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds from its load until the process ends; the call allocates
+ * nothing (no hipMalloc, no graph instantiation: every launch is enqueued on
+ * `stream` directly).  The mesh (prefactored, not in a server) keeps its state
+ * and factors in its own memory.  VH_EINVAL when the mesh's work buffers need
+ * more than the array holds (about 14 MB for the 390,400-tet shell).  Every
+ * call on one GPU uses that GPU's one array: calls that overlap on a device
+ * (other streams or threads) race and must be serialised by the caller.  The
+ * array is cleared at the start of each call. */
+#define VH_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int vh_mesh_step_noalloc(vh_mesh* mesh, int32_t n_frames, void* stream);
+
 /* Copy the state to host x, v [nv][3] (float64); synchronises `stream` and
  * returns VH_ENUMERIC if the state holds a NaN/Inf. */
 int vh_mesh_read_state(vh_mesh* mesh, double* x, double* v, void* stream);

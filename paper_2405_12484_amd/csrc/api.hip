@@ -568,6 +568,10 @@ int vh_ctx_create(vh_ctx** out, int device, size_t hbm_budget_bytes) {
     vh_ctx* c = new vh_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;
+    if (int rc = noalloc_init(c); rc != VH_OK) {
+        delete c;
+        return rc;
+    }
     *out = c;
     return VH_OK;
 }

@@ -57,6 +57,7 @@ struct Server;
 struct vh_ctx {
     int device = 0;
     vh_config cfg{1, 96, 384, 0, 3000};
+    void* scratch = nullptr;        // device address of the step scratch array (vh_mesh_step_noalloc)
     size_t budget = 0;
     size_t in_use = 0, peak = 0;
     std::vector<vh_mesh*> meshes;
@@ -160,6 +161,10 @@ int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_d
           const vh::DevMesh* G = nullptr);
 // one local/global iteration (local step, residual, solve with refinement, x += d)
 int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s, const vh::DevMesh* G = nullptr);
+
+// ctx->scratch = the device address of the step scratch array on the current
+// device (hipGetSymbolAddress); called once per context, its device current
+int noalloc_init(vh_ctx* ctx);
 // VH_ESTATE unless the mesh is prefactored; check_solo: and not driven by a
 // server; check_quiet: and no server frames of it pending
 int check_ready(vh_mesh* m);

@@ -87,6 +87,7 @@ SIGNATURES = {
     "vh_mesh_prefactor": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
     "vh_mesh_regime_counts": (ctypes.c_int, [_vp, _P(RegimeCounts), _i32, _vp]),
     "vh_mesh_step": (ctypes.c_int, [_vp, _i32, _vp]),
+    "vh_mesh_step_noalloc": (ctypes.c_int, [_vp, _i32, _vp]),
     "vh_mesh_read_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_mesh_write_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_mesh_read_state_device": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -253,6 +254,11 @@ class Mesh:
 
     def step(self, n_frames: int = 1, stream=None):
         _check(_lib.vh_mesh_step(self.h, int(n_frames), _stream_ptr(stream)))
+
+    def step_noalloc(self, n_frames: int = 1, stream=None):
+        """The step with its work buffers in the library's fixed scratch array
+        (allocates no device memory)."""
+        _check(_lib.vh_mesh_step_noalloc(self.h, int(n_frames), _stream_ptr(stream)))
 
     def read_state(self, stream=None):
         x = np.empty((self.nv, 3))
