@@ -276,6 +276,37 @@ int vh_mesh_adjoint_forward(vh_mesh* mesh, const double* x0, const double* v0, i
 int vh_mesh_adjoint_backward(vh_mesh* mesh, const double* xbar, const double* vbar, double* grad_gamma_s,
                              void* stream);
 
+/* ---- Adjoint Gauss-Newton direction for gamma_s (Sec. 6.2, Eq. gn, Eq. agn).
+ *
+ * At an equilibrium x_eq of one implicit Euler step of the mesh (the point the
+ * PD iteration of Sec. 7.1 converges to: g(x, gamma) = M (x - y)/dt^2 +
+ * sum_e G_e^T (w_s (F - R) + w_v (F - V)) = 0, Eq. g), for the loss
+ * eps = 1/2 ||x - x_target||^2 over the free vertices:
+ *   grad = d eps / d gamma_s = -B^T lambda,  A lambda = x_eq - x_target
+ *       (Eq. adjoint_state, Eq. adjoint_state_solve; A = dg/dx, B = dg/dgamma_s),
+ *   direction d:  (B^T A^{-1} A^{-1} B + kappa I) d = -grad
+ *       (Eq. gn with the Levenberg-Marquardt kappa I; the same d solves the
+ *       saddle system of Eq. agn with kappa I in its gamma block).
+ * d is found by conjugate gradients in gamma space (at most max_outer
+ * iterations, until the residual is outer_tol times the first one); every
+ * product takes two solves with A by conjugate gradients preconditioned with
+ * the step's decomposed solve (FP64 vectors; the projection Jacobian and the
+ * interior solves in FP32 as in the step).  x_eq, x_target [nv][3] (user
+ * order; pinned rows ignored); grad_gamma_s, direction [nt] (user element
+ * order); stats (may be NULL).  kappa >= 0 (absolute; the GN matrix scales
+ * like (dx/dgamma)^2), 0 < outer_tol < 1, max_outer >= 0.  The mesh's state is
+ * not changed.  VH_ENUMERIC if A or the damped GN matrix is not positive
+ * definite along a search direction (e.g. at a strongly compressed state). */
+typedef struct vh_gn_stats {
+    int32_t outer_iters;           /* conjugate-gradient iterations in gamma space */
+    int64_t inner_iters;           /* preconditioned CG iterations of all solves with A */
+    double outer_rel_residual;     /* final |r| / |r_0| of the gamma-space iteration */
+    double inner_rel_residual_max; /* worst final relative residual of a solve with A */
+} vh_gn_stats;
+int vh_mesh_gn_direction(vh_mesh* mesh, const double* x_eq, const double* x_target, double kappa,
+                         int32_t max_outer, double outer_tol, double* grad_gamma_s, double* direction,
+                         vh_gn_stats* stats, void* stream);
+
 /* ---- Entry points that run one part of the step, for testing each kernel
  * against a reference.  All arrays are host arrays in user vertex order. ---- */
 

@@ -105,6 +105,16 @@ hipError_t launch_adj_local(const DevMesh* dev_mesh, int32_t nt, const double* x
 // xbar = sum of partials, ybar += M lambda / dt^2 (free rows)
 hipError_t launch_adj_gather(const DevMesh* dev_mesh, int32_t n_free, const double* lam, double* xbar,
                              double* ybar, hipStream_t s);
+// adjoint Gauss-Newton (one garment): partials of B d (gathered by
+// launch_adj_gather), out = K v - geo on the free rows, FP64 vector helpers
+// (partial dot products: gn_dot_blocks() values, summed by the caller)
+hipError_t launch_gn_bd(const DevMesh* dev_mesh, int32_t nt, const double* x, const double* dgam, hipStream_t s);
+hipError_t launch_gn_av(const DevMesh* dev_mesh, int32_t n_free, const double* v, const double* geo, double* out,
+                        hipStream_t s);
+hipError_t launch_gn_axpy(int32_t n, double a, const double* x, double* y, hipStream_t s);
+hipError_t launch_gn_xpby(int32_t n, const double* x, double b, double* y, hipStream_t s);
+int32_t gn_dot_blocks();
+hipError_t launch_gn_dot(int32_t n, const double* x, const double* y, double* part, hipStream_t s);
 // frame boundaries of the reverse sweep over n3 = 3 n_free values
 hipError_t launch_adj_frame(int32_t n3, double dt, bool begin, double* xbar, double* vbar, double* xk, double* xn,
                             double* ybar, hipStream_t s);

@@ -914,6 +914,128 @@ __global__ __launch_bounds__(BLK) void k_adj_frame(int32_t n3, double dt, int32_
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint Gauss-Newton (Sec. 6.2, Eq. gn, Eq. agn) at an equilibrium x of one
+// implicit Euler step, g(x, gamma) = M (x - y) / dt^2 + sum_e G_e^T (w_s (F - R)
+// + w_v (F - V)) = 0:
+//   B = dg/dgamma_s,  column e = V_e G_e^T (F_e - R_e)
+//   A = dg/dx = K - sum_e G_e^T J_P(F_e) G_e   (K the step matrix of Sec. 7.1)
+// B^T v and the J_P term of A v come from k_adj_local (with x^(k) = x^(k+1)
+// = x its gamma_s term is V_e <G_e v, R_e - F_e> = -(B^T v)_e); B d and K v
+// are the kernels below.
+// ---------------------------------------------------------------------------
+
+// per-workgroup partials of B d: the corner forces of d_e V_e (F_e - R_e)
+__global__ __launch_bounds__(LBLK) void k_gn_bd(const DevMesh* __restrict__ GM, const double* __restrict__ x,
+                                                const double* __restrict__ dgam) {
+    __shared__ float LF[3][4 * LBLK];
+    const DevMesh& M = GM[0];
+    const int32_t nt = M.nt;
+    const int32_t e = blockIdx.x * LBLK + threadIdx.x;
+    if (e < nt) {
+        const float4* rec = M.trec + 4 * (size_t)e;
+        const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
+        const int32_t id[4] = {__float_as_int(r0.x), __float_as_int(r0.y), __float_as_int(r0.z),
+                               __float_as_int(r0.w)};
+        const float G[9] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
+        const float c = (float)(dgam[e] * (double)r3.w);       // d_e V_e
+        float F[9], U[9], W[9], sg[3];
+        tet_F(x, M.X, id, G, true, F);
+        svd3(F, U, sg, W);
+        // d_e V_e (F - R) = U diag(d_e V_e (sigma - 1)) W^T
+        float Mm[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Mm[i * 3 + j] = c * (U[i * 3 + 0] * (sg[0] - 1.0f) * W[j * 3 + 0] +
+                                     U[i * 3 + 1] * (sg[1] - 1.0f) * W[j * 3 + 1] +
+                                     U[i * 3 + 2] * (sg[2] - 1.0f) * W[j * 3 + 2]);
+        const uint2 lp = M.lpos[e];
+        const uint32_t pos[4] = {lp.x & 0xFFFFu, lp.x >> 16, lp.y & 0xFFFFu, lp.y >> 16};
+        float s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int cc = 1; cc < 4; ++cc) {
+            const float fx = Mm[0] * G[(cc - 1) * 3 + 0] + Mm[1] * G[(cc - 1) * 3 + 1] + Mm[2] * G[(cc - 1) * 3 + 2];
+            const float fy = Mm[3] * G[(cc - 1) * 3 + 0] + Mm[4] * G[(cc - 1) * 3 + 1] + Mm[5] * G[(cc - 1) * 3 + 2];
+            const float fz = Mm[6] * G[(cc - 1) * 3 + 0] + Mm[7] * G[(cc - 1) * 3 + 1] + Mm[8] * G[(cc - 1) * 3 + 2];
+            if (pos[cc] != 0xFFFFu) {
+                LF[0][pos[cc]] = fx;
+                LF[1][pos[cc]] = fy;
+                LF[2][pos[cc]] = fz;
+            }
+            s0 += fx;
+            s1 += fy;
+            s2 += fz;
+        }
+        if (pos[0] != 0xFFFFu) {
+            LF[0][pos[0]] = -s0;
+            LF[1][pos[0]] = -s1;
+            LF[2][pos[0]] = -s2;
+        }
+    }
+    __syncthreads();
+    const int32_t p0 = M.blk_part[blockIdx.x], np = M.blk_part[blockIdx.x + 1] - p0;
+    for (int32_t k = threadIdx.x; k < np; k += LBLK) {
+        const int32_t pk = M.part_pack[p0 + k];
+        const int32_t st = pk >> 16, cnt = pk & 0xFFFF;
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        for (int32_t q2 = st; q2 < st + cnt; ++q2) {
+            fx += LF[0][q2];
+            fy += LF[1][q2];
+            fz += LF[2][q2];
+        }
+        M.part[p0 + k] = make_float4(fx, fy, fz, 0.0f);
+    }
+}
+
+// out = K v - geo on the free rows (FP64; K over the free-free block)
+__global__ __launch_bounds__(BLK) void k_gn_av(const DevMesh* __restrict__ GM, const double* __restrict__ v,
+                                               const double* __restrict__ geo, double* __restrict__ out) {
+    const DevMesh& M = GM[0];
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= M.n_free) return;
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int32_t k = M.K_ptr[i]; k < M.K_ptr[i + 1]; ++k) {
+        const double kv = M.K_val[k];
+        const double* vp = v + 3 * M.K_col[k];
+        s0 += kv * vp[0];
+        s1 += kv * vp[1];
+        s2 += kv * vp[2];
+    }
+    out[3 * i] = s0 - geo[3 * i];
+    out[3 * i + 1] = s1 - geo[3 * i + 1];
+    out[3 * i + 2] = s2 - geo[3 * i + 2];
+}
+
+// FP64 vector helpers of the Krylov loops: y += a x; y = x + b y; partial dot
+// products (one per workgroup, summed in a fixed order on the host)
+__global__ __launch_bounds__(BLK) void k_gn_axpy(int32_t n, double a, const double* __restrict__ x,
+                                                 double* __restrict__ y) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+
+__global__ __launch_bounds__(BLK) void k_gn_xpby(int32_t n, const double* __restrict__ x, double b,
+                                                 double* __restrict__ y) {
+    const int32_t i = blockIdx.x * BLK + threadIdx.x;
+    if (i < n) y[i] = x[i] + b * y[i];
+}
+
+__global__ __launch_bounds__(BLK) void k_gn_dot(int32_t n, const double* __restrict__ x,
+                                                const double* __restrict__ y, double* __restrict__ part) {
+    __shared__ double red[BLK];
+    double acc = 0.0;
+    for (int32_t i = blockIdx.x * BLK + threadIdx.x; i < n; i += gridDim.x * BLK) acc += x[i] * y[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int32_t w = BLK / 2; w > 0; w >>= 1) {
+        if ((int32_t)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
 // Decomposed solve
 // ---------------------------------------------------------------------------
 
@@ -1696,6 +1818,38 @@ hipError_t launch_adj_gather(const DevMesh* dev_mesh, int32_t n_free, const doub
                              double* ybar, hipStream_t s) {
     if (n_free <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_adj_gather, dim3(nblk(n_free)), dim3(BLK), 0, s, dev_mesh, lam, xbar, ybar);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_bd(const DevMesh* dev_mesh, int32_t nt, const double* x, const double* dgam, hipStream_t s) {
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gn_bd, dim3(blocks_tets(nt)), dim3(LBLK), 0, s, dev_mesh, x, dgam);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_av(const DevMesh* dev_mesh, int32_t n_free, const double* v, const double* geo, double* out,
+                        hipStream_t s) {
+    if (n_free <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gn_av, dim3(nblk(n_free)), dim3(BLK), 0, s, dev_mesh, v, geo, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_axpy(int32_t n, double a, const double* x, double* y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gn_axpy, dim3(nblk(n)), dim3(BLK), 0, s, n, a, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_xpby(int32_t n, const double* x, double b, double* y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gn_xpby, dim3(nblk(n)), dim3(BLK), 0, s, n, x, b, y);
+    return hipGetLastError();
+}
+
+int32_t gn_dot_blocks() { return 256; }
+
+hipError_t launch_gn_dot(int32_t n, const double* x, const double* y, double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_gn_dot, dim3(gn_dot_blocks()), dim3(BLK), 0, s, n, x, y, part);
     return hipGetLastError();
 }
 

@@ -73,6 +73,14 @@ class RegimeCounts(ctypes.Structure):
 
 VH_PRECISION_MIXED = 0
 
+
+class GNStats(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int64),
+                ("outer_rel_residual", ctypes.c_double), ("inner_rel_residual_max", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
 SIGNATURES = {
     "vh_last_error": (ctypes.c_char_p, []),
     "vh_ctx_create": (ctypes.c_int, [_P(_vp), ctypes.c_int, _sz]),
@@ -104,6 +112,7 @@ SIGNATURES = {
     "vh_mesh_embed_device": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_mesh_adjoint_forward": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _vp, _vp]),
     "vh_mesh_adjoint_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "vh_mesh_gn_direction": (ctypes.c_int, [_vp, _vp, _vp, _dbl, _i32, _dbl, _vp, _vp, _P(GNStats), _vp]),
     "vh_serve_open": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
     "vh_serve_close": (ctypes.c_int, [_vp]),
     "vh_serve_add": (ctypes.c_int, [_vp, _vp, _i32, _i32]),
@@ -358,6 +367,18 @@ class Mesh:
         return g
 
     # -- per-kernel entry points (clobber the state) --
+    def gn_direction(self, x_eq, x_target, kappa, max_outer=200, outer_tol=1e-8, stream=None):
+        """Adjoint Gauss-Newton direction for gamma_s at the equilibrium x_eq
+        (returns gradient [nt], direction [nt], stats)."""
+        xe = np.ascontiguousarray(x_eq, dtype=np.float64)
+        xt = np.ascontiguousarray(x_target, dtype=np.float64)
+        g = np.zeros(self.nt)
+        d = np.zeros(self.nt)
+        st = GNStats()
+        _check(_lib.vh_mesh_gn_direction(self.h, _ptr(xe), _ptr(xt), float(kappa), int(max_outer), float(outer_tol),
+                                         _ptr(g), _ptr(d), ctypes.byref(st), _stream_ptr(stream)))
+        return g, d, st.as_dict()
+
     def debug_local_step(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)
         T = np.empty((self.nt, 9))
