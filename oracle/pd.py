@@ -314,10 +314,12 @@ def pd_energy(x, y, mass, dt, tets, grads, w_s, w_v):
 # ----------------------------------------------------------------------------
 class OracleSim:
     """Plain FP64 PD simulator.  ``solver`` is 'exact' (global sparse LU of the
-    free block of L) or 'dd' (the exact domain-decomposed solve of oracle.dd)."""
+    free block of L), 'dd' (the exact domain-decomposed solve of oracle.dd) or
+    'cms' (the inexact CMS solve of oracle.cms: cms_modes interior eigenmodes
+    per domain, then cms_sweeps Chebyshev-weighted Jacobi sweeps)."""
 
     def __init__(self, X, tets, gamma_s, gamma_v, mass, pinned, gravity, dt, pd_iters=10,
-                 solver="exact", n_subdomains=4):
+                 solver="exact", n_subdomains=4, cms_modes=20, cms_sweeps=0):
         self.X = np.asarray(X, dtype=np.float64)
         self.tets = np.asarray(tets, dtype=np.int64)
         self.nv = self.X.shape[0]
@@ -347,6 +349,12 @@ class OracleSim:
             from .dd import DDSolver, bisect_elements
             part = bisect_elements(self.tets, n_subdomains)
             self._dd = DDSolver(self.L_ff, self.free, self.tets, part)
+            self._solve = self._dd.solve
+        elif solver == "cms":
+            from .cms import CMSSolver
+            from .dd import bisect_elements
+            part = bisect_elements(self.tets, n_subdomains)
+            self._dd = CMSSolver(self.L_ff, self.free, self.tets, part, cms_modes, cms_sweeps)
             self._solve = self._dd.solve
         else:
             raise ValueError(solver)
@@ -382,7 +390,12 @@ class OracleSim:
                 info[k] += loc["info"][k]
             b = self.rhs(y, loc["P"])
             xk = xk.copy()
-            xk[self.free] = self._solve(b)
+            if self.solver_kind == "cms":
+                # an inexact solve corrects the current iterate (residual form)
+                xf = xk[self.free]
+                xk[self.free] = xf + self._solve(b - self.L_ff @ xf)
+            else:
+                xk[self.free] = self._solve(b)
         if track_energy:
             self.energies.append(pd_energy(xk, y, self.mass, self.dt, self.tets, self.grads,
                                            self.w_s, self.w_v))
