@@ -118,10 +118,13 @@ def run(args):
     m_count.close()
     ctx.set_config(**keep_cfg)
 
-    # first frame from rest, kept for the error against the oracle
+    # first frame from rest, kept for the error against the oracle; frame 10
+    # from rest, kept for the configuration's stored oracle frame and the CMS leg
     mesh.regime_counts(reset=True, stream=stream)
     mesh.step(1, stream)
     x1, v1 = mesh.read_state(stream)
+    mesh.step(9, stream)
+    x10, _ = mesh.read_state(stream)
     mesh.step(max(0, args.warmup - 1), stream)
     torch.cuda.synchronize()
 
@@ -234,8 +237,13 @@ def run(args):
         "breakdown_ms_per_frame": breakdown,
         "hbm_copy_calibration": copy_cal,
         "prefactor_s": round(prefactor_s, 3),
-        "projection_regimes": dict(regimes, element_evaluations=nt * p.pd_iters * (args.warmup + args.steps)),
+        "projection_regimes": dict(regimes, element_evaluations=nt * p.pd_iters * (args.warmup + args.steps + 9)),
     }
+    ref10 = _golden(f"{p.name}_oracle_x_f010.npy") if p.name == "shell" else None
+    if ref10 is not None:
+        out["rel_l2_frame10_vs_oracle"] = {"positions": _rel(x10, ref10),
+                                           "displacements": float(np.linalg.norm(x10 - ref10) /
+                                                                  np.linalg.norm(ref10 - p.X))}
 
     if not args.no_embed:
         out["embed"] = embed_timing(mesh, p, stream, torch)
@@ -245,6 +253,11 @@ def run(args):
         out["rel_l2_first_frame_vs_oracle"] = err
     mesh.close()
     ctx.close()
+    if args.legs and p.name == "shell":
+        out["precision_refine2_150frames"] = precision_leg(p, args, stream, torch)
+        print(f"# precision leg: {out['precision_refine2_150frames']}", file=sys.stderr, flush=True)
+        out["cms_solve"] = cms_leg(p, x10, args, stream, torch)
+        print(f"# CMS leg: {out['cms_solve']}", file=sys.stderr, flush=True)
     if args.serving:
         out["serving"] = serving(args)
     if args.adjoint:
@@ -492,10 +505,26 @@ def serving(args):
     return out
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _golden(name):
+    """A stored FP64 oracle value (tests/golden/, written from the oracle only),
+    or None when it is not there."""
+    path = os.path.join(GOLDEN, name)
+    return np.load(path) if os.path.exists(path) else None
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
 def adjoint_timing(args):
     """Gradient of 1/2 ||x_30 - x_30(hidden)||^2 with respect to gamma_s on the
     20,000-tet slab (30 frames of 10 iterations, checkpoints every 5) with the
-    GPU discrete adjoint: forward and backward wall times."""
+    GPU discrete adjoint: forward and backward wall times, and the gradient's
+    error against the stored FP64 oracle adjoint (same loss: the oracle's own
+    x_30(hidden) as the target)."""
     import torch
     from paper_2405_12484_amd import vhpd
     import synth
@@ -503,9 +532,13 @@ def adjoint_timing(args):
     ctx = vhpd.Context(0)
     m = vhpd.Mesh(ctx, p.X, p.tets)
     x0, v0 = p.initial_state()
-    m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
-    m.prefactor(p.n_subdomains)
-    xt = m.adjoint_forward(x0, v0, 30, 5)
+    xt = _golden("slab_oracle_target_x30.npy")
+    target = "oracle x_30(hidden)"
+    if xt is None:
+        m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
+        m.prefactor(p.n_subdomains)
+        xt = m.adjoint_forward(x0, v0, 30, 5)
+        target = "GPU x_30(hidden)"
     gs0 = np.full(p.nt, 1e4)
     m.set_params(gs0, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
     m.prefactor(p.n_subdomains)
@@ -520,9 +553,80 @@ def adjoint_timing(args):
     t2 = time.perf_counter()
     m.close()
     ctx.close()
-    return {"workload": "slab_20000tets_8subdomains_30frames_ckpt5", "forward_ms": round((t1 - t0) * 1e3, 2),
-            "backward_ms": round((t2 - t1) * 1e3, 2), "loss": 0.5 * float((d * d).sum()),
-            "grad_norm": float(np.linalg.norm(g))}
+    out = {"workload": "slab_20000tets_8subdomains_30frames_ckpt5", "target": target,
+           "forward_ms": round((t1 - t0) * 1e3, 2), "backward_ms": round((t2 - t1) * 1e3, 2),
+           "loss": 0.5 * float((d * d).sum()), "grad_norm": float(np.linalg.norm(g))}
+    g_ref = _golden("slab_oracle_grad.npy")
+    if g_ref is not None and target.startswith("oracle"):
+        out["rel_l2_vs_oracle_adjoint"] = _rel(g, g_ref)
+    return out
+
+
+def precision_leg(p, args, stream, torch):
+    """The shell run 150 frames from rest with 2 refinement steps per solve:
+    ms/frame and the error after 150 frames against the stored FP64 oracle
+    trajectory (free-running), beside the same error without refinement."""
+    from paper_2405_12484_amd import vhpd
+    x150 = _golden("shell_oracle_x_f150.npy")
+    out = {"workload": f"{p.name}_{p.nt}tets_150frames", "frames": 150}
+    ctx = vhpd.Context(0)
+    for refine in (2, 0):
+        m = vhpd.Mesh(ctx, p.X, p.tets)
+        m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
+        m.prefactor(p.n_subdomains, refine)
+        m.step(1, stream)
+        m.write_state(*p.initial_state(), stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        m.step(150, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        x, _ = m.read_state(stream)
+        leg = {"ms_per_frame": round(e0.elapsed_time(e1) / 150, 4)}
+        if x150 is not None:
+            leg["rel_l2_vs_oracle_frame150"] = _rel(x, x150)
+            leg["rel_disp_vs_oracle_frame150"] = float(np.linalg.norm(x - x150) / np.linalg.norm(x150 - p.X))
+        out[f"refine_{refine}"] = leg
+        m.close()
+    ctx.close()
+    return out
+
+
+def cms_leg(p, x10_exact, args, stream, torch):
+    """The paper's inexact CMS global solve (20 interior modes per subdomain,
+    10 Chebyshev-weighted Jacobi sweeps) on the same shell: ms/frame and its
+    error after 10 frames from rest against the exact solve (the library's
+    exact path, and the stored FP64 oracle when present)."""
+    from paper_2405_12484_amd import vhpd
+    ctx = vhpd.Context(0)
+    ctx.set_config(cms_modes=20, cms_sweeps=10)
+    m = vhpd.Mesh(ctx, p.X, p.tets)
+    m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, p.pd_iters)
+    t0 = time.perf_counter()
+    m.prefactor(p.n_subdomains)
+    pf = time.perf_counter() - t0
+    m.step(10, stream)
+    x10, _ = m.read_state(stream)
+    m.step(3, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    m.step(args.steps, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out = {"modes": 20, "sweeps": 10, "ms_per_frame": round(e0.elapsed_time(e1) / args.steps, 4),
+           "prefactor_s": round(pf, 2), "device_bytes": m.info()["device_bytes"],
+           "rel_l2_vs_exact_gpu_frame10": _rel(x10, x10_exact),
+           "rel_disp_vs_exact_gpu_frame10": float(np.linalg.norm(x10 - x10_exact) / np.linalg.norm(x10_exact - p.X))}
+    ref = _golden("shell_oracle_x_f010.npy")
+    if ref is not None:
+        out["rel_l2_vs_oracle_exact_frame10"] = _rel(x10, ref)
+    m.close()
+    ctx.close()
+    return out
 
 
 def cpu_baseline(p, x1_gpu, args):
@@ -568,6 +672,8 @@ def main():
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[200.0, 1000.0, 5000.0])
     ap.add_argument("--serve-requests", type=int, default=600, help="requests per Poisson run")
     ap.add_argument("--no-embed", action="store_true", help="skip the embedded-point timing")
+    ap.add_argument("--no-legs", dest="legs", action="store_false",
+                    help="skip the 150-frame refinement leg and the CMS-solve leg")
     ap.add_argument("--serve-full", action="store_true",
                     help="also serve the whole 200/s stream (150 frames per garment; about 100 s)")
     ap.add_argument("--serve-in-flight", type=int, default=2)

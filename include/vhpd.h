@@ -93,7 +93,20 @@ int vh_ctx_set_hbm_budget(vh_ctx* ctx, size_t hbm_budget_bytes);
  *                      bisection tree joins its parent's block when the merged
  *                      block has at most this many columns (fewer interface
  *                      launches, more stored values); 0: no merging.
- * The last four change the plan, hence rounding, not the solution.
+ * These four change the plan, hence rounding, not the solution.
+ *   cms_modes (default 0, >= 0): 0 solves the global step exactly (interior
+ *                      Cholesky solves, Sec. 7.2 with the interior modes made
+ *                      exact).  > 0 selects the paper's inexact component mode
+ *                      synthesis: per subdomain the cms_modes eigenvectors of
+ *                      the interior block with the smallest eigenvalues next
+ *                      to the exact boundary modes of Eq. cms_boundary, the
+ *                      reduced solve of Eq. global_subspace applied to each PD
+ *                      iteration's residual, then
+ *   cms_sweeps (default 10, >= 0) Jacobi sweeps of the global system with
+ *                      Chebyshev weights.  The CMS solve is approximate: it
+ *                      changes the trajectory (an error to report against the
+ *                      exact solve); it needs refine_steps == 0 and is not
+ *                      differentiated by the adjoint entry points.
  * vh_ctx_set_config validates and copies *cfg (VH_EINVAL on out-of-range
  * values); it applies to meshes prefactored and servers opened afterwards, and
  * use_graphs also to later vh_mesh_step calls of meshes already resident. */
@@ -102,6 +115,7 @@ typedef struct vh_config {
     int32_t iface_lanes32_min, iface_lanes64_min;
     int32_t thin_separators;
     int32_t iface_merge_max_cols;
+    int32_t cms_modes, cms_sweeps;
 } vh_config;
 int vh_ctx_get_config(const vh_ctx* ctx, vh_config* cfg);
 int vh_ctx_set_config(vh_ctx* ctx, const vh_config* cfg);

@@ -41,6 +41,9 @@ def build(verbose: bool = True) -> str:
     o = os.path.join(BUILD, "host_plan.o")
     _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "host_plan.cpp"), "-o", o])
     objs.append(o)
+    o = os.path.join(BUILD, "cms_plan.o")
+    _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "cms_plan.cpp"), "-o", o])
+    objs.append(o)
     for src in ("kernels.hip", "api.hip", "serve.hip", "adjoint.hip", "embed.hip", "noalloc.hip", "gn.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])

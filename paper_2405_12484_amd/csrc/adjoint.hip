@@ -75,6 +75,7 @@ int vh_mesh_adjoint_forward(vh_mesh* m, const double* x0, const double* v0, int3
     VH_TRY(check_solo(m));
     if (!x0 || !v0 || !x_final) return fail(VH_EINVAL, "null argument");
     if (n_frames < 1 || ckpt_every < 1) return fail(VH_EINVAL, "n_frames and ckpt_every must be >= 1");
+    if (m->cms.modes > 0) return fail(VH_EINVAL, "the adjoint reverses the exact global solve, not the CMS solve");
     VH_TRY(set_device(m));
     hipStream_t s = static_cast<hipStream_t>(stream);
     vh::DevMesh& d = m->dm;

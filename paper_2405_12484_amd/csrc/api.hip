@@ -162,6 +162,30 @@ int alloc_plan(vh_mesh* m) {
     chk(upload(m, &d.K_val, P.K_val));
     chk(dalloc(m, &d.flags, 4));
     chk(dalloc(m, &d.regime, 8));
+    const vh::CmsPlan& C = m->cms;
+    if (C.modes > 0) {
+        d.cms_modes = C.modes;
+        d.cms_sweeps = C.sweeps;
+        float *phi = nullptr, *psi = nullptr, *ilam = nullptr;
+        int64_t *phi_off = nullptr, *psi_off = nullptr;
+        double *invd = nullptr, *omega = nullptr;
+        chk(upload(m, &phi, C.phi));
+        chk(upload(m, &psi, C.psi));
+        chk(upload(m, &ilam, C.ilam));
+        chk(upload(m, &phi_off, C.phi_off));
+        chk(upload(m, &psi_off, C.psi_off));
+        chk(upload(m, &invd, C.inv_diag));
+        if (C.sweeps > 0) chk(upload(m, &omega, C.omega));
+        chk(dalloc(m, &d.cms_b1, (size_t)P.n_free * 3));
+        chk(dalloc(m, &d.cms_b2, (size_t)P.n_free * 3));
+        d.cms_phi = phi;
+        d.cms_psi = psi;
+        d.cms_ilam = ilam;
+        d.cms_phi_off = phi_off;
+        d.cms_psi_off = psi_off;
+        d.cms_invd = invd;
+        d.cms_omega = omega;
+    }
     return r;
 }
 
@@ -187,10 +211,16 @@ int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_d
         for (const auto& c : L.cfwd) VH_HIP(vh::launch_coarse(with_record(c.ref, G), c.kind, c.group, s));
         for (const auto& c : L.cbwd) VH_HIP(vh::launch_coarse(with_record(c.ref, G), c.kind, c.group, s));
     }
-    {
-        ProfScope ps(m, s, 5);
-        VH_HIP(vh::launch_interior_bwd(with_record(L.ibwd, G), L.lds_bwd, s, apply, keep_delta));
+    ProfScope ps(m, s, 5);
+    if (L.cms_modes > 0) {
+        // the inexact CMS solve: interiors from the modes, then the sweeps
+        VH_HIP(vh::launch_cms_back(with_record(L.ibwd, G), L.lds_cms, s));
+        VH_HIP(vh::launch_cms_iface(with_record(L.refine, G), s));
+        for (int32_t k = 0; k < L.cms_sweeps; ++k) VH_HIP(vh::launch_cms_sweep(with_record(L.refine, G), k, s));
+        VH_HIP(vh::launch_cms_apply(with_record(L.refine, G), L.cms_sweeps, apply, s));
+        return VH_OK;
     }
+    VH_HIP(vh::launch_interior_bwd(with_record(L.ibwd, G), L.lds_bwd, s, apply, keep_delta));
     return VH_OK;
 }
 
@@ -290,6 +320,11 @@ int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSe
     if (ng == 0) return fail(VH_EINVAL, "empty launch set");
     L.pd_iters = members[0]->plan.pd_iters;
     L.refine_steps = members[0]->refine;
+    L.cms_modes = members[0]->cms.modes;
+    L.cms_sweeps = members[0]->cms.sweeps;
+    for (vh_mesh* m : members)
+        if (m->cms.modes != L.cms_modes || m->cms.sweeps != L.cms_sweeps)
+            return fail(VH_EINVAL, "garments in one batch need the same global solve (CMS modes and sweeps)");
     for (vh_mesh* m : members)
         if (m->plan.pd_iters != L.pd_iters || m->refine != L.refine_steps)
             return fail(VH_EINVAL, "garments in one batch need equal pd_iters and refine steps");
@@ -375,6 +410,7 @@ int build_launch_set(vh_ctx* ctx, const std::vector<vh_mesh*>& members, LaunchSe
         d.max_cint = max_cint;
     }
     L.lds_fwd = vh::interior_fwd_lds(max_n, max_cint);
+    L.lds_cms = vh::cms_back_lds(max_n, max_nb, L.cms_modes);
     L.lds_bwd = vh::interior_bwd_lds(max_n, max_nb);
     {
         int lds_limit = 0;
@@ -484,6 +520,15 @@ int host_factor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     if (lds_need > (size_t)lds_limit)
         return fail(VH_EINVAL, "a subdomain needs " + std::to_string(lds_need) + " bytes of LDS (limit " +
                                    std::to_string(lds_limit) + "); use more subdomains");
+    m->cms = vh::CmsPlan();
+    if (m->ctx->cfg.cms_modes > 0) {
+        if (refine_steps > 0) return fail(VH_EINVAL, "the CMS solve is not combined with refinement steps");
+        const size_t lc = vh::cms_back_lds(std::max(P.max_sub_n, 1), P.max_nb, m->ctx->cfg.cms_modes);
+        if (lc > (size_t)lds_limit)
+            return fail(VH_EINVAL, "a subdomain needs " + std::to_string(lc) + " bytes of LDS for the CMS solve");
+        rc = vh::build_cms(P, m->ctx->cfg.cms_modes, m->ctx->cfg.cms_sweeps, m->cms, msg);
+        if (rc != 0) return fail(rc, msg);
+    }
     m->refine = refine_steps;
     m->planned = true;
     return VH_OK;
@@ -590,6 +635,8 @@ int vh_ctx_set_config(vh_ctx* ctx, const vh_config* cfg) {
     if (cfg->thin_separators != 0 && cfg->thin_separators != 1)
         return fail(VH_EINVAL, "thin_separators must be 0 or 1");
     if (cfg->iface_merge_max_cols < 0) return fail(VH_EINVAL, "iface_merge_max_cols must be >= 0");
+    if (cfg->cms_modes < 0 || cfg->cms_modes > 256 || cfg->cms_sweeps < 0 || cfg->cms_sweeps > 10000)
+        return fail(VH_EINVAL, "cms_modes must be in 0..256 and cms_sweeps in 0..10000");
     ctx->cfg = *cfg;
     return VH_OK;
 }

@@ -49,6 +49,17 @@ struct DevMesh {
     // [0] clamped, [1] inverted, [2] det F >= 2, [3] mixed-branch point taken,
     // [4] no + branch root
     unsigned long long* regime = nullptr;
+    // inexact CMS solve of Sec. 7.2 (cms_modes > 0): interior eigenmodes
+    // (column-major per subdomain at cms_phi_off[d]), their inverse
+    // eigenvalues [D][cms_modes], boundary modes Psi_d (column-major per
+    // subdomain at cms_psi_off[d], one column per Plan::bnd row), the inverse
+    // diagonal of K and the Chebyshev weights of the Jacobi sweeps, and two
+    // sweep buffers [n_free][3] (the first is delta)
+    int32_t cms_modes = 0, cms_sweeps = 0;
+    const float *cms_phi = nullptr, *cms_psi = nullptr, *cms_ilam = nullptr;
+    const int64_t *cms_phi_off = nullptr, *cms_psi_off = nullptr;
+    const double *cms_invd = nullptr, *cms_omega = nullptr;
+    double *cms_b1 = nullptr, *cms_b2 = nullptr;
     // debug outputs of the local step (allocated on demand)
     float *dbg_T = nullptr, *dbg_sig = nullptr, *dbg_s = nullptr;
 };
@@ -83,6 +94,16 @@ hipError_t launch_interior_fwd(const LaunchRef& r, size_t lds, hipStream_t s);
 hipError_t launch_coarse(const LaunchRef& r, int32_t kind, int32_t group, hipStream_t s);
 hipError_t launch_interior_bwd(const LaunchRef& r, size_t lds, hipStream_t s, bool apply, bool keep_delta);
 hipError_t launch_refine_residual(const LaunchRef& r, hipStream_t s);
+// inexact CMS solve (after the interior forward and interface solves):
+// interior rows from the modes (one block per subdomain; table of ibwd),
+// interface rows from the interface solution, Chebyshev-weighted Jacobi sweep
+// k, and the final correction to delta (with apply: x += d) (tables over the
+// free rows, like refine)
+size_t cms_back_lds(int32_t max_n, int32_t max_nb, int32_t modes);
+hipError_t launch_cms_back(const LaunchRef& r, size_t lds, hipStream_t s);
+hipError_t launch_cms_iface(const LaunchRef& r, hipStream_t s);
+hipError_t launch_cms_sweep(const LaunchRef& r, int32_t k, hipStream_t s);
+hipError_t launch_cms_apply(const LaunchRef& r, int32_t sweeps, bool apply, hipStream_t s);
 hipError_t launch_velocity(const LaunchRef& r, hipStream_t s);
 // embedded points: out[n][3] (internal record order) from the internal state x
 hipError_t launch_embed(const float4* rec, const double* x, int32_t n, double* out, hipStream_t s);

@@ -1637,6 +1637,157 @@ __global__ __launch_bounds__(BLK) void k_refine(const DevMesh* __restrict__ GM, 
     r[3 * i + 2] -= s2;
 }
 
+// ---------------------------------------------------------------------------
+// Inexact CMS solve of Sec. 7.2 (selectable instead of the interior back
+// substitution).  The condensed interface right-hand side b^b + sum_d Psi_d^T
+// b_d^i is what the interior forward solve already produces (the same
+// vector), so the interface values x^b are the exact ones; the interiors are
+// rebuilt from the subspace of Eq. global_subspace,
+//   x_d^i = Phi_d Lambda_d^{-1} Phi_d^T b_d^i + Psi_d x^b,
+// with the dense modes read from HBM (FP32 values, FP64 sums), and the whole
+// vector is polished by Jacobi sweeps with Chebyshev weights.  b = r (the PD
+// residual), x = d (the correction of the iterate).
+// ---------------------------------------------------------------------------
+constexpr int BLKC = 256;
+
+__global__ __launch_bounds__(BLKC) void k_cms_back(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                   const int32_t* __restrict__ active) {
+    extern __shared__ double csm[];
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t d = sl.lb;
+    const int32_t r0 = M.sub_off[d], n = M.sub_off[d + 1] - r0;
+    const int32_t b0 = M.bnd_off[d], nb = M.bnd_off[d + 1] - b0;
+    const int32_t R = M.cms_modes;
+    double* RB = csm;                  // [n][3] interior right-hand side
+    double* XB = RB + 3 * n;           // [nb][3] interface values
+    double* Q = XB + 3 * nb;           // [R][3] Lambda^{-1} Phi^T b
+    const int tid = threadIdx.x;
+    for (int32_t i = tid; i < 3 * n; i += BLKC) RB[i] = M.r[3 * (size_t)r0 + i];
+    for (int32_t i = tid; i < 3 * nb; i += BLKC) {
+        const int32_t k = i / 3, c = i - 3 * k;
+        XB[i] = M.dg[3 * (size_t)(M.bnd[b0 + k] - M.n_int) + c];
+    }
+    __syncthreads();
+    // Phi^T b: one mode per wave at a time, lanes over the rows
+    const float* phi = M.cms_phi + M.cms_phi_off[d];
+    const int wave = tid / 64, lane = tid % 64;
+    for (int32_t k = wave; k < R; k += BLKC / 64) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int32_t i = lane; i < n; i += 64) {
+            const double f = (double)phi[(size_t)k * n + i];
+            s0 += f * RB[3 * i];
+            s1 += f * RB[3 * i + 1];
+            s2 += f * RB[3 * i + 2];
+        }
+        s0 = group_sum<64>(s0);
+        s1 = group_sum<64>(s1);
+        s2 = group_sum<64>(s2);
+        if (lane == 0) {
+            const double il = (double)M.cms_ilam[(size_t)d * R + k];
+            Q[3 * k] = s0 * il;
+            Q[3 * k + 1] = s1 * il;
+            Q[3 * k + 2] = s2 * il;
+        }
+    }
+    __syncthreads();
+    // x^i = Phi q + Psi x^b, one row per thread (coalesced column reads)
+    const float* psi = M.cms_psi + M.cms_psi_off[d];
+    for (int32_t i = tid; i < n; i += BLKC) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int32_t k = 0; k < R; ++k) {
+            const double f = (double)phi[(size_t)k * n + i];
+            s0 += f * Q[3 * k];
+            s1 += f * Q[3 * k + 1];
+            s2 += f * Q[3 * k + 2];
+        }
+        for (int32_t j = 0; j < nb; ++j) {
+            const double f = (double)psi[(size_t)j * n + i];
+            s0 += f * XB[3 * j];
+            s1 += f * XB[3 * j + 1];
+            s2 += f * XB[3 * j + 2];
+        }
+        double* dp = M.delta + 3 * (size_t)(r0 + i);
+        dp[0] = s0;
+        dp[1] = s1;
+        dp[2] = s2;
+    }
+}
+
+// interface rows of the correction: the interface solution
+__global__ __launch_bounds__(BLK) void k_cms_iface(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                   const int32_t* __restrict__ active) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t i = sl.lb * BLK + threadIdx.x;
+    if (i < M.n_int || i >= M.n_free) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) M.delta[3 * (size_t)i + c] = M.dg[3 * (size_t)(i - M.n_int) + c];
+}
+
+// Jacobi sweep k with the Chebyshev weight omega_k:
+//   xhat = x_k + D^{-1} (r - K x_k),  x_{k+1} = omega_k (xhat - x_{k-1}) + x_{k-1}
+// buffers: x_k in B[k % 3], x_{k-1} in B[(k + 2) % 3] (x_0 for k = 0, where
+// omega = 1), x_{k+1} to B[(k + 1) % 3]; B = {delta, cms_b1, cms_b2}
+__global__ __launch_bounds__(BLK) void k_cms_sweep(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                   const int32_t* __restrict__ active, int32_t k) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t i = sl.lb * BLK + threadIdx.x;
+    if (i >= M.n_free) return;
+    double* B[3] = {M.delta, M.cms_b1, M.cms_b2};
+    const double* xk = B[k % 3];
+    const double* xp = (k == 0) ? B[0] : B[(k + 2) % 3];
+    double* xn = B[(k + 1) % 3];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int32_t t = M.K_ptr[i]; t < M.K_ptr[i + 1]; ++t) {
+        const double v = M.K_val[t];
+        const double* q = xk + 3 * (size_t)M.K_col[t];
+        s0 += v * q[0];
+        s1 += v * q[1];
+        s2 += v * q[2];
+    }
+    const double id = M.cms_invd[i], om = M.cms_omega[k];
+    const double* rr = M.r + 3 * (size_t)i;
+    const double h0 = xk[3 * i] + id * (rr[0] - s0);
+    const double h1 = xk[3 * i + 1] + id * (rr[1] - s1);
+    const double h2 = xk[3 * i + 2] + id * (rr[2] - s2);
+    xn[3 * i] = om * (h0 - xp[3 * i]) + xp[3 * i];
+    xn[3 * i + 1] = om * (h1 - xp[3 * i + 1]) + xp[3 * i + 1];
+    xn[3 * i + 2] = om * (h2 - xp[3 * i + 2]) + xp[3 * i + 2];
+}
+
+// the final correction d (in B[sweeps % 3]) to delta; with apply, x += d and
+// u = float(x - X); free rows
+__global__ __launch_bounds__(BLK) void k_cms_apply(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                   const int32_t* __restrict__ active, int32_t sweeps,
+                                                   int32_t apply) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t i = sl.lb * BLK + threadIdx.x;
+    if (i >= M.n_free) return;
+    const double* B[3] = {M.delta, M.cms_b1, M.cms_b2};
+    const double* dp = B[sweeps % 3] + 3 * (size_t)i;
+    const double d0 = dp[0], d1 = dp[1], d2 = dp[2];
+    if (sweeps % 3 != 0) {
+        M.delta[3 * (size_t)i] = d0;
+        M.delta[3 * (size_t)i + 1] = d1;
+        M.delta[3 * (size_t)i + 2] = d2;
+    }
+    if (!apply) return;
+    double* xp = M.x + 3 * (size_t)i;
+    const double* Xp = M.X + 3 * (size_t)i;
+    const double x0 = xp[0] + d0, x1 = xp[1] + d1, x2 = xp[2] + d2;
+    xp[0] = x0;
+    xp[1] = x1;
+    xp[2] = x2;
+    store_global4(M.u + i, (float)(x0 - Xp[0]), (float)(x1 - Xp[1]), (float)(x2 - Xp[2]), 0.0f);
+}
+
 __global__ __launch_bounds__(BLK) void k_velocity(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
                                                   const int32_t* __restrict__ active) {
     Slot sl;
@@ -1701,6 +1852,9 @@ hipError_t interior_set_lds_limit(size_t bytes) {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interior_bwd),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cms_back),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     return e;
 }
 
@@ -1739,6 +1893,34 @@ hipError_t launch_refine_residual(const LaunchRef& r, hipStream_t s) {
 hipError_t launch_embed(const float4* rec, const double* x, int32_t n, double* out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_embed, dim3((n + BLK - 1) / BLK), dim3(BLK), 0, s, rec, x, n, out);
+    return hipGetLastError();
+}
+
+size_t cms_back_lds(int32_t max_n, int32_t max_nb, int32_t modes) {
+    return sizeof(double) * 3 * ((size_t)max_n + (size_t)max_nb + (size_t)modes);
+}
+
+hipError_t launch_cms_back(const LaunchRef& r, size_t lds, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cms_back, dim3(r.nblocks), dim3(BLKC), lds, s, r.G, r.L, r.active);
+    return hipGetLastError();
+}
+
+hipError_t launch_cms_iface(const LaunchRef& r, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cms_iface, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active);
+    return hipGetLastError();
+}
+
+hipError_t launch_cms_sweep(const LaunchRef& r, int32_t k, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cms_sweep, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_cms_apply(const LaunchRef& r, int32_t sweeps, bool apply, hipStream_t s) {
+    if (r.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cms_apply, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active, sweeps, (int32_t)apply);
     return hipGetLastError();
 }
 

@@ -117,10 +117,29 @@ struct Plan {
 // interface programs: a phase whose mean task length is at least lanes32_min
 // (lanes64_min) runs 32 (64) lanes per task, else 16.
 struct PlanOptions {
-    bool thin_separators = false;
+    bool thin_separators = true;
     int64_t merge_max_cols = 3000;
     int64_t lanes32_min = 96, lanes64_min = 384;
 };
+
+// The inexact CMS solve of Sec. 7.2 (host data): per subdomain d, with n_d
+// interior rows and nb_d adjacent interface rows (Plan::bnd), the interior
+// eigenmodes Phi_d (modes columns of n_d, column-major at phi_off[d]), their
+// inverse eigenvalues, the boundary modes Psi_d = -(K_d^ii)^{-1} K_d^ib
+// (nb_d columns of n_d, column-major at psi_off[d]); for the Jacobi sweeps the
+// inverse diagonal of K, the spectral radius rho of I - D^{-1} K and the
+// Chebyshev weights omega_1..omega_sweeps.
+struct CmsPlan {
+    int32_t modes = 0, sweeps = 0;
+    double rho = 0.0;
+    std::vector<double> omega;
+    std::vector<int64_t> phi_off, psi_off;
+    std::vector<float> phi, psi, ilam;     // ilam: [D][modes] (0 past a subdomain's size)
+    std::vector<double> lambda;            // [D][modes] FP64 eigenvalues (reports)
+    std::vector<double> inv_diag;          // [n_free]
+};
+// Returns 0, or a negative VH_E* code with msg set.
+int build_cms(const Plan& plan, int32_t modes, int32_t sweeps, CmsPlan& cms, std::string& msg);
 
 // Build a plan; returns 0 or a negative VH_E* code with msg set.
 int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,

@@ -45,8 +45,9 @@ struct LaunchSet {
     int32_t ng = 0;
     vh::LaunchRef predict, local, residual, ifwd, ibwd, refine, velocity;
     std::vector<CoarseLaunch> cfwd, cbwd;
-    size_t lds_fwd = 0, lds_bwd = 0;
+    size_t lds_fwd = 0, lds_bwd = 0, lds_cms = 0;
     int32_t pd_iters = 10, refine_steps = 0;
+    int32_t cms_modes = 0, cms_sweeps = 0;   // inexact CMS solve when cms_modes > 0
     size_t bytes = 0;
 };
 
@@ -56,7 +57,7 @@ struct Server;
 
 struct vh_ctx {
     int device = 0;
-    vh_config cfg{1, 96, 384, 0, 3000};
+    vh_config cfg{1, 96, 384, 1, 3000, 0, 10};
     void* scratch = nullptr;        // device address of the step scratch array (vh_mesh_step_noalloc)
     size_t budget = 0;
     size_t in_use = 0, peak = 0;
@@ -78,6 +79,7 @@ struct vh_mesh {
     double dt = 0;
     int32_t iters = 10;
     vh::Plan plan;
+    vh::CmsPlan cms;                // inexact CMS data (cms.modes > 0 when selected)
     vh::DevMesh dm;
     std::vector<void*> allocs;
     size_t bytes = 0;

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 OUT = os.path.join(HERE, "_plan_host.so")
 SRCS = [os.path.join(HERE, "plan_emulate.cpp"), os.path.join(HERE, "serve_shim.cpp"),
-        os.path.join(ROOT, "paper_2405_12484_amd", "csrc", "host_plan.cpp")]
+        os.path.join(ROOT, "paper_2405_12484_amd", "csrc", "host_plan.cpp"),
+        os.path.join(ROOT, "paper_2405_12484_amd", "csrc", "cms_plan.cpp")]
 DEPS = SRCS + [os.path.join(ROOT, "paper_2405_12484_amd", "csrc", h) for h in ("plan.h", "serve_policy.h")]
 
 

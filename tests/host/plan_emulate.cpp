@@ -178,3 +178,89 @@ int vhp_sn_stats(void* h, int* out) {
     return (int)P.sn.size();
 }
 }
+
+extern "C" {
+
+// as vhp_build, with the plan options (thin_separators 0/1, merge_max_cols)
+void* vhp_build_opts(const double* X, int nv, const int* tets, int nt, const double* gs, const double* gv,
+                     const double* mass, const unsigned char* pinned, const double* g, double dt, int iters,
+                     int D, int thin, int merge, int* rc, char* msg, int msglen) {
+    Plan* P = new Plan();
+    std::string m;
+    PlanOptions o;
+    o.thin_separators = thin != 0;
+    o.merge_max_cols = merge;
+    *rc = build_plan(X, nv, tets, nt, gs, gv, mass, pinned, g, dt, iters, D, 0, 32, 12288, o, *P, m);
+    std::snprintf(msg, msglen, "%s", m.c_str());
+    if (*rc != 0) {
+        delete P;
+        return nullptr;
+    }
+    return P;
+}
+
+// interior row ranges of the subdomains (D + 1 values, internal ids)
+void vhp_sub_off(void* h, int* out) {
+    const Plan& P = *static_cast<Plan*>(h);
+    for (size_t i = 0; i < P.sub_off.size(); ++i) out[i] = P.sub_off[i];
+}
+
+// The CMS solve as the device runs it, in FP64 from the FP32-stored modes:
+// x^b from the decomposed solve's interface rows (the exact interface
+// values), x^i = Phi (Lambda^{-1} Phi^T b^i) + Psi x^b per subdomain, then the
+// Chebyshev-weighted Jacobi sweeps.  rhs, d: [nv][3] user order.  Returns
+// build_cms's code; info[0] = rho.
+int vhp_cms_solve(void* h, int modes, int sweeps, const double* rhs, double* d, double* info) {
+    const Plan& P = *static_cast<Plan*>(h);
+    CmsPlan C;
+    std::string msg;
+    int rc = build_cms(P, modes, sweeps, C, msg);
+    if (rc != 0) return rc;
+    info[0] = C.rho;
+    const int32_t nf = P.n_free;
+    std::vector<double> exact((size_t)P.nv * 3, 0.0);
+    vhp_solve(h, rhs, exact.data());
+    std::vector<double> b((size_t)nf * 3), x((size_t)nf * 3, 0.0);
+    for (int32_t i = 0; i < nf; ++i)
+        for (int c = 0; c < 3; ++c) {
+            b[3 * i + c] = rhs[3 * P.perm[i] + c];
+            if (i >= P.n_int) x[3 * i + c] = exact[3 * P.perm[i] + c];
+        }
+    for (int32_t dd = 0; dd < P.D; ++dd) {
+        const int32_t r0 = P.sub_off[dd], n = P.sub_off[dd + 1] - r0;
+        const int32_t b0 = P.bnd_off[dd], nb = P.bnd_off[dd + 1] - b0;
+        for (int c = 0; c < 3; ++c) {
+            std::vector<double> q(modes, 0.0);
+            for (int k = 0; k < modes; ++k) {
+                double s = 0.0;
+                for (int32_t i = 0; i < n; ++i) s += (double)C.phi[C.phi_off[dd] + (size_t)k * n + i] * b[3 * (r0 + i) + c];
+                q[k] = s * (double)C.ilam[(size_t)dd * modes + k];
+            }
+            for (int32_t i = 0; i < n; ++i) {
+                double s = 0.0;
+                for (int k = 0; k < modes; ++k) s += (double)C.phi[C.phi_off[dd] + (size_t)k * n + i] * q[k];
+                for (int32_t j = 0; j < nb; ++j)
+                    s += (double)C.psi[C.psi_off[dd] + (size_t)j * n + i] * x[3 * P.bnd[b0 + j] + c];
+                x[3 * (r0 + i) + c] = s;
+            }
+        }
+    }
+    std::vector<double> prev = x, nx(x.size());
+    for (int32_t k = 0; k < sweeps; ++k) {
+        for (int32_t i = 0; i < nf; ++i)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int32_t t = P.K_ptr[i]; t < P.K_ptr[i + 1]; ++t) s += P.K_val[t] * x[3 * P.K_col[t] + c];
+                const double xh = x[3 * i + c] + C.inv_diag[i] * (b[3 * i + c] - s);
+                nx[3 * i + c] = C.omega[k] * (xh - prev[3 * i + c]) + prev[3 * i + c];
+            }
+        prev.swap(x);
+        x.swap(nx);
+    }
+    std::fill(d, d + (size_t)P.nv * 3, 0.0);
+    for (int32_t i = 0; i < nf; ++i)
+        for (int c = 0; c < 3; ++c) d[3 * P.perm[i] + c] = x[3 * i + c];
+    return 0;
+}
+
+}  // extern "C"

@@ -124,3 +124,53 @@ def test_non_finite_pivot_is_not_spd(hl):
     p = dataclasses.replace(synth.problem_by_name("box"), dt=1e-160)
     h, rc, msg, info = _build(hl, p, 4)
     assert h is None and rc == -3 and "pivot" in msg
+
+
+def _build_opts(hl, p, D, thin, merge=3000):
+    a = lambda x, t: np.ascontiguousarray(x, dtype=t)
+    keep = [a(p.X, np.float64), a(p.tets, np.int32), a(p.gamma_s, np.float64), a(p.gamma_v, np.float64),
+            a(p.mass, np.float64), a(p.pinned, np.uint8), a(p.gravity, np.float64)]
+    hl.vhp_build_opts.restype = _vp
+    hl.vhp_build_opts.argtypes = [_vp, _ci, _vp, _ci, _vp, _vp, _vp, _vp, _vp, _cd, _ci, _ci, _ci, _ci, _vp, _vp, _ci]
+    rc = ctypes.c_int(0)
+    msg = ctypes.create_string_buffer(256)
+    h = hl.vhp_build_opts(keep[0].ctypes.data, p.nv, keep[1].ctypes.data, p.nt, keep[2].ctypes.data,
+                          keep[3].ctypes.data, keep[4].ctypes.data, keep[5].ctypes.data, keep[6].ctypes.data,
+                          p.dt, p.pd_iters, D, thin, merge, ctypes.byref(rc), msg, 256)
+    assert rc.value == 0, msg.value.decode()
+    return h
+
+
+@pytest.mark.parametrize("name", ["box", "shell_small", "slab"])
+def test_cms_program_matches_oracle(hl, name):
+    """The library's CMS data (host FP64 Lanczos modes and boundary modes,
+    stored FP32) run as the device does (host emulation) against the FP64 CMS
+    oracle on the same partition (separators not thinned: the oracle's
+    interface is every vertex two subdomains share): 20 modes, 10 Chebyshev
+    sweeps, the same spectral radius."""
+    from oracle.cms import CMSSolver
+    from oracle.dd import bisect_elements
+    p = synth.problem_by_name(name)
+    h = _build_opts(hl, p, p.n_subdomains, 0)
+    try:
+        perm = np.zeros(p.nv, dtype=np.int32)
+        hl.vhp_perm(h, perm.ctypes.data)
+        so = np.zeros(p.n_subdomains + 1, dtype=np.int32)
+        hl.vhp_sub_off.argtypes = [_vp, _vp]
+        hl.vhp_sub_off(h, so.ctypes.data)
+        sim = oracle.OracleSim.from_problem(p)
+        cms = CMSSolver(sim.L_ff, sim.free, sim.tets, bisect_elements(sim.tets, p.n_subdomains), 20, 10)
+        assert [set(perm[so[d]:so[d + 1]].tolist()) for d in range(p.n_subdomains)] == \
+            [set(sim.free[I].tolist()) for I in cms.interiors]
+        rhs = np.random.default_rng(2).standard_normal((p.nv, 3))
+        rhs[p.pinned.astype(bool)] = 0.0
+        d = np.zeros((p.nv, 3))
+        info = np.zeros(2)
+        hl.vhp_cms_solve.argtypes = [_vp, _ci, _ci, _vp, _vp, _vp]
+        assert hl.vhp_cms_solve(h, 20, 10, rhs.ctypes.data, d.ctypes.data, info.ctypes.data) == 0
+        assert abs(info[0] - cms.rho) <= 1e-10
+        xo = np.zeros((p.nv, 3))
+        xo[sim.free] = cms.solve(rhs[sim.free])
+        assert np.linalg.norm(d - xo) <= 1e-7 * np.linalg.norm(xo)
+    finally:
+        hl.vhp_free(h)
