@@ -20,7 +20,14 @@ Prints ONE JSON line with:
   * serving: 64 uneven garments, batched against sequential plain stepping
     (saturated, Poisson arrivals at several rates, a 1 GB HBM budget);
   * the discrete adjoint with respect to gamma_s on the 20,000-tet slab
-    (30 frames, checkpoints every 5): forward and backward wall times.
+    (30 frames, checkpoints every 5): forward and backward wall times, and the
+    gradient's relative L2 error against the stored FP64 oracle adjoint;
+  * the 150-frame shell run at 2 refinement steps and without, each with
+    ms/frame and its frame-150 error against the stored FP64 oracle frame;
+  * the paper's inexact CMS solve (20 interior modes, 10 Chebyshev-weighted
+    Jacobi sweeps) on the shell: ms/frame and its frame-10 distance from the
+    exact solve.
+`--no-legs` prints the step, roofline and cpu_baseline only.
 """
 
 from __future__ import annotations
@@ -617,7 +624,13 @@ def cms_leg(p, x10_exact, args, stream, torch):
     m.step(args.steps, stream)
     e1.record(stream)
     torch.cuda.synchronize()
+    m.profile(list(vhpd.Mesh.PROFILE_CLASSES))
+    m.step(3, stream)
+    br = m.profile_read()
+    m.profile([])
     out = {"modes": 20, "sweeps": 10, "ms_per_frame": round(e0.elapsed_time(e1) / args.steps, 4),
+           "breakdown_ms_per_frame": {("cms_back_and_sweeps" if k == "interior_bwd" else k): round(v[0] / 3, 4)
+                                      for k, v in br.items()},
            "prefactor_s": round(pf, 2), "device_bytes": m.info()["device_bytes"],
            "rel_l2_vs_exact_gpu_frame10": _rel(x10, x10_exact),
            "rel_disp_vs_exact_gpu_frame10": float(np.linalg.norm(x10 - x10_exact) / np.linalg.norm(x10_exact - p.X))}

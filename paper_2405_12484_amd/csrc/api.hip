@@ -176,6 +176,7 @@ int alloc_plan(vh_mesh* m) {
         chk(upload(m, &psi_off, C.psi_off));
         chk(upload(m, &invd, C.inv_diag));
         if (C.sweeps > 0) chk(upload(m, &omega, C.omega));
+        chk(dalloc(m, &d.cms_q, (size_t)P.D * C.modes * 3));
         chk(dalloc(m, &d.cms_b1, (size_t)P.n_free * 3));
         chk(dalloc(m, &d.cms_b2, (size_t)P.n_free * 3));
         d.cms_phi = phi;

@@ -60,6 +60,7 @@ struct DevMesh {
     const int64_t *cms_phi_off = nullptr, *cms_psi_off = nullptr;
     const double *cms_invd = nullptr, *cms_omega = nullptr;
     double *cms_b1 = nullptr, *cms_b2 = nullptr;
+    double* cms_q = nullptr;        // [D][cms_modes][3] Lambda^{-1} Phi^T b per subdomain
     // debug outputs of the local step (allocated on demand)
     float *dbg_T = nullptr, *dbg_sig = nullptr, *dbg_s = nullptr;
 };

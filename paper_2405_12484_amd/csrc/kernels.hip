@@ -1649,52 +1649,70 @@ __global__ __launch_bounds__(BLK) void k_refine(const DevMesh* __restrict__ GM, 
 // residual), x = d (the correction of the iterate).
 // ---------------------------------------------------------------------------
 constexpr int BLKC = 256;
+constexpr int kCmsSlices = 8;          // workgroups per subdomain in k_cms_back
 
-__global__ __launch_bounds__(BLKC) void k_cms_back(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
-                                                   const int32_t* __restrict__ active) {
-    extern __shared__ double csm[];
+// q_d = Lambda_d^{-1} Phi_d^T b_d^i, one workgroup per subdomain, one mode per
+// wave at a time (lanes over the rows), to cms_q [D][modes][3]
+__global__ __launch_bounds__(BLKC) void k_cms_modes(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                    const int32_t* __restrict__ active) {
     Slot sl;
     if (!slot_of(L, active, sl)) return;
     const DevMesh& M = GM[sl.g];
     const int32_t d = sl.lb;
     const int32_t r0 = M.sub_off[d], n = M.sub_off[d + 1] - r0;
-    const int32_t b0 = M.bnd_off[d], nb = M.bnd_off[d + 1] - b0;
     const int32_t R = M.cms_modes;
-    double* RB = csm;                  // [n][3] interior right-hand side
-    double* XB = RB + 3 * n;           // [nb][3] interface values
-    double* Q = XB + 3 * nb;           // [R][3] Lambda^{-1} Phi^T b
-    const int tid = threadIdx.x;
-    for (int32_t i = tid; i < 3 * n; i += BLKC) RB[i] = M.r[3 * (size_t)r0 + i];
-    for (int32_t i = tid; i < 3 * nb; i += BLKC) {
-        const int32_t k = i / 3, c = i - 3 * k;
-        XB[i] = M.dg[3 * (size_t)(M.bnd[b0 + k] - M.n_int) + c];
-    }
-    __syncthreads();
-    // Phi^T b: one mode per wave at a time, lanes over the rows
     const float* phi = M.cms_phi + M.cms_phi_off[d];
-    const int wave = tid / 64, lane = tid % 64;
+    const double* rb = M.r + 3 * (size_t)r0;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     for (int32_t k = wave; k < R; k += BLKC / 64) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int32_t i = lane; i < n; i += 64) {
             const double f = (double)phi[(size_t)k * n + i];
-            s0 += f * RB[3 * i];
-            s1 += f * RB[3 * i + 1];
-            s2 += f * RB[3 * i + 2];
+            s0 += f * rb[3 * i];
+            s1 += f * rb[3 * i + 1];
+            s2 += f * rb[3 * i + 2];
         }
         s0 = group_sum<64>(s0);
         s1 = group_sum<64>(s1);
         s2 = group_sum<64>(s2);
         if (lane == 0) {
             const double il = (double)M.cms_ilam[(size_t)d * R + k];
-            Q[3 * k] = s0 * il;
-            Q[3 * k + 1] = s1 * il;
-            Q[3 * k + 2] = s2 * il;
+            double* q = M.cms_q + 3 * ((size_t)d * R + k);
+            q[0] = s0 * il;
+            q[1] = s1 * il;
+            q[2] = s2 * il;
         }
     }
+}
+
+// x^i = Phi q + Psi x^b: kCmsSlices workgroups per subdomain (table entry
+// blockIdx.x / kCmsSlices), each a contiguous slice of the rows, one row per
+// thread (coalesced column reads of the column-major modes)
+__global__ __launch_bounds__(BLKC) void k_cms_back(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                   const int32_t* __restrict__ active) {
+    extern __shared__ double csm[];
+    const int4 ent = reinterpret_cast<const int4*>(L)[blockIdx.x / kCmsSlices];
+    if (active[ent.x] == 0) return;
+    const DevMesh& M = GM[ent.x];
+    const int32_t d = ent.y, slice = blockIdx.x % kCmsSlices;
+    const int32_t r0 = M.sub_off[d], n = M.sub_off[d + 1] - r0;
+    const int32_t b0 = M.bnd_off[d], nb = M.bnd_off[d + 1] - b0;
+    const int32_t R = M.cms_modes;
+    const int32_t per = (n + kCmsSlices - 1) / kCmsSlices;
+    const int32_t i0 = slice * per, i1 = min(n, i0 + per);
+    if (i0 >= i1) return;
+    double* XB = csm;                  // [nb][3] interface values
+    double* Q = XB + 3 * nb;           // [R][3]
+    const int tid = threadIdx.x;
+    for (int32_t i = tid; i < 3 * nb; i += BLKC) {
+        const int32_t k = i / 3, c = i - 3 * k;
+        XB[i] = M.dg[3 * (size_t)(M.bnd[b0 + k] - M.n_int) + c];
+    }
+    for (int32_t i = tid; i < 3 * R; i += BLKC) Q[i] = M.cms_q[3 * (size_t)d * R + i];
     __syncthreads();
-    // x^i = Phi q + Psi x^b, one row per thread (coalesced column reads)
+    const float* phi = M.cms_phi + M.cms_phi_off[d];
     const float* psi = M.cms_psi + M.cms_psi_off[d];
-    for (int32_t i = tid; i < n; i += BLKC) {
+    for (int32_t i = i0 + tid; i < i1; i += BLKC) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int32_t k = 0; k < R; ++k) {
             const double f = (double)phi[(size_t)k * n + i];
@@ -1897,12 +1915,16 @@ hipError_t launch_embed(const float4* rec, const double* x, int32_t n, double* o
 }
 
 size_t cms_back_lds(int32_t max_n, int32_t max_nb, int32_t modes) {
-    return sizeof(double) * 3 * ((size_t)max_n + (size_t)max_nb + (size_t)modes);
+    (void)max_n;
+    return sizeof(double) * 3 * ((size_t)max_nb + (size_t)modes);
 }
 
 hipError_t launch_cms_back(const LaunchRef& r, size_t lds, hipStream_t s) {
     if (r.nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cms_back, dim3(r.nblocks), dim3(BLKC), lds, s, r.G, r.L, r.active);
+    hipLaunchKernelGGL(k_cms_modes, dim3(r.nblocks), dim3(BLKC), 0, s, r.G, r.L, r.active);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cms_back, dim3(r.nblocks * kCmsSlices), dim3(BLKC), lds, s, r.G, r.L, r.active);
     return hipGetLastError();
 }
 
