@@ -335,6 +335,17 @@ int vh_debug_local_step(vh_mesh* mesh, const double* x, double* T, double* sigma
  * are 0).  Uses the local-step and scatter kernels. */
 int vh_debug_residual(vh_mesh* mesh, const double* x, const double* y, double* r);
 
+/* The scatter of the local step's corner forces by element colouring, a
+ * cross-check of the atomic-free partial sums the step uses (Sec. 7.1's
+ * assembly of the global right-hand side): the tets are coloured greedily so
+ * that no two of a colour share a free vertex, and one launch per colour adds
+ * each tet's four corner forces (formed from the local step at x [nv][3])
+ * straight into FP32 vertex sums.  Writes the elastic forces f [nv][3]
+ * (pinned rows 0) -- vh_debug_residual with y = x gives the same forces up to
+ * FP32 summation order -- and, if not NULL, the colour count.  VH_EINVAL when
+ * more than 64 colours would be needed. */
+int vh_debug_scatter_colored(vh_mesh* mesh, const double* x, double* f, int32_t* n_colors);
+
 /* Solve K_ff d = rhs with the decomposed solver; rhs and d are [nv][3]
  * (pinned rows ignored on input, 0 on output). */
 int vh_debug_solve(vh_mesh* mesh, const double* rhs, double* d);

@@ -897,6 +897,67 @@ int vh_debug_local_step(vh_mesh* m, const double* x, double* T, double* sigma, d
     return VH_OK;
 }
 
+int vh_debug_scatter_colored(vh_mesh* m, const double* x, double* f, int32_t* n_colors) {
+    VH_TRY(check_solo(m));
+    if (!x || !f) return fail(VH_EINVAL, "null argument");
+    VH_TRY(set_device(m));
+    vh::DevMesh& d = m->dm;
+    const vh::Plan& P = m->plan;
+    const int32_t nt = d.nt, nf = d.n_free;
+    // greedy colouring in element order: the smallest colour no tet sharing a
+    // free vertex has taken yet (one bit per colour and vertex)
+    std::vector<uint64_t> used((size_t)P.nv, 0);
+    std::vector<int32_t> colour((size_t)nt);
+    int32_t ncol = 0;
+    for (int32_t e = 0; e < nt; ++e) {
+        uint64_t forbidden = 0;
+        for (int a = 0; a < 4; ++a) {
+            const int32_t v = P.tet_soa[(size_t)a * nt + e];
+            if (v < nf) forbidden |= used[v];
+        }
+        if (~forbidden == 0) return fail(VH_EINVAL, "the element colouring needs more than 64 colours");
+        const int32_t c = __builtin_ctzll(~forbidden);
+        colour[e] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int a = 0; a < 4; ++a) {
+            const int32_t v = P.tet_soa[(size_t)a * nt + e];
+            if (v < nf) used[v] |= (uint64_t)1 << c;
+        }
+    }
+    std::vector<int32_t> ptr(ncol + 1, 0), list((size_t)nt);
+    for (int32_t e = 0; e < nt; ++e) ++ptr[colour[e] + 1];
+    for (int32_t c = 0; c < ncol; ++c) ptr[c + 1] += ptr[c];
+    {
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int32_t e = 0; e < nt; ++e) list[fill[colour[e]]++] = e;
+    }
+    if (!d.dbg_T) {
+        VH_TRY(dalloc(m, &d.dbg_T, (size_t)nt * 9));
+        VH_TRY(dalloc(m, &d.dbg_sig, (size_t)nt * 3));
+        VH_TRY(dalloc(m, &d.dbg_s, (size_t)nt * 3));
+    }
+    if (!d.dbg_col) {
+        VH_TRY(dalloc(m, &d.dbg_col, (size_t)nt));
+        VH_TRY(dalloc(m, &d.dbg_b, (size_t)nf * 3));
+    }
+    VH_TRY(put_user(m, x, d.x, true, nullptr));
+    VH_HIP(hipMemcpy(&m->ls.G[0].dbg_T, &d.dbg_T, 3 * sizeof(float*), hipMemcpyHostToDevice));
+    VH_HIP(vh::launch_refresh_u(d, nullptr));
+    VH_HIP(vh::launch_local(m->ls.local, nullptr, true));
+    VH_HIP(hipMemcpy(d.dbg_col, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    VH_HIP(hipMemset(d.dbg_b, 0, (size_t)nf * 3 * sizeof(float)));
+    for (int32_t c = 0; c < ncol; ++c)
+        VH_HIP(vh::launch_scatter_colour(d, d.dbg_col + ptr[c], ptr[c + 1] - ptr[c], nullptr));
+    VH_HIP(hipDeviceSynchronize());
+    std::vector<float> hb((size_t)nf * 3);
+    VH_HIP(hipMemcpy(hb.data(), d.dbg_b, hb.size() * sizeof(float), hipMemcpyDeviceToHost));
+    std::fill(f, f + (size_t)P.nv * 3, 0.0);
+    for (int32_t i = 0; i < nf; ++i)
+        for (int c = 0; c < 3; ++c) f[3 * (size_t)P.perm[i] + c] = hb[3 * (size_t)i + c];
+    if (n_colors) *n_colors = ncol;
+    return VH_OK;
+}
+
 int vh_debug_residual(vh_mesh* m, const double* x, const double* y, double* r) {
     VH_TRY(check_solo(m));
     if (!x || !y || !r) return fail(VH_EINVAL, "null argument");

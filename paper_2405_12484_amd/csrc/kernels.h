@@ -63,6 +63,9 @@ struct DevMesh {
     double* cms_q = nullptr;        // [D][cms_modes][3] Lambda^{-1} Phi^T b per subdomain
     // debug outputs of the local step (allocated on demand)
     float *dbg_T = nullptr, *dbg_sig = nullptr, *dbg_s = nullptr;
+    // the element-colouring cross-check of the scatter (allocated on demand)
+    int32_t* dbg_col = nullptr;     // [nt] tets grouped by colour
+    float* dbg_b = nullptr;         // [n_free][3] FP32 force sums
 };
 
 // One launch over one or more garments: G is a device array of DevMesh, L the
@@ -90,6 +93,10 @@ int32_t coarse_blocks(int32_t ntasks, int32_t group);
 
 hipError_t launch_predictor(const LaunchRef& r, hipStream_t s);
 hipError_t launch_local(const LaunchRef& r, hipStream_t s, bool debug);
+// one colour of the element-colouring scatter: the count tets list[0..count)
+// (no two share a free vertex) add their corner forces, formed from the debug
+// stress dbg_T, into dbg_b
+hipError_t launch_scatter_colour(const DevMesh& d, const int32_t* list, int32_t count, hipStream_t s);
 hipError_t launch_residual(const LaunchRef& r, hipStream_t s);
 hipError_t launch_interior_fwd(const LaunchRef& r, size_t lds, hipStream_t s);
 hipError_t launch_coarse(const LaunchRef& r, int32_t kind, int32_t group, hipStream_t s);

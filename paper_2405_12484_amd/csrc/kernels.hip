@@ -601,6 +601,45 @@ __global__ __launch_bounds__(LBLK, 8) void k_local(const DevMesh* __restrict__ G
     }
 }
 
+// Cross-check of the scatter above (the alternative the partial sums replace):
+// the tets of one colour share no free vertex, so each adds its four corner
+// forces straight into the vertex sums.  The forces are formed from the stress
+// the debug local step stored, with the expressions of k_local.
+__global__ __launch_bounds__(BLK) void k_scatter_colour(const float4* __restrict__ trec, const float* __restrict__ T,
+                                                        const int32_t* __restrict__ list, int32_t count,
+                                                        int32_t n_free, float* __restrict__ b) {
+    const int32_t j = blockIdx.x * BLK + threadIdx.x;
+    if (j >= count) return;
+    const int32_t e = list[j];
+    const float4 r0 = trec[4 * (size_t)e], r1 = trec[4 * (size_t)e + 1], r2 = trec[4 * (size_t)e + 2],
+                 r3 = trec[4 * (size_t)e + 3];
+    const int32_t v[4] = {__float_as_int(r0.x), __float_as_int(r0.y), __float_as_int(r0.z), __float_as_int(r0.w)};
+    const float G[9] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
+    float t[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) t[k] = T[(size_t)e * 9 + k];
+    float s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int c = 1; c < 4; ++c) {
+        const float fx = t[0] * G[(c - 1) * 3 + 0] + t[1] * G[(c - 1) * 3 + 1] + t[2] * G[(c - 1) * 3 + 2];
+        const float fy = t[3] * G[(c - 1) * 3 + 0] + t[4] * G[(c - 1) * 3 + 1] + t[5] * G[(c - 1) * 3 + 2];
+        const float fz = t[6] * G[(c - 1) * 3 + 0] + t[7] * G[(c - 1) * 3 + 1] + t[8] * G[(c - 1) * 3 + 2];
+        if (v[c] < n_free) {
+            b[3 * (size_t)v[c] + 0] += fx;
+            b[3 * (size_t)v[c] + 1] += fy;
+            b[3 * (size_t)v[c] + 2] += fz;
+        }
+        s0 += fx;
+        s1 += fy;
+        s2 += fz;
+    }
+    if (v[0] < n_free) {
+        b[3 * (size_t)v[0] + 0] += -s0;
+        b[3 * (size_t)v[0] + 1] += -s1;
+        b[3 * (size_t)v[0] + 2] += -s2;
+    }
+}
+
 __global__ __launch_bounds__(BLK) void k_predict(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
                                                  const int32_t* __restrict__ active) {
     Slot sl;
@@ -1317,7 +1356,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
 //   GEMV:    zg[idx], cgd[idx] or (a root, rows of Ti^T Ti) dg[idx] = row . rg
 //   BGEMV:   dg[out] = Ti column . zg + (-W_B) column . dg[gather]
 template <int G>
-__global__ __launch_bounds__(BLK) void k_coarse(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+__global__ __launch_bounds__(BLK, 8) void k_coarse(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
                                                 const int32_t* __restrict__ active, int32_t kind) {
     Slot sl;
     if (!slot_of(L, active, sl)) return;
@@ -1836,6 +1875,13 @@ inline int nblk(int64_t n) { return (int)((n + BLK - 1) / BLK); }
 hipError_t launch_predictor(const LaunchRef& r, hipStream_t s) {
     if (r.nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_predict, dim3(r.nblocks), dim3(BLK), 0, s, r.G, r.L, r.active);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_colour(const DevMesh& d, const int32_t* list, int32_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_colour, dim3((count + BLK - 1) / BLK), dim3(BLK), 0, s, d.trec, d.dbg_T, list, count,
+                       d.n_free, d.dbg_b);
     return hipGetLastError();
 }
 

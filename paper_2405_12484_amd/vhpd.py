@@ -107,6 +107,7 @@ SIGNATURES = {
     "vh_mesh_profile_read": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_debug_local_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vh_debug_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "vh_debug_scatter_colored": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_debug_solve": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_mesh_set_embedding": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
     "vh_mesh_embed": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -394,6 +395,14 @@ class Mesh:
         r = np.empty((self.nv, 3))
         _check(_lib.vh_debug_residual(self.h, _ptr(x), _ptr(y), _ptr(r)))
         return r
+
+    def debug_scatter_colored(self, x):
+        """Elastic forces at x [nv][3] assembled by element colouring, and the colour count."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        f = np.empty((self.nv, 3))
+        nc = ctypes.c_int32(0)
+        _check(_lib.vh_debug_scatter_colored(self.h, _ptr(x), _ptr(f), ctypes.byref(nc)))
+        return f, int(nc.value)
 
     def debug_solve(self, rhs):
         rhs = np.ascontiguousarray(rhs, dtype=np.float64)

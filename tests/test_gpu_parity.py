@@ -241,6 +241,29 @@ def test_residual_matches_oracle(vh, ctx, name):
     m.close()
 
 
+@pytest.mark.parametrize("name", ["box", "shell_small", "slab"])
+def test_scatter_matches_element_colouring(vh, ctx, name):
+    """The atomic-free scatter (per-workgroup LDS partial sums, then a gather
+    per vertex) against the element-colouring scatter: the same corner forces
+    summed in another order, so equal to FP32 summation rounding; both match
+    the oracle's elastic forces."""
+    say(f"[scatter colouring] {name}")
+    p = synth.problem_by_name(name)
+    m = make_mesh(vh, ctx, p)
+    sim = oracle.OracleSim.from_problem(p)
+    x = deformed(p, amp=2e-3, seed=6)
+    f_col, ncol = m.debug_scatter_colored(x)
+    f_part = m.debug_residual(x, x)          # y = x: the inertial term vanishes
+    scale = np.abs(f_part).max()
+    assert 4 <= ncol <= 64
+    assert np.abs(f_col - f_part).max() <= 1e-5 * scale
+    assert np.all(f_col[p.pinned.astype(bool)] == 0)
+    loc = oracle.local_step(x, sim.tets, sim.grads, sim.w_s, sim.w_v)
+    fref = sim.rhs(x, loc["P"]) - sim.L_ff @ x[sim.free]   # residual at y = x
+    assert np.linalg.norm(f_col[sim.free] - fref) <= 1e-5 * np.linalg.norm(fref)
+    m.close()
+
+
 # --- decomposed solve ---------------------------------------------------------------
 @pytest.mark.parametrize("name,D", [("box", 4), ("box", 1), ("shell_small", 8), ("slab", 8)])
 def test_solve_matches_exact(vh, ctx, name, D):
