@@ -155,6 +155,19 @@ enum { VH_PRECISION_MIXED = 0 };
 int vh_mesh_prefactor(vh_mesh* mesh, int32_t n_subdomains, int32_t refine_steps,
                       int32_t precision_mode);
 
+/* New per-element stiffness gamma_s, gamma_v [nt] (>= 0, as in
+ * vh_mesh_set_params) for a prefactored mesh, as a fitting loop changes it
+ * (Sec. 6).  The global matrix of Sec. 7.1 depends on gamma only through its
+ * values: the partition, orderings, supernodes and solve programs are kept,
+ * the element weights, the matrix values and the numeric FP64 factorization
+ * are redone on the host, and the device factor is overwritten in place, so
+ * captured frame graphs stay valid.  The state x, v is kept; adjoint
+ * checkpoints are dropped.  VH_ESTATE unless prefactored (or while the server
+ * drives the mesh); VH_EINVAL with the CMS solve selected (vh_mesh_prefactor
+ * rebuilds its modes); VH_ENOTSPD on a non-positive pivot, after which the
+ * mesh needs vh_mesh_prefactor. */
+int vh_mesh_refactor(vh_mesh* mesh, const double* gamma_s, const double* gamma_v);
+
 /* Advance n_frames time steps on `stream` (asynchronous). */
 int vh_mesh_step(vh_mesh* mesh, int32_t n_frames, void* stream);
 

@@ -9,8 +9,9 @@ its checkpoints and the discrete adjoint run in libvhpd).
     loss.backward()              # gamma_s.grad via vh_mesh_adjoint_backward
 
 The stiffness enters the global matrix, so a forward at a new gamma_s
-refactors it (host FP64); a forward at the gamma_s already factored reuses the
-factorization.  One trajectory holds one set of checkpoints (those of its
+refactors it (vh_mesh_refactor: host FP64 numeric factorization over the
+structure of the first prefactor); a forward at the gamma_s already factored
+reuses the factorization.  One trajectory holds one set of checkpoints (those of its
 latest forward); the backward of an earlier output replays that output's
 forward first, so every gradient belongs to its own gamma_s.
 """
@@ -60,9 +61,12 @@ class Trajectory:
 
     def _run(self, gamma_s):
         m = self.mesh
-        if self._factored_gs is None or not np.array_equal(self._factored_gs, gamma_s):
+        if self._factored_gs is None:
             m.set_params(gamma_s, self.gamma_v, self.mass, self.pinned, self.gravity, self.dt, self.pd_iters)
             m.prefactor(self.n_subdomains, self.refine_steps)
+            self._factored_gs = np.array(gamma_s, dtype=np.float64)
+        elif not np.array_equal(self._factored_gs, gamma_s):
+            m.refactor(gamma_s, self.gamma_v)      # same structure, new factor values
             self._factored_gs = np.array(gamma_s, dtype=np.float64)
         self.generation += 1
         return m.adjoint_forward(self.X, np.zeros_like(self.X), self.frames, self.ckpt_every)

@@ -739,6 +739,37 @@ int vh_mesh_prefactor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps, in
     return upload_device(m);
 }
 
+int vh_mesh_refactor(vh_mesh* m, const double* gamma_s, const double* gamma_v) {
+    VH_TRY(check_solo(m));
+    if (!gamma_s || !gamma_v) return fail(VH_EINVAL, "null argument");
+    for (int32_t e = 0; e < m->nt; ++e)
+        if (!(gamma_s[e] >= 0.0) || !(gamma_v[e] >= 0.0) || !std::isfinite(gamma_s[e]) ||
+            !std::isfinite(gamma_v[e]))
+            return fail(VH_EINVAL, "gamma must be finite and >= 0 (element " + std::to_string(e) + ")");
+    if (m->cms.modes > 0) return fail(VH_EINVAL, "a mesh with the CMS solve is refactored by vh_mesh_prefactor");
+    VH_TRY(set_device(m));
+    std::string msg;
+    const int rc = vh::refactor_plan(m->plan, m->X.data(), m->tets.data(), gamma_s, gamma_v, msg);
+    if (rc != 0) {
+        // the host plan holds a partial factorization
+        free_device(m);
+        m->planned = false;
+        return fail(rc, msg);
+    }
+    m->gs.assign(gamma_s, gamma_s + m->nt);
+    m->gv.assign(gamma_v, gamma_v + m->nt);
+    // the values in place: same sizes and addresses (work in flight finishes first)
+    const vh::Plan& P = m->plan;
+    const vh::DevMesh& d = m->dm;
+    VH_HIP(hipDeviceSynchronize());
+    VH_HIP(hipMemcpy(d.trec, P.trec.data(), P.trec.size() * sizeof(float), hipMemcpyHostToDevice));
+    VH_HIP(hipMemcpy(d.ivals, P.ivals.data(), P.ivals.size() * sizeof(float), hipMemcpyHostToDevice));
+    VH_HIP(hipMemcpy(d.dvals, P.dvals.data(), P.dvals.size() * sizeof(double), hipMemcpyHostToDevice));
+    VH_HIP(hipMemcpy(d.K_val, P.K_val.data(), P.K_val.size() * sizeof(double), hipMemcpyHostToDevice));
+    free_adjoint(m);
+    return VH_OK;
+}
+
 int vh_mesh_step(vh_mesh* m, int32_t n_frames, void* stream) {
     VH_TRY(check_solo(m));
     if (n_frames < 0) return fail(VH_EINVAL, "n_frames must be >= 0");

@@ -326,6 +326,191 @@ void lower_inverse(const double* L, int32_t f, int32_t n, std::vector<double>& T
     }
 }
 
+// K on the free unknowns in internal order (CSR, columns ascending):
+// sum_e V_e (gs_e + gv_e) (G_e)_ab plus M/dt^2 on the diagonal (Sec. 7.1).
+// Vol, Gd: per internal element its volume and Dm^{-1} (row-major).
+void assemble_matrix(Plan& P, const std::vector<double>& Vol, const std::vector<double>& Gd, const double* gamma_s,
+                     const double* gamma_v, double dt) {
+    const int32_t nf = P.n_free, nt = P.nt;
+
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(nf);
+    for (int32_t e = 0; e < nt; ++e) {
+        double gr[4][3];
+        const double* G = &Gd[(size_t)e * 9];
+        for (int k = 0; k < 3; ++k) {
+            gr[0][k] = -(G[0 * 3 + k] + G[1 * 3 + k] + G[2 * 3 + k]);
+            for (int c = 1; c < 4; ++c) gr[c][k] = G[(c - 1) * 3 + k];
+        }
+        int32_t u = P.elem_perm[e];
+        double w = Vol[e] * (gamma_s[u] + gamma_v[u]);
+        for (int a = 0; a < 4; ++a) {
+            int32_t ia = P.tet_soa[(size_t)a * nt + e];
+            if (ia >= nf) continue;
+            for (int b = 0; b < 4; ++b) {
+                int32_t ib = P.tet_soa[(size_t)b * nt + e];
+                if (ib >= nf) continue;
+                double g = gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2];
+                rows[ia].push_back({ib, w * g});
+            }
+        }
+    }
+    P.K_ptr.assign(nf + 1, 0);
+    for (int32_t i = 0; i < nf; ++i) {
+        auto& r = rows[i];
+        r.push_back({i, P.mass_int[i] / (dt * dt)});
+        std::sort(r.begin(), r.end(),
+                  [](const auto& a, const auto& b) { return a.first < b.first; });
+        size_t w = 0;
+        for (size_t k = 0; k < r.size(); ++k) {
+            if (w > 0 && r[w - 1].first == r[k].first) r[w - 1].second += r[k].second;
+            else r[w++] = r[k];
+        }
+        r.resize(w);
+        P.K_ptr[i + 1] = P.K_ptr[i] + (int32_t)w;
+    }
+    P.K_col.resize(P.K_ptr[nf]);
+    P.K_val.resize(P.K_ptr[nf]);
+    for (int32_t i = 0; i < nf; ++i)
+        for (size_t k = 0; k < rows[i].size(); ++k) {
+            P.K_col[P.K_ptr[i] + k] = rows[i][k].first;
+            P.K_val[P.K_ptr[i] + k] = rows[i][k].second;
+        }
+}
+
+// Numeric multifrontal FP64 factorization of P's matrix over its supernodes
+// (rows below and value offsets already set): the value blocks of interior
+// supernodes go to ivd (P.n_ivd values), those of interface supernodes to
+// P.dvals.  Interior subdomains in parallel; interface supernodes in order,
+// each with parallel dense kernels.  OK, or ENOTSPD_ with msg set.
+int factor_numeric(Plan& P, std::vector<double>& ivd, std::string& msg) {
+    std::vector<Supernode>& SN = P.sn;
+    const int32_t nsn = (int32_t)SN.size(), nf = P.n_free, D = P.D;
+    std::vector<std::vector<double>> upd(nsn);
+    int err = OK;
+    auto numeric = [&](int32_t t, std::vector<int32_t>& pos, bool par) -> int {
+        Supernode& s = SN[t];
+        const int32_t n = s.n, m = (int32_t)s.rows.size(), f = n + m;
+        std::vector<double> F((size_t)f * f, 0.0);
+        for (int32_t a = 0; a < n; ++a) pos[s.col0 + a] = a;
+        for (int32_t b = 0; b < m; ++b) pos[s.rows[b]] = n + b;
+        for (int32_t a = 0; a < n; ++a) {
+            int32_t j = s.col0 + a;
+            for (int32_t k = P.K_ptr[j]; k < P.K_ptr[j + 1]; ++k) {
+                int32_t i = P.K_col[k];
+                if (i < j) continue;
+                F[(size_t)a * f + pos[i]] += P.K_val[k];
+            }
+        }
+        for (int32_t c : s.children) {
+            const Supernode& cs = SN[c];
+            const int32_t mc = (int32_t)cs.rows.size();
+            const std::vector<double>& U = upd[c];
+            for (int32_t b2 = 0; b2 < mc; ++b2) {
+                int32_t pb = pos[cs.rows[b2]];
+                for (int32_t a2 = b2; a2 < mc; ++a2)
+                    F[(size_t)pb * f + pos[cs.rows[a2]]] += U[(size_t)b2 * mc + a2];
+            }
+            std::vector<double>().swap(upd[c]);
+        }
+        int rc = partial_cholesky(F.data(), f, n, par);
+        if (rc != OK) return rc;
+        std::vector<double> Ti;
+        lower_inverse(F.data(), f, n, Ti, par);
+        // W_B[p][a] = sum_{b >= a} B[p][b] Ti[b][a], B[p][b] = F(n + p, b)
+        std::vector<double> WB((size_t)m * n, 0.0);
+        auto wrow = [&](int32_t p) {
+            for (int32_t b = 0; b < n; ++b) {
+                const double bv = F[(size_t)b * f + n + p];
+                if (bv == 0.0) continue;
+                const double* tr = &Ti[(size_t)b * n];
+                double* wr = &WB[(size_t)p * n];
+                for (int32_t a = 0; a <= b; ++a) wr[a] += bv * tr[a];
+            }
+        };
+        if (par && (int64_t)m * n * n > 4000000) {
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int32_t p = 0; p < m; ++p) wrow(p);
+        } else {
+            for (int32_t p = 0; p < m; ++p) wrow(p);
+        }
+        double* vals = (s.sub >= 0) ? ivd.data() : P.dvals.data();
+        const int64_t tri = (int64_t)n * (n + 1) / 2;
+        if (s.sub < 0 && m == 0) {
+            // an interface root (no rows below): its forward and backward
+            // solves compose to d = Ti^T Ti r', so the full symmetric
+            // A = Ti^T Ti (n^2 <= 2 tri values, both layouts' space) is stored
+            // row-major and applied in one pass.  A[i][j] = sum_{k >= max(i, j)}
+            // Ti[k][i] Ti[k][j], dot products of Ti's columns.
+            std::vector<double> TC((size_t)n * n, 0.0);   // TC[i][k] = Ti[k][i]
+            for (int32_t k = 0; k < n; ++k)
+                for (int32_t i = 0; i <= k; ++i) TC[(size_t)i * n + k] = Ti[(size_t)k * n + i];
+            double* A = vals + s.wf_off;
+#pragma omp parallel for schedule(dynamic, 8) if (par)
+            for (int32_t i = 0; i < n; ++i) {
+                const double* ci = &TC[(size_t)i * n];
+                for (int32_t j = i; j < n; ++j) {
+                    const double* cj = &TC[(size_t)j * n];
+                    double acc = 0.0;
+                    for (int32_t k = j; k < n; ++k) acc += ci[k] * cj[k];
+                    A[(int64_t)i * n + j] = acc;
+                    A[(int64_t)j * n + i] = acc;
+                }
+            }
+            upd[t].clear();
+            return OK;
+        }
+        for (int32_t a = 0; a < n; ++a)
+            for (int32_t b = 0; b <= a; ++b) vals[s.wf_off + (int64_t)a * (a + 1) / 2 + b] = Ti[(size_t)a * n + b];
+        for (int32_t p = 0; p < m; ++p)
+            for (int32_t a = 0; a < n; ++a) vals[s.wf_off + tri + (int64_t)p * n + a] = WB[(size_t)p * n + a];
+        for (int32_t k = 0; k < n; ++k) {
+            int64_t off = s.wb_off + (int64_t)k * (n + m) - (int64_t)k * (k - 1) / 2;
+            for (int32_t i = k; i < n; ++i) vals[off + (i - k)] = Ti[(size_t)i * n + k];
+            off += n - k;
+            // interface blocks hold -W_B (backward dot products); interior blocks +W_B
+            const double sg = (s.sub >= 0) ? 1.0 : -1.0;
+            for (int32_t p = 0; p < m; ++p) vals[off + p] = sg * WB[(size_t)p * n + k];
+        }
+        std::vector<double> U((size_t)m * m);
+        for (int32_t b = 0; b < m; ++b)
+            for (int32_t a = b; a < m; ++a) U[(size_t)b * m + a] = F[(size_t)(n + b) * f + n + a];
+        upd[t] = std::move(U);
+        return OK;
+    };
+#pragma omp parallel
+    {
+        std::vector<int32_t> pos(nf, 0);
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t d = 0; d < D; ++d) {
+            for (int32_t t = 0; t < nsn; ++t) {
+                if (SN[t].sub != d) continue;
+                int rc = numeric(t, pos, false);
+                if (rc != OK) {
+#pragma omp critical
+                    err = rc;
+                    break;
+                }
+            }
+        }
+    }
+    if (err != OK) {
+        msg = "non-positive pivot in an interior factor";
+        return err;
+    }
+    {
+        std::vector<int32_t> pos(nf, 0);
+        for (int32_t t = 0; t < nsn; ++t) {
+            if (SN[t].sub >= 0) continue;
+            int rc = numeric(t, pos, true);
+            if (rc != OK) {
+                msg = "non-positive pivot in the interface factor";
+                return rc;
+            }
+        }
+    }
+    return OK;
+}
+
 }  // namespace
 
 int check_mesh(const double* X, int32_t nv, const int32_t* tets, int32_t nt, std::string& msg) {
@@ -760,50 +945,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
 
     // ---- FP64 matrix on free unknowns (internal order) ------------------------------
     const int32_t nf = P.n_free;
-    {
-        std::vector<std::vector<std::pair<int32_t, double>>> rows(nf);
-        for (int32_t e = 0; e < nt; ++e) {
-            double gr[4][3];
-            const double* G = &Gd[(size_t)e * 9];
-            for (int k = 0; k < 3; ++k) {
-                gr[0][k] = -(G[0 * 3 + k] + G[1 * 3 + k] + G[2 * 3 + k]);
-                for (int c = 1; c < 4; ++c) gr[c][k] = G[(c - 1) * 3 + k];
-            }
-            int32_t u = P.elem_perm[e];
-            double w = Vol[e] * (gamma_s[u] + gamma_v[u]);
-            for (int a = 0; a < 4; ++a) {
-                int32_t ia = P.tet_soa[(size_t)a * nt + e];
-                if (ia >= nf) continue;
-                for (int b = 0; b < 4; ++b) {
-                    int32_t ib = P.tet_soa[(size_t)b * nt + e];
-                    if (ib >= nf) continue;
-                    double g = gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2];
-                    rows[ia].push_back({ib, w * g});
-                }
-            }
-        }
-        P.K_ptr.assign(nf + 1, 0);
-        for (int32_t i = 0; i < nf; ++i) {
-            auto& r = rows[i];
-            r.push_back({i, P.mass_int[i] / (dt * dt)});
-            std::sort(r.begin(), r.end(),
-                      [](const auto& a, const auto& b) { return a.first < b.first; });
-            size_t w = 0;
-            for (size_t k = 0; k < r.size(); ++k) {
-                if (w > 0 && r[w - 1].first == r[k].first) r[w - 1].second += r[k].second;
-                else r[w++] = r[k];
-            }
-            r.resize(w);
-            P.K_ptr[i + 1] = P.K_ptr[i] + (int32_t)w;
-        }
-        P.K_col.resize(P.K_ptr[nf]);
-        P.K_val.resize(P.K_ptr[nf]);
-        for (int32_t i = 0; i < nf; ++i)
-            for (size_t k = 0; k < rows[i].size(); ++k) {
-                P.K_col[P.K_ptr[i] + k] = rows[i][k].first;
-                P.K_val[P.K_ptr[i] + k] = rows[i][k].second;
-            }
-    }
+    assemble_matrix(P, Vol, Gd, gamma_s, gamma_v, dt);
 
     // ---- symbolic: rows below each supernode --------------------------------------
     const int32_t nsn = (int32_t)SN.size();
@@ -874,128 +1016,10 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
     }
 
     // ---- numeric: multifrontal FP64 --------------------------------------------------
-    std::vector<std::vector<double>> upd(nsn);
-    int err = OK;
-    auto numeric = [&](int32_t t, std::vector<int32_t>& pos, bool par) -> int {
-        Supernode& s = SN[t];
-        const int32_t n = s.n, m = (int32_t)s.rows.size(), f = n + m;
-        std::vector<double> F((size_t)f * f, 0.0);
-        for (int32_t a = 0; a < n; ++a) pos[s.col0 + a] = a;
-        for (int32_t b = 0; b < m; ++b) pos[s.rows[b]] = n + b;
-        for (int32_t a = 0; a < n; ++a) {
-            int32_t j = s.col0 + a;
-            for (int32_t k = P.K_ptr[j]; k < P.K_ptr[j + 1]; ++k) {
-                int32_t i = P.K_col[k];
-                if (i < j) continue;
-                F[(size_t)a * f + pos[i]] += P.K_val[k];
-            }
-        }
-        for (int32_t c : s.children) {
-            const Supernode& cs = SN[c];
-            const int32_t mc = (int32_t)cs.rows.size();
-            const std::vector<double>& U = upd[c];
-            for (int32_t b2 = 0; b2 < mc; ++b2) {
-                int32_t pb = pos[cs.rows[b2]];
-                for (int32_t a2 = b2; a2 < mc; ++a2)
-                    F[(size_t)pb * f + pos[cs.rows[a2]]] += U[(size_t)b2 * mc + a2];
-            }
-            std::vector<double>().swap(upd[c]);
-        }
-        int rc = partial_cholesky(F.data(), f, n, par);
+    P.n_ivd = fo;
+    {
+        const int rc = factor_numeric(P, ivd, msg);
         if (rc != OK) return rc;
-        std::vector<double> Ti;
-        lower_inverse(F.data(), f, n, Ti, par);
-        // W_B[p][a] = sum_{b >= a} B[p][b] Ti[b][a], B[p][b] = F(n + p, b)
-        std::vector<double> WB((size_t)m * n, 0.0);
-        auto wrow = [&](int32_t p) {
-            for (int32_t b = 0; b < n; ++b) {
-                const double bv = F[(size_t)b * f + n + p];
-                if (bv == 0.0) continue;
-                const double* tr = &Ti[(size_t)b * n];
-                double* wr = &WB[(size_t)p * n];
-                for (int32_t a = 0; a <= b; ++a) wr[a] += bv * tr[a];
-            }
-        };
-        if (par && (int64_t)m * n * n > 4000000) {
-#pragma omp parallel for schedule(dynamic, 4)
-            for (int32_t p = 0; p < m; ++p) wrow(p);
-        } else {
-            for (int32_t p = 0; p < m; ++p) wrow(p);
-        }
-        double* vals = (s.sub >= 0) ? ivd.data() : P.dvals.data();
-        const int64_t tri = (int64_t)n * (n + 1) / 2;
-        if (s.sub < 0 && m == 0) {
-            // an interface root (no rows below): its forward and backward
-            // solves compose to d = Ti^T Ti r', so the full symmetric
-            // A = Ti^T Ti (n^2 <= 2 tri values, both layouts' space) is stored
-            // row-major and applied in one pass.  A[i][j] = sum_{k >= max(i, j)}
-            // Ti[k][i] Ti[k][j], dot products of Ti's columns.
-            std::vector<double> TC((size_t)n * n, 0.0);   // TC[i][k] = Ti[k][i]
-            for (int32_t k = 0; k < n; ++k)
-                for (int32_t i = 0; i <= k; ++i) TC[(size_t)i * n + k] = Ti[(size_t)k * n + i];
-            double* A = vals + s.wf_off;
-#pragma omp parallel for schedule(dynamic, 8) if (par)
-            for (int32_t i = 0; i < n; ++i) {
-                const double* ci = &TC[(size_t)i * n];
-                for (int32_t j = i; j < n; ++j) {
-                    const double* cj = &TC[(size_t)j * n];
-                    double acc = 0.0;
-                    for (int32_t k = j; k < n; ++k) acc += ci[k] * cj[k];
-                    A[(int64_t)i * n + j] = acc;
-                    A[(int64_t)j * n + i] = acc;
-                }
-            }
-            upd[t].clear();
-            return OK;
-        }
-        for (int32_t a = 0; a < n; ++a)
-            for (int32_t b = 0; b <= a; ++b) vals[s.wf_off + (int64_t)a * (a + 1) / 2 + b] = Ti[(size_t)a * n + b];
-        for (int32_t p = 0; p < m; ++p)
-            for (int32_t a = 0; a < n; ++a) vals[s.wf_off + tri + (int64_t)p * n + a] = WB[(size_t)p * n + a];
-        for (int32_t k = 0; k < n; ++k) {
-            int64_t off = s.wb_off + (int64_t)k * (n + m) - (int64_t)k * (k - 1) / 2;
-            for (int32_t i = k; i < n; ++i) vals[off + (i - k)] = Ti[(size_t)i * n + k];
-            off += n - k;
-            // interface blocks hold -W_B (backward dot products); interior blocks +W_B
-            const double sg = (s.sub >= 0) ? 1.0 : -1.0;
-            for (int32_t p = 0; p < m; ++p) vals[off + p] = sg * WB[(size_t)p * n + k];
-        }
-        std::vector<double> U((size_t)m * m);
-        for (int32_t b = 0; b < m; ++b)
-            for (int32_t a = b; a < m; ++a) U[(size_t)b * m + a] = F[(size_t)(n + b) * f + n + a];
-        upd[t] = std::move(U);
-        return OK;
-    };
-#pragma omp parallel
-    {
-        std::vector<int32_t> pos(nf, 0);
-#pragma omp for schedule(dynamic, 1)
-        for (int32_t d = 0; d < D; ++d) {
-            for (int32_t t = 0; t < nsn; ++t) {
-                if (SN[t].sub != d) continue;
-                int rc = numeric(t, pos, false);
-                if (rc != OK) {
-#pragma omp critical
-                    err = rc;
-                    break;
-                }
-            }
-        }
-    }
-    if (err != OK) {
-        msg = "non-positive pivot in an interior factor";
-        return err;
-    }
-    {
-        std::vector<int32_t> pos(nf, 0);
-        for (int32_t t = 0; t < nsn; ++t) {
-            if (SN[t].sub >= 0) continue;
-            int rc = numeric(t, pos, true);
-            if (rc != OK) {
-                msg = "non-positive pivot in the interface factor";
-                return rc;
-            }
-        }
     }
 
     // ---- contribution slots ------------------------------------------------------------
@@ -1072,25 +1096,40 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         int32_t kind = 0;
         std::vector<int32_t> desc;
         std::vector<float> data;
+        std::vector<int32_t> src;   // per data word: its FP64 interior value, or -1
+        void word(float w) {
+            data.push_back(w);
+            src.push_back(-1);
+        }
+        void value(const std::vector<double>& v, int64_t o) {
+            data.push_back((float)v[o]);
+            src.push_back((int32_t)o);
+        }
     } cb;
     bool too_big = false;
     auto dwords = [](int32_t kind) { return kind == PULLSUM ? 4 : 8; };
     auto flush = [&]() {
         const int32_t nt_ = (int32_t)cb.desc.size() / dwords(cb.kind);
         if (nt_ == 0) return;
-        while (P.ivals.size() % 4) P.ivals.push_back(0.0f);
+        while (P.ivals.size() % 4) {
+            P.ivals.push_back(0.0f);
+            P.ival_src.push_back(-1);
+        }
         Chunk c;
         c.kind = cb.kind;
         c.ntasks = nt_;
         c.v0 = (int32_t)P.ivals.size();
         for (int32_t v : cb.desc) P.ivals.push_back(as_f(v));
+        P.ival_src.insert(P.ival_src.end(), cb.desc.size(), -1);
         P.ivals.insert(P.ivals.end(), cb.data.begin(), cb.data.end());
+        P.ival_src.insert(P.ival_src.end(), cb.src.begin(), cb.src.end());
         c.nv = (int32_t)P.ivals.size() - c.v0;
         c.pad[0] = c.pad[1] = c.pad[2] = c.pad[3] = 0;
         if (c.nv > chunk_floats) too_big = true;
         P.chunks.push_back(c);
         cb.desc.clear();
         cb.data.clear();
+        cb.src.clear();
     };
     auto room = [&](int32_t need_words) {
         return (int32_t)(cb.desc.size() + cb.data.size()) + need_words <= chunk_floats || cb.desc.empty();
@@ -1100,6 +1139,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         cb.kind = kind;
     };
     P.ivals.clear();
+    P.ival_src.clear();
     P.chunks.clear();
     P.sub_fwd_ch.assign(D + 1, 0);
     P.sub_bwd_ch.assign(D + 1, 0);
@@ -1117,7 +1157,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                     if (L.empty()) continue;
                     if (!room(4 + (int32_t)L.size())) flush();
                     int32_t off = (int32_t)cb.data.size();
-                    for (int32_t sl : L) cb.data.push_back(as_f(sl));
+                    for (int32_t sl : L) cb.word(as_f(sl));
                     int32_t dsc[4] = {SN[t].col0 + a - base, off, (int32_t)L.size(), 0};
                     cb.desc.insert(cb.desc.end(), dsc, dsc + 4);
                 }
@@ -1131,7 +1171,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                 const int32_t nblk_rows = (n + m + 63) / 64;
                 if (!room(8 * nblk_rows + blk)) flush();
                 const int32_t off = (int32_t)cb.data.size();
-                for (int32_t q = 0; q < blk; ++q) cb.data.push_back((float)ivd[S.wb_off + q]);
+                for (int32_t q = 0; q < blk; ++q) cb.value(ivd, S.wb_off + q);
                 for (int32_t rb = 0; rb < nblk_rows; ++rb) {
                     int32_t dsc[8] = {S.col0 - base, n, m, S.m_int, S.cint0, S.cg0, off, 64 * rb};
                     cb.desc.insert(cb.desc.end(), dsc, dsc + 8);
@@ -1159,9 +1199,9 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                 const int32_t nblk_cols = (n + 63) / 64;
                 if (!room(8 * nblk_cols + m + blk)) flush();
                 const int32_t goff = (int32_t)cb.data.size();
-                for (int32_t r : S.rows) cb.data.push_back(as_f(r < P.n_int ? r - base : bpos[r]));
+                for (int32_t r : S.rows) cb.word(as_f(r < P.n_int ? r - base : bpos[r]));
                 const int32_t off = (int32_t)cb.data.size();
-                for (int32_t q = 0; q < blk; ++q) cb.data.push_back((float)ivd[S.wf_off + q]);
+                for (int32_t q = 0; q < blk; ++q) cb.value(ivd, S.wf_off + q);
                 for (int32_t cbk = 0; cbk < nblk_cols; ++cbk) {
                     int32_t dsc[8] = {S.col0 - base, n, m, off, goff, 64 * cbk, 0, 0};
                     cb.desc.insert(cb.desc.end(), dsc, dsc + 8);
@@ -1171,7 +1211,10 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         }
     }
     P.sub_bwd_ch[D] = (int32_t)P.chunks.size();
-    while (P.ivals.size() % 4) P.ivals.push_back(0.0f);
+    while (P.ivals.size() % 4) {
+        P.ivals.push_back(0.0f);
+        P.ival_src.push_back(-1);
+    }
     if (too_big) {
         msg = "an interior supernode's solve block does not fit one LDS chunk";
         return EINVAL_;
@@ -1282,6 +1325,39 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
         }
         close_cphase(ph, tl, P.cbwd);
     }
+    P.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    return OK;
+}
+
+int refactor_plan(Plan& P, const double* X, const int32_t* tets, const double* gamma_s, const double* gamma_v,
+                  std::string& msg) {
+    auto t_start = std::chrono::steady_clock::now();
+    const int32_t nt = P.nt;
+    std::vector<double> Vol(nt), Gd((size_t)nt * 9);
+    for (int32_t e = 0; e < nt; ++e) {
+        const int32_t u = P.elem_perm[e];
+        double Dm[9], G[9];
+        tet_dm(X, tets + 4 * u, Dm);
+        const double det = det3(Dm);
+        inv3(Dm, det, G);
+        Vol[e] = det / 6.0;
+        for (int k = 0; k < 9; ++k) Gd[(size_t)e * 9 + k] = G[k];
+        P.trec[(size_t)e * 16 + 13] = (float)(Vol[e] * gamma_s[u]);
+        P.trec[(size_t)e * 16 + 14] = (float)(Vol[e] * gamma_v[u]);
+    }
+    assemble_matrix(P, Vol, Gd, gamma_s, gamma_v, P.dt);
+    std::vector<double> ivd;
+    try {
+        ivd.assign(P.n_ivd, 0.0);
+    } catch (...) {
+        msg = "host allocation of the factor failed";
+        return ENOMEM_;
+    }
+    std::fill(P.dvals.begin(), P.dvals.end(), 0.0);
+    const int rc = factor_numeric(P, ivd, msg);
+    if (rc != OK) return rc;
+    for (size_t k = 0; k < P.ivals.size(); ++k)
+        if (P.ival_src[k] >= 0) P.ivals[k] = (float)ivd[P.ival_src[k]];
     P.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return OK;
 }

@@ -107,6 +107,12 @@ struct Plan {
     std::vector<CPhase> cfwd, cbwd;
     int32_t n_cgf = 0, n_cgd = 0;                  // global FP32 / FP64 contribution slots
 
+    // refactorization with new stiffness (refactor_plan): the number of FP64
+    // interior values, and for every word of ivals the interior value it
+    // holds as FP32 (-1: a descriptor or index word)
+    int64_t n_ivd = 0;
+    std::vector<int32_t> ival_src;
+
     double seconds = 0;
 };
 
@@ -147,6 +153,13 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                const uint8_t* pinned, const double* gravity, double dt, int32_t pd_iters,
                int32_t n_subdomains, int32_t refine_steps, int32_t leaf_max,
                int32_t chunk_floats, const PlanOptions& opt, Plan& plan, std::string& msg);
+
+// New per-element stiffness for a built plan of the same mesh (X, tets in
+// user order): element weights, matrix values and the numeric factorization
+// are redone; partition, orderings, supernodes and programs are kept, their
+// values refreshed in place.  0 or a negative VH_E* code with msg set.
+int refactor_plan(Plan& P, const double* X, const int32_t* tets, const double* gamma_s, const double* gamma_v,
+                  std::string& msg);
 
 // Rest-shape checks used at mesh creation: every tet has positive volume.
 int check_mesh(const double* X, int32_t nv, const int32_t* tets, int32_t nt, std::string& msg);

@@ -94,6 +94,7 @@ SIGNATURES = {
     "vh_mesh_destroy": (ctypes.c_int, [_vp]),
     "vh_mesh_set_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _dbl, _i32]),
     "vh_mesh_prefactor": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
+    "vh_mesh_refactor": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_mesh_regime_counts": (ctypes.c_int, [_vp, _P(RegimeCounts), _i32, _vp]),
     "vh_mesh_step": (ctypes.c_int, [_vp, _i32, _vp]),
     "vh_mesh_step_noalloc": (ctypes.c_int, [_vp, _i32, _vp]),
@@ -256,6 +257,15 @@ class Mesh:
 
     def prefactor(self, n_subdomains: int, refine_steps: int = 0, precision_mode: int = VH_PRECISION_MIXED):
         _check(_lib.vh_mesh_prefactor(self.h, int(n_subdomains), int(refine_steps), int(precision_mode)))
+
+    def refactor(self, gamma_s, gamma_v):
+        """New per-element stiffness for the prefactored mesh (factor values
+        redone, structure and state kept)."""
+        gs = np.ascontiguousarray(gamma_s, dtype=np.float64)
+        gv = np.ascontiguousarray(gamma_v, dtype=np.float64)
+        if gs.shape != (self.nt,) or gv.shape != (self.nt,):
+            raise ValueError("gamma_s and gamma_v must have shape (nt,)")
+        _check(_lib.vh_mesh_refactor(self.h, _ptr(gs), _ptr(gv)))
 
     def regime_counts(self, reset: bool = False, stream=None) -> dict:
         """Projection regime counters of the local step since the last reset."""

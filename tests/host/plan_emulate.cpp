@@ -38,6 +38,14 @@ void* vhp_build(const double* X, int nv, const int* tets, int nt, const double* 
 
 void vhp_free(void* h) { delete static_cast<Plan*>(h); }
 
+// refactor_plan with new per-element stiffness (X, tets as given to vhp_build)
+void vhp_refactor(void* h, const double* X, const int* tets, const double* gs, const double* gv, int* rc, char* msg,
+                  int msglen) {
+    std::string m;
+    *rc = refactor_plan(*static_cast<Plan*>(h), X, tets, gs, gv, m);
+    std::snprintf(msg, msglen, "%s", m.c_str());
+}
+
 // sizes: n_free, n_int, n_gamma, D, n_sn, n_clevels, nnz_int, nnz_coarse, max_sub_phases,
 // n_chunks, n_ctasks, n_cslots, max_sub_n
 void vhp_info(void* h, long long* out) {

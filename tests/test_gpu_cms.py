@@ -101,6 +101,9 @@ def test_cms_misuse(vh, ctx):
         m.adjoint_forward(x0, v0, 2, 1)                       # the adjoint needs the exact solve
     assert ei.value.code == vh.VH_EINVAL
     with pytest.raises(vh.VHError) as ei:
+        m.refactor(p.gamma_s, p.gamma_v)                      # the modes are rebuilt by prefactor
+    assert ei.value.code == vh.VH_EINVAL
+    with pytest.raises(vh.VHError) as ei:
         ctx.set_config(cms_modes=-1)
     assert ei.value.code == vh.VH_EINVAL
     m.close()

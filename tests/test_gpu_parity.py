@@ -4,6 +4,8 @@ Tolerances: positions within 1e-5 relative L2 per step (FP32 bulk arithmetic);
 per-kernel tolerances follow from FP32 rounding of O(1) quantities (the
 deformation gradient, singular values) scaled by the element weights."""
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -435,6 +437,59 @@ def test_errors_are_reported(vh, ctx):
     with pytest.raises(vh.VHError) as ei:
         ctx.set_config(use_graphs=2)
     assert ei.value.code == vh.VH_EINVAL
+    m.close()
+
+
+@pytest.mark.parametrize("name", ["box", "shell_small"])
+def test_refactor_matches_prefactor(vh, ctx, name):
+    """vh_mesh_refactor with new stiffness gives the factor a fresh prefactor
+    with that stiffness gives: solves and frames bitwise equal, also through
+    the frame graph captured before the refactor; the state is kept."""
+    say(f"[refactor] {name}")
+    p = synth.problem_by_name(name)
+    rng = np.random.default_rng(13)
+    gs2 = p.gamma_s * rng.uniform(0.5, 2.0, p.nt)
+    gv2 = p.gamma_v * rng.uniform(0.5, 2.0, p.nt)
+    a = make_mesh(vh, ctx, p)
+    a.step(2)                                   # captures the frame graph
+    xa, va = a.read_state()
+    a.refactor(gs2, gv2)
+    xk, vk = a.read_state()
+    assert np.array_equal(xk, xa) and np.array_equal(vk, va)
+    b = make_mesh(vh, ctx, p, gamma_s=gs2, gamma_v=gv2)
+    rhs = rng.standard_normal((p.nv, 3))
+    assert np.array_equal(a.debug_solve(rhs), b.debug_solve(rhs))
+    a.write_state(*p.initial_state())
+    a.step(3)
+    b.step(3)
+    xa, va = a.read_state()
+    xb, vb = b.read_state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    sim = oracle.OracleSim.from_problem(dataclasses.replace(p, gamma_s=gs2, gamma_v=gv2))
+    x, v = p.initial_state()
+    for _ in range(3):
+        x, v = sim.step(x, v)
+    assert rel_l2(xa, x) <= 1e-5
+    a.close()
+    b.close()
+
+
+def test_refactor_misuse(vh, ctx):
+    say("[refactor misuse]")
+    p = synth.problem_by_name("box")
+    m = vh.Mesh(ctx, p.X, p.tets)
+    m.set_params(p.gamma_s, p.gamma_v, p.mass, p.pinned, p.gravity, p.dt, 10)
+    with pytest.raises(vh.VHError) as ei:
+        m.refactor(p.gamma_s, p.gamma_v)           # not prefactored
+    assert ei.value.code == vh.VH_ESTATE
+    m.prefactor(4)
+    g = p.gamma_s.copy()
+    g[7] = np.inf
+    with pytest.raises(vh.VHError) as ei:
+        m.refactor(g, p.gamma_v)
+    assert ei.value.code == vh.VH_EINVAL
+    m.refactor(p.gamma_s, p.gamma_v)               # still usable
+    m.step(1)
     m.close()
 
 

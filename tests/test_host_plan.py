@@ -3,6 +3,7 @@ multifrontal factorization, solve programs) through a host emulation of the
 device solve programs, against the oracle's exact sparse solve."""
 
 import ctypes
+import dataclasses
 
 import numpy as np
 import pytest
@@ -87,6 +88,42 @@ def test_long_interior_program(hl):
         assert np.linalg.norm(d[sim.free] - xe) <= 2e-7 * np.linalg.norm(xe)
     finally:
         hl.vhp_free(h)
+
+
+def test_refactor_matches_fresh_plan(hl):
+    """A plan refactored with new stiffness solves exactly as a plan built
+    from scratch with that stiffness (bitwise: the same matrix assembly and
+    numeric factorization over the same supernodes), and matches the oracle's
+    exact solve with the new stiffness."""
+    p = synth.problem_by_name("shell_small")
+    rng = np.random.default_rng(11)
+    gs2 = p.gamma_s * rng.uniform(0.5, 2.0, p.nt)
+    gv2 = p.gamma_v * rng.uniform(0.5, 2.0, p.nt)
+    p2 = dataclasses.replace(p, gamma_s=gs2, gamma_v=gv2)
+    h1, rc, msg, _ = _build(hl, p, 8)
+    assert rc == 0, msg
+    h2, rc, msg, _ = _build(hl, p2, 8)
+    assert rc == 0, msg
+    try:
+        hl.vhp_refactor.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _ci]
+        X = np.ascontiguousarray(p.X, dtype=np.float64)
+        T = np.ascontiguousarray(p.tets, dtype=np.int32)
+        rcv = ctypes.c_int(0)
+        m = ctypes.create_string_buffer(256)
+        hl.vhp_refactor(h1, X.ctypes.data, T.ctypes.data, gs2.ctypes.data, gv2.ctypes.data, ctypes.byref(rcv), m, 256)
+        assert rcv.value == 0, m.value.decode()
+        rhs = np.random.default_rng(12).standard_normal((p.nv, 3))
+        d1 = np.zeros((p.nv, 3))
+        d2 = np.zeros((p.nv, 3))
+        hl.vhp_solve(h1, rhs.ctypes.data, d1.ctypes.data)
+        hl.vhp_solve(h2, rhs.ctypes.data, d2.ctypes.data)
+        assert np.array_equal(d1, d2)
+        sim = oracle.OracleSim.from_problem(p2)
+        xe = sim._solve(rhs[sim.free])
+        assert np.linalg.norm(d1[sim.free] - xe) <= 2e-7 * np.linalg.norm(xe)
+    finally:
+        hl.vhp_free(h1)
+        hl.vhp_free(h2)
 
 
 def test_permutation_is_bijection_free_first(hl):
