@@ -21,6 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvhpd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-mcode-object-version=5",
@@ -44,12 +45,14 @@ def build(verbose: bool = True) -> str:
     o = os.path.join(BUILD, "cms_plan.o")
     _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "cms_plan.cpp"), "-o", o])
     objs.append(o)
-    for src in ("kernels.hip", "api.hip", "serve.hip", "adjoint.hip", "embed.hip", "noalloc.hip", "gn.hip"):
+    for src in ("kernels.hip", "api.hip", "serve.hip", "adjoint.hip", "embed.hip", "noalloc.hip", "gn.hip",
+                "iface_factor.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-mcode-object-version=5", "-shared", "-fPIC", "-o", tmp, *objs, "-lgomp"])
+    _run([HIPCC, f"--offload-arch={ARCH}", "-mcode-object-version=5", "-shared", "-fPIC", "-o", tmp, *objs, "-lgomp",
+          f"-L{ROCM_LIB}", "-lrocsolver", "-lrocblas", f"-Wl,-rpath,{ROCM_LIB}"])
     os.replace(tmp, LIB)
     return LIB
 

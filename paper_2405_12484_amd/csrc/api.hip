@@ -507,6 +507,7 @@ int host_factor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps) {
     opt.lanes64_min = m->ctx->cfg.iface_lanes64_min;
     opt.thin_separators = m->ctx->cfg.thin_separators != 0;
     opt.merge_max_cols = m->ctx->cfg.iface_merge_max_cols;
+    opt.iface_on_device = true;
     int rc = vh::build_plan(m->X.data(), m->nv, m->tets.data(), m->nt, m->gs.data(), m->gv.data(),
                             m->mass.data(), m->pinned.data(), m->g, m->dt, m->iters, n_subdomains,
                             refine_steps, 32, vh::interior_chunk_words(), opt, m->plan, msg);
@@ -566,8 +567,10 @@ int upload_device(vh_mesh* m) {
     d.dt = P.dt;
     for (int c = 0; c < 3; ++c) d.g[c] = P.gravity[c];
     int r = alloc_plan(m);
+    if (r == VH_OK && !P.dvals_ready) r = device_interface_factor(m);
     if (r != VH_OK) {
         free_device(m);
+        if (!m->plan.dvals_ready) m->planned = false;
         return r;
     }
     const size_t nv3 = (size_t)P.nv * 3;
@@ -648,6 +651,7 @@ int vh_ctx_destroy(vh_ctx* ctx) {
     server_destroy(ctx);
     std::vector<vh_mesh*> ms = ctx->meshes;
     for (vh_mesh* m : ms) vh_mesh_destroy(m);
+    blas_destroy(ctx);
     delete ctx;
     return VH_OK;
 }
@@ -764,9 +768,18 @@ int vh_mesh_refactor(vh_mesh* m, const double* gamma_s, const double* gamma_v) {
     VH_HIP(hipDeviceSynchronize());
     VH_HIP(hipMemcpy(d.trec, P.trec.data(), P.trec.size() * sizeof(float), hipMemcpyHostToDevice));
     VH_HIP(hipMemcpy(d.ivals, P.ivals.data(), P.ivals.size() * sizeof(float), hipMemcpyHostToDevice));
-    VH_HIP(hipMemcpy(d.dvals, P.dvals.data(), P.dvals.size() * sizeof(double), hipMemcpyHostToDevice));
     VH_HIP(hipMemcpy(d.K_val, P.K_val.data(), P.K_val.size() * sizeof(double), hipMemcpyHostToDevice));
     free_adjoint(m);
+    if (P.dvals_ready) {
+        VH_HIP(hipMemcpy(d.dvals, P.dvals.data(), P.dvals.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        const int frc = device_interface_factor(m);   // the interface factor on the device, in place
+        if (frc != VH_OK) {
+            free_device(m);
+            m->planned = false;
+            return frc;
+        }
+    }
     return VH_OK;
 }
 

@@ -328,12 +328,53 @@ void lower_inverse(const double* L, int32_t f, int32_t n, std::vector<double>& T
 
 // K on the free unknowns in internal order (CSR, columns ascending):
 // sum_e V_e (gs_e + gv_e) (G_e)_ab plus M/dt^2 on the diagonal (Sec. 7.1).
-// Vol, Gd: per internal element its volume and Dm^{-1} (row-major).
+// Vol, Gd: per internal element its volume and Dm^{-1} (row-major).  The
+// pattern, and the entry each (element, corner pair) adds to, are found once;
+// the values are then summed in element order (a refactorization repeats
+// only that, in the same order).
 void assemble_matrix(Plan& P, const std::vector<double>& Vol, const std::vector<double>& Gd, const double* gamma_s,
                      const double* gamma_v, double dt) {
     const int32_t nf = P.n_free, nt = P.nt;
-
-    std::vector<std::vector<std::pair<int32_t, double>>> rows(nf);
+    if (P.K_pair.empty()) {
+        std::vector<std::vector<int32_t>> rows(nf);
+        for (int32_t e = 0; e < nt; ++e)
+            for (int a = 0; a < 4; ++a) {
+                const int32_t ia = P.tet_soa[(size_t)a * nt + e];
+                if (ia >= nf) continue;
+                for (int b = 0; b < 4; ++b) {
+                    const int32_t ib = P.tet_soa[(size_t)b * nt + e];
+                    if (ib < nf) rows[ia].push_back(ib);
+                }
+            }
+        P.K_ptr.assign(nf + 1, 0);
+        for (int32_t i = 0; i < nf; ++i) {
+            auto& r = rows[i];
+            r.push_back(i);
+            std::sort(r.begin(), r.end());
+            r.erase(std::unique(r.begin(), r.end()), r.end());
+            P.K_ptr[i + 1] = P.K_ptr[i] + (int32_t)r.size();
+        }
+        P.K_col.resize(P.K_ptr[nf]);
+        for (int32_t i = 0; i < nf; ++i) std::copy(rows[i].begin(), rows[i].end(), P.K_col.begin() + P.K_ptr[i]);
+        auto at = [&](int32_t i, int32_t j) {
+            const auto b0 = P.K_col.begin() + P.K_ptr[i], b1 = P.K_col.begin() + P.K_ptr[i + 1];
+            return (int32_t)(std::lower_bound(b0, b1, j) - P.K_col.begin());
+        };
+        P.K_diag.resize(nf);
+        for (int32_t i = 0; i < nf; ++i) P.K_diag[i] = at(i, i);
+        P.K_pair.assign((size_t)nt * 16, -1);
+        for (int32_t e = 0; e < nt; ++e)
+            for (int a = 0; a < 4; ++a) {
+                const int32_t ia = P.tet_soa[(size_t)a * nt + e];
+                if (ia >= nf) continue;
+                for (int b = 0; b < 4; ++b) {
+                    const int32_t ib = P.tet_soa[(size_t)b * nt + e];
+                    if (ib < nf) P.K_pair[(size_t)e * 16 + a * 4 + b] = at(ia, ib);
+                }
+            }
+    }
+    P.K_val.assign(P.K_col.size(), 0.0);
+    for (int32_t i = 0; i < nf; ++i) P.K_val[P.K_diag[i]] = P.mass_int[i] / (dt * dt);
     for (int32_t e = 0; e < nt; ++e) {
         double gr[4][3];
         const double* G = &Gd[(size_t)e * 9];
@@ -341,40 +382,16 @@ void assemble_matrix(Plan& P, const std::vector<double>& Vol, const std::vector<
             gr[0][k] = -(G[0 * 3 + k] + G[1 * 3 + k] + G[2 * 3 + k]);
             for (int c = 1; c < 4; ++c) gr[c][k] = G[(c - 1) * 3 + k];
         }
-        int32_t u = P.elem_perm[e];
-        double w = Vol[e] * (gamma_s[u] + gamma_v[u]);
-        for (int a = 0; a < 4; ++a) {
-            int32_t ia = P.tet_soa[(size_t)a * nt + e];
-            if (ia >= nf) continue;
+        const int32_t u = P.elem_perm[e];
+        const double w = Vol[e] * (gamma_s[u] + gamma_v[u]);
+        const int32_t* kp = &P.K_pair[(size_t)e * 16];
+        for (int a = 0; a < 4; ++a)
             for (int b = 0; b < 4; ++b) {
-                int32_t ib = P.tet_soa[(size_t)b * nt + e];
-                if (ib >= nf) continue;
-                double g = gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2];
-                rows[ia].push_back({ib, w * g});
+                const int32_t k = kp[a * 4 + b];
+                if (k < 0) continue;
+                P.K_val[k] += w * (gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2]);
             }
-        }
     }
-    P.K_ptr.assign(nf + 1, 0);
-    for (int32_t i = 0; i < nf; ++i) {
-        auto& r = rows[i];
-        r.push_back({i, P.mass_int[i] / (dt * dt)});
-        std::sort(r.begin(), r.end(),
-                  [](const auto& a, const auto& b) { return a.first < b.first; });
-        size_t w = 0;
-        for (size_t k = 0; k < r.size(); ++k) {
-            if (w > 0 && r[w - 1].first == r[k].first) r[w - 1].second += r[k].second;
-            else r[w++] = r[k];
-        }
-        r.resize(w);
-        P.K_ptr[i + 1] = P.K_ptr[i] + (int32_t)w;
-    }
-    P.K_col.resize(P.K_ptr[nf]);
-    P.K_val.resize(P.K_ptr[nf]);
-    for (int32_t i = 0; i < nf; ++i)
-        for (size_t k = 0; k < rows[i].size(); ++k) {
-            P.K_col[P.K_ptr[i] + k] = rows[i][k].first;
-            P.K_val[P.K_ptr[i] + k] = rows[i][k].second;
-        }
 }
 
 // Numeric multifrontal FP64 factorization of P's matrix over its supernodes
@@ -497,6 +514,15 @@ int factor_numeric(Plan& P, std::vector<double>& ivd, std::string& msg) {
         msg = "non-positive pivot in an interior factor";
         return err;
     }
+    if (P.iface_on_device) {
+        // the interior contributions to interface fronts wait for the device
+        P.iface_child_upd.assign(nsn, {});
+        for (int32_t t = 0; t < nsn; ++t)
+            if (SN[t].sub >= 0 && SN[t].parent >= 0 && SN[SN[t].parent].sub < 0)
+                P.iface_child_upd[t] = std::move(upd[t]);
+        P.dvals_ready = false;
+        return OK;
+    }
     {
         std::vector<int32_t> pos(nf, 0);
         for (int32_t t = 0; t < nsn; ++t) {
@@ -508,6 +534,7 @@ int factor_numeric(Plan& P, std::vector<double>& ivd, std::string& msg) {
             }
         }
     }
+    P.dvals_ready = true;
     return OK;
 }
 
@@ -1017,6 +1044,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
 
     // ---- numeric: multifrontal FP64 --------------------------------------------------
     P.n_ivd = fo;
+    P.iface_on_device = opt.iface_on_device;
     {
         const int rc = factor_numeric(P, ivd, msg);
         if (rc != OK) return rc;

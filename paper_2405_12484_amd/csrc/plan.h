@@ -86,9 +86,12 @@ struct Plan {
     std::vector<int32_t> part_pack;       // per partial: start << 16 | count
     std::vector<int32_t> vpart_ptr, vpart;  // per free vertex: its partials (ascending)
 
-    // FP64 free-free matrix in internal order (CSR) for refinement residuals
+    // FP64 free-free matrix in internal order (CSR) for refinement residuals;
+    // the entry of each diagonal and each (element, corner a, corner b) pair
+    // of free corners ([nt][4][4], -1 for a pinned corner)
     std::vector<int32_t> K_ptr, K_col;
     std::vector<double> K_val;
+    std::vector<int32_t> K_diag, K_pair;
 
     // factor and solve programs
     std::vector<Supernode> sn;
@@ -112,18 +115,27 @@ struct Plan {
     // holds as FP32 (-1: a descriptor or index word)
     int64_t n_ivd = 0;
     std::vector<int32_t> ival_src;
+    // interface supernodes factored on the device (PlanOptions::iface_on_device):
+    // the update matrices of interior supernodes whose parent is an interface
+    // supernode ([nsn], row-major upper m x m, empty otherwise) are kept for
+    // it, and dvals holds the interface factor only once dvals_ready is set
+    bool iface_on_device = false, dvals_ready = false;
+    std::vector<std::vector<double>> iface_child_upd;
 
     double seconds = 0;
 };
 
 // Plan options.  thin_separators: separator vertices whose neighbours lie
 // under one child only are eliminated inside that child's subtree.
+// iface_on_device: the numeric factorization stops after the interior
+// supernodes (the device factors the interface ones).
 // merge_max_cols: the separators at odd depths join their parent's when the
 // merged block has at most this many columns (0: no merging).  Tuning of the
 // interface programs: a phase whose mean task length is at least lanes32_min
 // (lanes64_min) runs 32 (64) lanes per task, else 16.
 struct PlanOptions {
     bool thin_separators = true;
+    bool iface_on_device = false;   // leave the interface numeric factorization to the device
     int64_t merge_max_cols = 3000;
     int64_t lanes32_min = 96, lanes64_min = 384;
 };

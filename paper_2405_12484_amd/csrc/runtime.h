@@ -59,6 +59,7 @@ struct vh_ctx {
     int device = 0;
     vh_config cfg{1, 96, 384, 1, 3000, 0, 10};
     void* scratch = nullptr;        // device address of the step scratch array (vh_mesh_step_noalloc)
+    void* blas = nullptr;           // rocBLAS handle of the interface factorization (created on first use)
     size_t budget = 0;
     size_t in_use = 0, peak = 0;
     std::vector<vh_mesh*> meshes;
@@ -124,6 +125,11 @@ int host_factor(vh_mesh* m, int32_t n_subdomains, int32_t refine_steps);
 int device_need(vh_mesh* m, size_t* bytes);
 // uploads m->plan, sets the state to rest, builds the mesh's own launch set
 int upload_device(vh_mesh* m);
+// the interface supernodes' numeric factorization on the device (rocSOLVER /
+// rocBLAS FP64) into the resident factor, copied back into the host plan
+int device_interface_factor(vh_mesh* m);
+int blas_handle(vh_ctx* ctx, void** out);
+void blas_destroy(vh_ctx* ctx);
 // frees every device buffer of the mesh (state included)
 void free_device(vh_mesh* m);
 // frees the adjoint checkpoints of the mesh
