@@ -1079,6 +1079,23 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
     }
     P.n_cgf = ncgf;
     P.n_cgd = ncgd;
+    // Slot numbers grouped by the receiving row: each interface row's FP32 and
+    // FP64 slots are contiguous, in its summation order, so an interface
+    // PULLSUM reads two runs and needs no slot list.
+    std::vector<int32_t> fslot(ncgf, -1), dslot(ncgd, -1), fbase(nf, 0), dbase(nf, 0);
+    {
+        int32_t nfs = 0, nds = 0;
+        for (int32_t r = P.n_int; r < nf; ++r) {
+            fbase[r] = nfs;
+            for (int32_t o : pull_f[r]) fslot[o] = nfs++;
+            dbase[r] = nds;
+            for (int32_t o : pull_d[r]) dslot[o] = nds++;
+        }
+        if (nfs != ncgf || nds != ncgd) {
+            msg = "contribution slots not all received by interface rows";
+            return EINVAL_;
+        }
+    }
     P.max_cint = 0;
     for (int32_t d = 0; d < D; ++d) P.max_cint = std::max(P.max_cint, cint_used[d]);
 
@@ -1114,8 +1131,9 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
     };
     // Chunk layouts (32-bit words; ints bit-cast into the float array):
     //   PULLSUM: ntasks x {row, list offset, count, 0}, then the slot lists
-    //   GEMV:    ntasks x {col0, n, m, m_int, cint0, cg0, value offset, row0}, then
-    //            the supernodes' column-major blocks (column k: rows k..n+m-1)
+    //   GEMV:    ntasks x {col0, n, m, m_int, cint0, slot list offset, value
+    //            offset, row0}, then per supernode its column-major block
+    //            (column k: rows k..n+m-1) and the FP32 slots of its interface rows
     //   BGEMV:   ntasks x {col0, n, m, value offset, gather offset, col0 of the
     //            block, 0, 0}, then gather lists and row-major blocks
     // Descriptors are 8 words (PULLSUM uses 4); data offsets are relative to the
@@ -1197,11 +1215,13 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                 const int32_t n = S.n, m = (int32_t)S.rows.size();
                 const int32_t blk = n * (n + 1) / 2 + m * n;
                 const int32_t nblk_rows = (n + m + 63) / 64;
-                if (!room(8 * nblk_rows + blk)) flush();
+                if (!room(8 * nblk_rows + blk + (m - S.m_int))) flush();
                 const int32_t off = (int32_t)cb.data.size();
                 for (int32_t q = 0; q < blk; ++q) cb.value(ivd, S.wb_off + q);
+                const int32_t soff = (int32_t)cb.data.size();   // FP32 slots of the interface rows
+                for (int32_t p = S.m_int; p < m; ++p) cb.word(as_f(fslot[S.cg0 + p - S.m_int]));
                 for (int32_t rb = 0; rb < nblk_rows; ++rb) {
-                    int32_t dsc[8] = {S.col0 - base, n, m, S.m_int, S.cint0, S.cg0, off, 64 * rb};
+                    int32_t dsc[8] = {S.col0 - base, n, m, S.m_int, S.cint0, soff, off, 64 * rb};
                     cb.desc.insert(cb.desc.end(), dsc, dsc + 8);
                 }
             }
@@ -1286,12 +1306,10 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
                 const int32_t r = SN[t].col0 + a;
                 CTask c{};
                 c.a[0] = r - P.n_int;
-                c.a[1] = (int32_t)P.cslots.size();
+                c.a[1] = fbase[r];
                 c.a[2] = (int32_t)pull_f[r].size();
-                P.cslots.insert(P.cslots.end(), pull_f[r].begin(), pull_f[r].end());
-                c.a[3] = (int32_t)P.cslots.size();
+                c.a[3] = dbase[r];
                 c.a[4] = (int32_t)pull_d[r].size();
-                P.cslots.insert(P.cslots.end(), pull_d[r].begin(), pull_d[r].end());
                 tl += c.a[2] + c.a[4];
                 P.ctasks.push_back(c);
             }
@@ -1321,7 +1339,7 @@ int build_plan(const double* X, int32_t nv, const int32_t* tets, int32_t nt,
             for (int32_t i = 0; i < n + m; ++i) {
                 CTask c{};
                 c.a[0] = (i < n) ? 0 : 1;
-                c.a[1] = (i < n) ? S.col0 - P.n_int + i : S.cg0 + (i - n);
+                c.a[1] = (i < n) ? S.col0 - P.n_int + i : dslot[S.cg0 + (i - n)];
                 c.a[2] = (int32_t)(S.wf_off + ((i < n) ? (int64_t)i * (i + 1) / 2 : tri + (int64_t)(i - n) * n));
                 c.a[3] = (i < n) ? i + 1 : n;
                 c.a[4] = S.col0 - P.n_int;

@@ -1204,6 +1204,24 @@ __device__ __forceinline__ Chunk chunk_desc(const Chunk* __restrict__ chunks, co
     return K;
 }
 
+// The start of a subdomain's chunk program, issued at kernel entry so that it
+// overlaps the staging of the subdomain's vectors: the first chunk's load into
+// registers, and the copy of the chunk descriptors into the LDS table.
+struct ChunkStart {
+    Chunk K0;
+    ChunkRegs ra;
+};
+__device__ __forceinline__ void chunk_first(const Chunk* __restrict__ chunks, const float4* __restrict__ iv4,
+                                            int32_t c0, int32_t c1, int4* cd, ChunkStart& st) {
+    if (c0 >= c1) return;
+    st.K0 = chunk_desc_global(chunks, c0);
+    chunk_load(iv4 + st.K0.v0 / 4, (st.K0.nv + 3) / 4, st.ra);
+    for (int32_t c = c0 + (int32_t)threadIdx.x; c < min(c1, c0 + CHD); c += BLKI) {
+        const Chunk K = chunk_desc_global(chunks, c);
+        cd[c - c0] = make_int4(K.kind, K.ntasks, K.v0, K.nv);
+    }
+}
+
 // Runs compute(K, buf, spare) over the chunks c0..c1-1 of one subdomain.
 // Chunk c is computed from LDS buffer (c - c0) & 1 while chunk c + 1 waits in
 // registers for the other buffer (`spare`, free during compute) and the loads
@@ -1211,21 +1229,17 @@ __device__ __forceinline__ Chunk chunk_desc(const Chunk* __restrict__ chunks, co
 // compute to complete.  compute is called by every thread; ends with a barrier.
 template <class F>
 __device__ __forceinline__ void chunk_pipeline(const Chunk* __restrict__ chunks, const float4* __restrict__ iv4,
-                                               int32_t c0, int32_t c1, float* sm, int4* cd, F&& compute) {
-    // the first chunk's descriptor comes straight from global memory, so its
-    // load is in flight while the descriptor table is staged
-    ChunkRegs ra, rb;   // ra: next chunk for buffer 1, rb: next chunk for buffer 0
+                                               int32_t c0, int32_t c1, float* sm, int4* cd, ChunkStart& st,
+                                               F&& compute) {
+    // st: chunk_first's first chunk (registers) and descriptor table (LDS)
     if (c0 >= c1) {
         __syncthreads();   // the caller's LDS writes before the pipeline stay ordered before its reads after
         return;
     }
+    ChunkRegs& ra = st.ra;   // next chunk for buffer 1
+    ChunkRegs rb;            // next chunk for buffer 0
     const int32_t last = c1 - 1;
-    Chunk K0 = chunk_desc_global(chunks, c0);
-    chunk_load(iv4 + K0.v0 / 4, (K0.nv + 3) / 4, ra);
-    for (int32_t c = c0 + (int32_t)threadIdx.x; c < min(c1, c0 + CHD); c += BLKI) {
-        const Chunk K = chunk_desc_global(chunks, c);
-        cd[c - c0] = make_int4(K.kind, K.ntasks, K.v0, K.nv);
-    }
+    Chunk K0 = st.K0;
     __syncthreads();
     float* buf0 = sm;
     float* buf1 = sm + CHI;
@@ -1286,12 +1300,16 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
     const int32_t base = as_global(a.sub_off)[d];
     const int32_t n_loc = as_global(a.sub_off)[d + 1] - base;
     const int tid = threadIdx.x;
-    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)as_global(a.r)[3 * base + i];
     const int32_t c0 = as_global(a.sub_fwd_ch)[d], c1 = as_global(a.sub_fwd_ch)[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
+    // the residual first: loads complete in issue order, so the chunk's loads
+    // issued after it stay in flight while it is converted and stored
+    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)as_global(a.r)[3 * base + i];
+    ChunkStart st;
+    chunk_first(a.chunks, iv4, c0, c1, cd, st);
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
-    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, [&](const Chunk& K, const float* cur, float*) {
+    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, st, [&](const Chunk& K, const float* cur, float*) {
         const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
         if (K.kind == PULLSUM) {
             const int32_t* idat = desc + 4 * K.ntasks;
@@ -1340,7 +1358,8 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
                     op[1] = s1;
                     op[2] = s2;
                 } else {
-                    VH_GLOBAL float* op = as_global(a.cgf) + 3 * (size_t)(q[5] + i - n - mi);
+                    const int32_t slot = reinterpret_cast<const int32_t*>(dat)[q[5] + i - n - mi];
+                    VH_GLOBAL float* op = as_global(a.cgf) + 3 * (size_t)slot;
                     op[0] = s0;
                     op[1] = s1;
                     op[2] = s2;
@@ -1352,7 +1371,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
 }
 
 // Interface phases, one group of G lanes per task (FP64).
-//   PULLSUM: rg[row] = r[row] - sum FP32 slots - sum FP64 slots
+//   PULLSUM: rg[row] = r[row] - sum of its FP32 slots - sum of its FP64 slots
 //   GEMV:    zg[idx], cgd[idx] or (a root, rows of Ti^T Ti) dg[idx] = row . rg
 //   BGEMV:   dg[out] = Ti column . zg + (-W_B) column . dg[gather]
 template <int G>
@@ -1374,16 +1393,16 @@ __global__ __launch_bounds__(BLK, 8) void k_coarse(const DevMesh* __restrict__ G
     }
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     if (kind == PULLSUM) {
-        const VH_GLOBAL int32_t* lf = as_global(a.cslots) + T.a[1];
+        // the row's slots are two contiguous runs (FP32 from the interiors,
+        // FP64 from interface supernodes)
         for (int32_t k = lane; k < T.a[2]; k += G) {
-            const VH_GLOBAL float* cp = as_global(a.cgf) + 3 * (size_t)lf[k];
+            const VH_GLOBAL float* cp = as_global(a.cgf) + 3 * ((size_t)T.a[1] + k);
             s0 += (double)cp[0];
             s1 += (double)cp[1];
             s2 += (double)cp[2];
         }
-        const VH_GLOBAL int32_t* ld = as_global(a.cslots) + T.a[3];
         for (int32_t k = lane; k < T.a[4]; k += G) {
-            const VH_GLOBAL double* cp = as_global(a.cgd) + 3 * (size_t)ld[k];
+            const VH_GLOBAL double* cp = as_global(a.cgd) + 3 * ((size_t)T.a[3] + k);
             s0 += cp[0];
             s1 += cp[1];
             s2 += cp[2];
@@ -1502,6 +1521,10 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
     const int32_t n_loc = as_global(a.sub_off)[d + 1] - base;
     const int32_t b0 = as_global(a.bnd_off)[d], nb = as_global(a.bnd_off)[d + 1] - b0;
     const int tid = threadIdx.x;
+    const int32_t c0 = as_global(a.sub_bwd_ch)[d], c1 = as_global(a.sub_bwd_ch)[d + 1];
+    const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
+    ChunkStart st;
+    chunk_first(a.chunks, iv4, c0, c1, cd, st);
     for (int32_t i = tid; i < 3 * n_loc; i += BLKI) Z[i] = as_global(a.zf)[3 * base + i];
     for (int32_t i = tid; i < 3 * nb; i += BLKI) {
         const int32_t k = i / 3, c = i - 3 * k;
@@ -1546,11 +1569,9 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
             if (apply) store_global4(a.u + gi, du[0], du[1], du[2], 0.0f);
         }
     }
-    const int32_t c0 = as_global(a.sub_bwd_ch)[d], c1 = as_global(a.sub_bwd_ch)[d + 1];
-    const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
-    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, [&](const Chunk& K, const float* cur, float* spare) {
+    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, st, [&](const Chunk& K, const float* cur, float* spare) {
         const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
         const float* dat = cur + 8 * K.ntasks;
         const int32_t* idat = reinterpret_cast<const int32_t*>(dat);
@@ -1582,7 +1603,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
                 }
                 const float* wb = w + n * (n + 1) / 2;
                 const int32_t* g = idat + q[4];
-#pragma unroll 2
+#pragma unroll 4
                 for (int32_t p = j + lpc * sub; p < m; p += stride) {
                     const float v = wb[p * n];
                     const float* xp = DL + 3 * g[p];

@@ -46,7 +46,7 @@ struct Chunk {
 };
 
 // Interface task (global memory, FP64 values):
-//   PULLSUM: {row, FP32-slot list offset, count, FP64-slot list offset, count}
+//   PULLSUM: {row, first FP32 slot, count, first FP64 slot, count} (a row's slots are contiguous)
 //   GEMV:    {dest (0 z, 1 FP64 slot, 2 solution d), index, value offset, len, x offset}
 //            (dest 2: a root supernode, whose rows of A = Ti^T Ti give d at once)
 //   BGEMV:   {out, value offset, len1, z offset, len2, gather list offset}
@@ -106,7 +106,7 @@ struct Plan {
     // interface: FP64 values and one launch per phase
     std::vector<double> dvals;
     std::vector<CTask> ctasks;
-    std::vector<int32_t> cslots, cgidx;            // contribution slot lists, gather lists
+    std::vector<int32_t> cslots, cgidx;            // (unused: slots are contiguous per row), gather lists
     std::vector<CPhase> cfwd, cbwd;
     int32_t n_cgf = 0, n_cgd = 0;                  // global FP32 / FP64 contribution slots
 

@@ -95,7 +95,7 @@ void vhp_solve(void* h, const double* rhs, double* d) {
                         r[word(q)] -= acc;
                     } else {
                         const int col0 = word(q), n = word(q + 1), m = word(q + 2), mi = word(q + 3),
-                                  ci0 = word(q + 4), cg0 = word(q + 5), off = word(q + 6), row0 = word(q + 7);
+                                  ci0 = word(q + 4), so = word(q + 5), off = word(q + 6), row0 = word(q + 7);
                         for (int i = row0; i < std::min(row0 + 64, n + m); ++i) {
                             double acc = 0.0;
                             long co = 0;
@@ -106,7 +106,7 @@ void vhp_solve(void* h, const double* rhs, double* d) {
                             }
                             if (i < n) z[col0 + i] = acc;
                             else if (i < n + mi) C[ci0 + i - n] = (double)(float)acc;
-                            else CGF[cg0 + i - n - mi] = (double)(float)acc;
+                            else CGF[word(dat + so + i - n - mi)] = (double)(float)acc;
                         }
                     }
                 }
@@ -120,8 +120,8 @@ void vhp_solve(void* h, const double* rhs, double* d) {
                 const int32_t* a = P.ctasks[t].a;
                 if (ph.kind == PULLSUM) {
                     double acc = 0.0;
-                    for (int k = 0; k < a[2]; ++k) acc += CGF[P.cslots[a[1] + k]];
-                    for (int k = 0; k < a[4]; ++k) acc += CGD[P.cslots[a[3] + k]];
+                    for (int k = 0; k < a[2]; ++k) acc += CGF[a[1] + k];
+                    for (int k = 0; k < a[4]; ++k) acc += CGD[a[3] + k];
                     rg[a[0]] = Rc[nint + a[0]] - acc;
                 } else {
                     double acc = 0.0;
