@@ -1027,6 +1027,45 @@ __global__ __launch_bounds__(LBLK) void k_gn_bd(const DevMesh* __restrict__ GM, 
     }
 }
 
+// (K x)_i over the FP64 CSR matrix for the three components of x ([n][3]):
+// four entries per round have their columns, values and gathered x in flight
+// together; the products are added in entry order.
+__device__ __forceinline__ void csr_row3(const int32_t* __restrict__ Kp, const int32_t* __restrict__ Kc,
+                                         const double* __restrict__ Kv, const double* __restrict__ x, int32_t i,
+                                         double& s0, double& s1, double& s2) {
+    int32_t t = Kp[i];
+    const int32_t t1 = Kp[i + 1];
+    for (; t + 3 < t1; t += 4) {
+        const int32_t c0 = Kc[t], c1 = Kc[t + 1], c2 = Kc[t + 2], c3 = Kc[t + 3];
+        const double v0 = Kv[t], v1 = Kv[t + 1], v2 = Kv[t + 2], v3 = Kv[t + 3];
+        const double* q0 = x + 3 * (size_t)c0;
+        const double* q1 = x + 3 * (size_t)c1;
+        const double* q2 = x + 3 * (size_t)c2;
+        const double* q3 = x + 3 * (size_t)c3;
+        const double a0 = q0[0], a1 = q0[1], a2 = q0[2], b0 = q1[0], b1 = q1[1], b2 = q1[2];
+        const double e0 = q2[0], e1 = q2[1], e2 = q2[2], g0 = q3[0], g1 = q3[1], g2 = q3[2];
+        s0 += v0 * a0;
+        s1 += v0 * a1;
+        s2 += v0 * a2;
+        s0 += v1 * b0;
+        s1 += v1 * b1;
+        s2 += v1 * b2;
+        s0 += v2 * e0;
+        s1 += v2 * e1;
+        s2 += v2 * e2;
+        s0 += v3 * g0;
+        s1 += v3 * g1;
+        s2 += v3 * g2;
+    }
+    for (; t < t1; ++t) {
+        const double v = Kv[t];
+        const double* q = x + 3 * (size_t)Kc[t];
+        s0 += v * q[0];
+        s1 += v * q[1];
+        s2 += v * q[2];
+    }
+}
+
 // out = K v - geo on the free rows (FP64; K over the free-free block)
 __global__ __launch_bounds__(BLK) void k_gn_av(const DevMesh* __restrict__ GM, const double* __restrict__ v,
                                                const double* __restrict__ geo, double* __restrict__ out) {
@@ -1034,13 +1073,7 @@ __global__ __launch_bounds__(BLK) void k_gn_av(const DevMesh* __restrict__ GM, c
     const int32_t i = blockIdx.x * BLK + threadIdx.x;
     if (i >= M.n_free) return;
     double s0 = 0, s1 = 0, s2 = 0;
-    for (int32_t k = M.K_ptr[i]; k < M.K_ptr[i + 1]; ++k) {
-        const double kv = M.K_val[k];
-        const double* vp = v + 3 * M.K_col[k];
-        s0 += kv * vp[0];
-        s1 += kv * vp[1];
-        s2 += kv * vp[2];
-    }
+    csr_row3(M.K_ptr, M.K_col, M.K_val, v, i, s0, s1, s2);
     out[3 * i] = s0 - geo[3 * i];
     out[3 * i + 1] = s1 - geo[3 * i + 1];
     out[3 * i + 2] = s2 - geo[3 * i + 2];
@@ -1685,13 +1718,7 @@ __global__ __launch_bounds__(BLK) void k_refine(const DevMesh* __restrict__ GM, 
     const int32_t i = sl.lb * BLK + threadIdx.x;
     if (i >= n_free) return;
     double s0 = 0, s1 = 0, s2 = 0;
-    for (int32_t k = Kp[i]; k < Kp[i + 1]; ++k) {
-        const double v = Kv[k];
-        const double* dp = delta + 3 * Kc[k];
-        s0 += v * dp[0];
-        s1 += v * dp[1];
-        s2 += v * dp[2];
-    }
+    csr_row3(Kp, Kc, Kv, delta, i, s0, s1, s2);
     r[3 * i] -= s0;
     r[3 * i + 1] -= s1;
     r[3 * i + 2] -= s2;
@@ -1821,13 +1848,7 @@ __global__ __launch_bounds__(BLK) void k_cms_sweep(const DevMesh* __restrict__ G
     const double* xp = (k == 0) ? B[0] : B[(k + 2) % 3];
     double* xn = B[(k + 1) % 3];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int32_t t = M.K_ptr[i]; t < M.K_ptr[i + 1]; ++t) {
-        const double v = M.K_val[t];
-        const double* q = xk + 3 * (size_t)M.K_col[t];
-        s0 += v * q[0];
-        s1 += v * q[1];
-        s2 += v * q[2];
-    }
+    csr_row3(M.K_ptr, M.K_col, M.K_val, xk, i, s0, s1, s2);
     const double id = M.cms_invd[i], om = M.cms_omega[k];
     const double* rr = M.r + 3 * (size_t)i;
     const double h0 = xk[3 * i] + id * (rr[0] - s0);
