@@ -215,7 +215,7 @@ int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_d
     ProfScope ps(m, s, 5);
     if (L.cms_modes > 0) {
         // the inexact CMS solve: interiors from the modes, then the sweeps
-        VH_HIP(vh::launch_cms_back(with_record(L.ibwd, G), L.lds_cms, s));
+        VH_HIP(vh::launch_cms_back(with_record(L.ibwd, G), L.lds_cms, L.cms_modes, s));
         VH_HIP(vh::launch_cms_iface(with_record(L.refine, G), s));
         for (int32_t k = 0; k < L.cms_sweeps; ++k) VH_HIP(vh::launch_cms_sweep(with_record(L.refine, G), k, s));
         VH_HIP(vh::launch_cms_apply(with_record(L.refine, G), L.cms_sweeps, apply, s));

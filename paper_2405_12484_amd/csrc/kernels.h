@@ -108,7 +108,7 @@ hipError_t launch_refine_residual(const LaunchRef& r, hipStream_t s);
 // k, and the final correction to delta (with apply: x += d) (tables over the
 // free rows, like refine)
 size_t cms_back_lds(int32_t max_n, int32_t max_nb, int32_t modes);
-hipError_t launch_cms_back(const LaunchRef& r, size_t lds, hipStream_t s);
+hipError_t launch_cms_back(const LaunchRef& r, size_t lds, int32_t modes, hipStream_t s);
 hipError_t launch_cms_iface(const LaunchRef& r, hipStream_t s);
 hipError_t launch_cms_sweep(const LaunchRef& r, int32_t k, hipStream_t s);
 hipError_t launch_cms_apply(const LaunchRef& r, int32_t sweeps, bool apply, hipStream_t s);

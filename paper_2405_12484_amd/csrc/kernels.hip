@@ -1738,37 +1738,39 @@ __global__ __launch_bounds__(BLK) void k_refine(const DevMesh* __restrict__ GM, 
 constexpr int BLKC = 256;
 constexpr int kCmsSlices = 8;          // workgroups per subdomain in k_cms_back
 
-// q_d = Lambda_d^{-1} Phi_d^T b_d^i, one workgroup per subdomain, one mode per
-// wave at a time (lanes over the rows), to cms_q [D][modes][3]
+// q_d = Lambda_d^{-1} Phi_d^T b_d^i, `groups` workgroups per subdomain (table
+// entry blockIdx.x / groups), one mode per wave (lanes over the rows), to
+// cms_q [D][modes][3]
 __global__ __launch_bounds__(BLKC) void k_cms_modes(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
-                                                    const int32_t* __restrict__ active) {
-    Slot sl;
-    if (!slot_of(L, active, sl)) return;
-    const DevMesh& M = GM[sl.g];
-    const int32_t d = sl.lb;
+                                                    const int32_t* __restrict__ active, int32_t groups) {
+    const int4 ent = reinterpret_cast<const int4*>(L)[blockIdx.x / groups];
+    if (active[ent.x] == 0) return;
+    const DevMesh& M = GM[ent.x];
+    const int32_t d = ent.y;
     const int32_t r0 = M.sub_off[d], n = M.sub_off[d + 1] - r0;
     const int32_t R = M.cms_modes;
     const float* phi = M.cms_phi + M.cms_phi_off[d];
     const double* rb = M.r + 3 * (size_t)r0;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int32_t k = wave; k < R; k += BLKC / 64) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int32_t i = lane; i < n; i += 64) {
-            const double f = (double)phi[(size_t)k * n + i];
-            s0 += f * rb[3 * i];
-            s1 += f * rb[3 * i + 1];
-            s2 += f * rb[3 * i + 2];
-        }
-        s0 = group_sum<64>(s0);
-        s1 = group_sum<64>(s1);
-        s2 = group_sum<64>(s2);
-        if (lane == 0) {
-            const double il = (double)M.cms_ilam[(size_t)d * R + k];
-            double* q = M.cms_q + 3 * ((size_t)d * R + k);
-            q[0] = s0 * il;
-            q[1] = s1 * il;
-            q[2] = s2 * il;
-        }
+    const int32_t k = (int32_t)(blockIdx.x % groups) * (BLKC / 64) + wave;   // this wave's mode
+    if (k >= R) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
+    for (int32_t i = lane; i < n; i += 64) {
+        const double f = (double)phi[(size_t)k * n + i];
+        s0 += f * rb[3 * i];
+        s1 += f * rb[3 * i + 1];
+        s2 += f * rb[3 * i + 2];
+    }
+    s0 = group_sum<64>(s0);
+    s1 = group_sum<64>(s1);
+    s2 = group_sum<64>(s2);
+    if (lane == 0) {
+        const double il = (double)M.cms_ilam[(size_t)d * R + k];
+        double* q = M.cms_q + 3 * ((size_t)d * R + k);
+        q[0] = s0 * il;
+        q[1] = s1 * il;
+        q[2] = s2 * il;
     }
 }
 
@@ -1801,12 +1803,14 @@ __global__ __launch_bounds__(BLKC) void k_cms_back(const DevMesh* __restrict__ G
     const float* psi = M.cms_psi + M.cms_psi_off[d];
     for (int32_t i = i0 + tid; i < i1; i += BLKC) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
         for (int32_t k = 0; k < R; ++k) {
             const double f = (double)phi[(size_t)k * n + i];
             s0 += f * Q[3 * k];
             s1 += f * Q[3 * k + 1];
             s2 += f * Q[3 * k + 2];
         }
+#pragma unroll 8
         for (int32_t j = 0; j < nb; ++j) {
             const double f = (double)psi[(size_t)j * n + i];
             s0 += f * XB[3 * j];
@@ -2007,9 +2011,10 @@ size_t cms_back_lds(int32_t max_n, int32_t max_nb, int32_t modes) {
     return sizeof(double) * 3 * ((size_t)max_nb + (size_t)modes);
 }
 
-hipError_t launch_cms_back(const LaunchRef& r, size_t lds, hipStream_t s) {
+hipError_t launch_cms_back(const LaunchRef& r, size_t lds, int32_t modes, hipStream_t s) {
     if (r.nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cms_modes, dim3(r.nblocks), dim3(BLKC), 0, s, r.G, r.L, r.active);
+    const int32_t groups = (modes + BLKC / 64 - 1) / (BLKC / 64);
+    hipLaunchKernelGGL(k_cms_modes, dim3(r.nblocks * groups), dim3(BLKC), 0, s, r.G, r.L, r.active, groups);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cms_back, dim3(r.nblocks * kCmsSlices), dim3(BLKC), lds, s, r.G, r.L, r.active);
