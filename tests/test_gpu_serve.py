@@ -216,6 +216,76 @@ def test_serving_sizes_span_is_bitwise_alone(vh):
         assert np.array_equal(mixed[i], alone[i]), i
 
 
+def test_mix_with_refinement_is_bitwise_plain(vh, probs):
+    """Two garments served together with one refinement step per PD
+    iteration (the FP64 residual and a second decomposed solve inside the
+    batched frame) end bitwise where plain stepping with the same refinement
+    ends."""
+    say("[serve] mix with refinement")
+    which = [0, 1]
+    ctx = vh.Context(0)
+    srv = vh.Server(ctx, "batched", 2)
+    ms = {}
+    for g in which:
+        ms[g] = new_mesh(vh, ctx, probs[g])
+        srv.add(ms[g], probs[g].n_subdomains, 1)
+    tickets = [srv.submit(ms[g], n) for g in which for n in REQUESTS[g]]
+    srv.drain()
+    assert all(srv.poll(t)[0] for t in tickets)
+    out = {g: ms[g].read_state() for g in which}
+    assert srv.stats()["mean_batch"] > 1.0
+    srv.close()
+    for m in ms.values():
+        m.close()
+    ctx.close()
+    for g in which:
+        p = probs[g]
+        c2 = vh.Context(0)
+        m = new_mesh(vh, c2, p)
+        m.prefactor(p.n_subdomains, 1)
+        m.step(sum(REQUESTS[g]))
+        x, v = m.read_state()
+        m.close()
+        c2.close()
+        assert np.array_equal(out[g][0], x), g
+        assert np.array_equal(out[g][1], v), g
+
+
+def test_mix_with_cms_solve_is_bitwise_plain(vh, probs):
+    """Two garments served together with the inexact CMS global solve (8
+    interior modes, 4 sweeps) end bitwise where plain stepping with the same
+    solve ends."""
+    say("[serve] mix with the CMS solve")
+    which = [0, 1]
+    ctx = vh.Context(0)
+    ctx.set_config(cms_modes=8, cms_sweeps=4)
+    srv = vh.Server(ctx, "batched", 2)
+    ms = {}
+    for g in which:
+        ms[g] = new_mesh(vh, ctx, probs[g])
+        srv.add(ms[g], probs[g].n_subdomains)
+    tickets = [srv.submit(ms[g], n) for g in which for n in REQUESTS[g]]
+    srv.drain()
+    assert all(srv.poll(t)[0] for t in tickets)
+    out = {g: ms[g].read_state() for g in which}
+    srv.close()
+    for m in ms.values():
+        m.close()
+    ctx.close()
+    for g in which:
+        p = probs[g]
+        c2 = vh.Context(0)
+        c2.set_config(cms_modes=8, cms_sweeps=4)
+        m = new_mesh(vh, c2, p)
+        m.prefactor(p.n_subdomains)
+        m.step(sum(REQUESTS[g]))
+        x, v = m.read_state()
+        m.close()
+        c2.close()
+        assert np.array_equal(out[g][0], x), g
+        assert np.array_equal(out[g][1], v), g
+
+
 def test_sequential_mode_is_bitwise_alone(vh, probs, alone):
     say("[serve] sequential mix")
     out, st = serve(vh, probs, [0, 1, 2], mode="sequential", order_seed=5)
