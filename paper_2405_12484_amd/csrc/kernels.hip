@@ -1335,8 +1335,8 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
     const int tid = threadIdx.x;
     const int32_t c0 = as_global(a.sub_fwd_ch)[d], c1 = as_global(a.sub_fwd_ch)[d + 1];
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
-    // the residual first: loads complete in issue order, so the chunk's loads
-    // issued after it stay in flight while it is converted and stored
+    // the residual is staged before the chunk program starts: vector loads
+    // complete in issue order, so chunk loads issued first would hold it up
     for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)as_global(a.r)[3 * base + i];
     ChunkStart st;
     chunk_first(a.chunks, iv4, c0, c1, cd, st);
