@@ -359,6 +359,12 @@ int vh_debug_residual(vh_mesh* mesh, const double* x, const double* y, double* r
  * more than 64 colours would be needed. */
 int vh_debug_scatter_colored(vh_mesh* mesh, const double* x, double* f, int32_t* n_colors);
 
+/* The resident interface factor values (the FP64 blocks of the interface
+ * supernodes the interface phases read: rows of [Ti; W_B] and columns of
+ * [Ti; -W_B], or a root's A = Ti^T Ti), copied from the device.  With out ==
+ * NULL, *count receives their number; otherwise *count must equal it. */
+int vh_debug_interface_factor(vh_mesh* mesh, double* out, int64_t* count);
+
 /* Solve K_ff d = rhs with the decomposed solver; rhs and d are [nv][3]
  * (pinned rows ignored on input, 0 on output). */
 int vh_debug_solve(vh_mesh* mesh, const double* rhs, double* d);

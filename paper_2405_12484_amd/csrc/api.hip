@@ -1016,6 +1016,21 @@ int vh_debug_residual(vh_mesh* m, const double* x, const double* y, double* r) {
     return get_user(m, d.r, r, d.n_free, nullptr);
 }
 
+int vh_debug_interface_factor(vh_mesh* m, double* out, int64_t* count) {
+    VH_TRY(check_solo(m));
+    if (!count) return fail(VH_EINVAL, "null argument");
+    const int64_t n = (int64_t)m->plan.dvals.size();
+    if (!out) {
+        *count = n;
+        return VH_OK;
+    }
+    if (*count != n) return fail(VH_EINVAL, "count must equal the number of interface factor values");
+    VH_TRY(set_device(m));
+    VH_HIP(hipDeviceSynchronize());
+    if (n > 0) VH_HIP(hipMemcpy(out, m->dm.dvals, (size_t)n * sizeof(double), hipMemcpyDeviceToHost));
+    return VH_OK;
+}
+
 int vh_debug_solve(vh_mesh* m, const double* rhs, double* out) {
     VH_TRY(check_solo(m));
     if (!rhs || !out) return fail(VH_EINVAL, "null argument");

@@ -109,6 +109,7 @@ SIGNATURES = {
     "vh_debug_local_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vh_debug_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_debug_scatter_colored": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "vh_debug_interface_factor": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_debug_solve": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_mesh_set_embedding": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
     "vh_mesh_embed": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -413,6 +414,14 @@ class Mesh:
         nc = ctypes.c_int32(0)
         _check(_lib.vh_debug_scatter_colored(self.h, _ptr(x), _ptr(f), ctypes.byref(nc)))
         return f, int(nc.value)
+
+    def debug_interface_factor(self):
+        """The resident interface factor values (FP64), in the plan's layout."""
+        n = ctypes.c_int64(0)
+        _check(_lib.vh_debug_interface_factor(self.h, None, ctypes.byref(n)))
+        out = np.empty(n.value, dtype=np.float64)
+        _check(_lib.vh_debug_interface_factor(self.h, _ptr(out), ctypes.byref(n)))
+        return out
 
     def debug_solve(self, rhs):
         rhs = np.ascontiguousarray(rhs, dtype=np.float64)

@@ -38,6 +38,14 @@ void* vhp_build(const double* X, int nv, const int* tets, int nt, const double* 
 
 void vhp_free(void* h) { delete static_cast<Plan*>(h); }
 
+// the plan's interface factor values (host FP64 numeric factorization); their
+// number, copied to out when it is not NULL
+long long vhp_dvals(void* h, double* out) {
+    const Plan& P = *static_cast<Plan*>(h);
+    if (out) std::memcpy(out, P.dvals.data(), P.dvals.size() * sizeof(double));
+    return (long long)P.dvals.size();
+}
+
 // refactor_plan with new per-element stiffness (X, tets as given to vhp_build)
 void vhp_refactor(void* h, const double* X, const int* tets, const double* gs, const double* gv, int* rc, char* msg,
                   int msglen) {

@@ -440,13 +440,16 @@ def test_errors_are_reported(vh, ctx):
     m.close()
 
 
-@pytest.mark.parametrize("name", ["box", "shell_small"])
-def test_refactor_matches_prefactor(vh, ctx, name):
+@pytest.mark.parametrize("name,D", [("box", None), ("box", 1), ("shell_small", None)])
+def test_refactor_matches_prefactor(vh, ctx, name, D):
     """vh_mesh_refactor with new stiffness gives the factor a fresh prefactor
     with that stiffness gives: solves and frames bitwise equal, also through
-    the frame graph captured before the refactor; the state is kept."""
-    say(f"[refactor] {name}")
+    the frame graph captured before the refactor; the state is kept.  (D = 1:
+    one subdomain, no interface supernodes.)"""
+    say(f"[refactor] {name} D={D}")
     p = synth.problem_by_name(name)
+    if D is not None:
+        p = dataclasses.replace(p, n_subdomains=D)
     rng = np.random.default_rng(13)
     gs2 = p.gamma_s * rng.uniform(0.5, 2.0, p.nt)
     gv2 = p.gamma_v * rng.uniform(0.5, 2.0, p.nt)
@@ -472,6 +475,47 @@ def test_refactor_matches_prefactor(vh, ctx, name):
     assert rel_l2(xa, x) <= 1e-5
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("name,D", [("box", 4), ("shell_small", 8), ("slab", 8)])
+def test_device_interface_factor_matches_host(vh, ctx, name, D):
+    """The interface supernodes factored on the device (rocSOLVER / rocBLAS)
+    against the host's FP64 multifrontal factorization of the same plan (the
+    test library builds it with the host path): every stored value of the
+    blocks the interface phases read, Ti, W_B and the root's Ti^T Ti."""
+    import ctypes
+    from tests.host import build as hbuild
+    say(f"[device factor] {name} D={D}")
+    p = synth.problem_by_name(name)
+    m = make_mesh(vh, ctx, p, n_subdomains=D)
+    dev = m.debug_interface_factor()
+    m.close()
+    hl = ctypes.CDLL(hbuild.ensure())
+    vp, ci = ctypes.c_void_p, ctypes.c_int
+    hl.vhp_build.restype = vp
+    hl.vhp_build.argtypes = [vp, ci, vp, ci, vp, vp, vp, vp, vp, ctypes.c_double, ci, ci, ci, ci, vp, vp, ci]
+    hl.vhp_dvals.restype = ctypes.c_longlong
+    hl.vhp_dvals.argtypes = [vp, vp]
+    hl.vhp_free.argtypes = [vp]
+    a = lambda x, t: np.ascontiguousarray(x, dtype=t)
+    keep = [a(p.X, np.float64), a(p.tets, np.int32), a(p.gamma_s, np.float64), a(p.gamma_v, np.float64),
+            a(p.mass, np.float64), a(p.pinned, np.uint8), a(p.gravity, np.float64)]
+    rc = ctypes.c_int(0)
+    msg = ctypes.create_string_buffer(256)
+    h = hl.vhp_build(keep[0].ctypes.data, p.nv, keep[1].ctypes.data, p.nt, keep[2].ctypes.data,
+                     keep[3].ctypes.data, keep[4].ctypes.data, keep[5].ctypes.data, keep[6].ctypes.data,
+                     p.dt, p.pd_iters, D, 0, 32, ctypes.byref(rc), msg, 256)
+    assert rc.value == 0, msg.value.decode()
+    try:
+        n = hl.vhp_dvals(h, None)
+        host = np.empty(n)
+        hl.vhp_dvals(h, host.ctypes.data)
+    finally:
+        hl.vhp_free(h)
+    assert dev.shape == host.shape and dev.size > 0
+    err = np.abs(dev - host).max() / np.abs(host).max()
+    say(f"[device factor] {name}: {dev.size} values, max |device - host| / max |host| = {err:.2e}")
+    assert err <= 1e-13
 
 
 def test_refactor_misuse(vh, ctx):
