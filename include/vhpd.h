@@ -236,9 +236,11 @@ int vh_mesh_regime_counts(vh_mesh* mesh, vh_regime_counts* out, int32_t reset, v
 
 /* Per-kernel timing with HIP events recorded on the step's stream around each
  * launch group of a kernel class (bit c of class_mask enables class c):
- *   0 predictor, 1 local step, 2 residual gather, 3 interior forward solve,
- *   4 interface solve (all tree levels), 5 interior backward solve + update,
- *   6 refinement residual, 7 velocity.
+ *   0 predictor, 1 local step, 2 (unused: the PD iterations form the residual
+ *   inside the interior forward solve), 3 interior forward solve (with the
+ *   residual gather of the PD iteration, when it forms it), 4 interface solve
+ *   (all tree levels), 5 interior backward solve + update, 6 refinement
+ *   residual, 7 velocity.
  * vh_mesh_profile resets the record and sets the mask (0 = off);
  * vh_mesh_profile_read synchronises and returns, per class, the summed
  * milliseconds ms[8] and the number of timed groups launches[8] since then. */
@@ -246,11 +248,13 @@ int vh_mesh_regime_counts(vh_mesh* mesh, vh_regime_counts* out, int32_t reset, v
 int vh_mesh_profile(vh_mesh* mesh, uint32_t class_mask);
 int vh_mesh_profile_read(vh_mesh* mesh, double* ms, int64_t* launches);
 
-/* Launch one kernel class (1 local step, 2 residual gather, 3 interior
- * forward, 4 all interface phases of one solve, 5 interior backward without
- * update) `reps` times back to back on `stream`, on the mesh's current data,
- * for timing with events around the call.  The local step and residual
- * overwrite only their outputs; the solve kernels only their work vectors. */
+/* Launch one kernel class (1 local step, 2 residual gather as a launch of
+ * its own, 3 interior forward with the residual gather as the PD iterations
+ * run it, 4 all interface phases of one solve, 5 interior backward without
+ * update, 6 interior forward reading the residual) `reps` times back to back
+ * on `stream`, on the mesh's current data, for timing with events around the
+ * call.  The local step and residual overwrite only their outputs; the solve
+ * kernels only their work vectors and the residual. */
 int vh_mesh_time_kernel(vh_mesh* mesh, int32_t kernel_class, int32_t reps, void* stream);
 
 /* ---- Embedded points (Eq. m2y): positions of points carried by the mesh,
@@ -347,6 +351,13 @@ int vh_debug_local_step(vh_mesh* mesh, const double* x, double* T, double* sigma
  * target y: r = b(x) - K x on free vertices, written to r [nv][3] (pinned rows
  * are 0).  Uses the local-step and scatter kernels. */
 int vh_debug_residual(vh_mesh* mesh, const double* x, const double* y, double* r);
+
+/* The same residual as the PD iterations form it: the local step, then the
+ * interior forward solve, whose first stage gathers r (each subdomain's
+ * workgroup its interior rows and an equal share of the interface rows)
+ * before it solves.  Writes r [nv][3] (pinned rows 0); equal bit for bit to
+ * vh_debug_residual's. */
+int vh_debug_residual_in_solve(vh_mesh* mesh, const double* x, const double* y, double* r);
 
 /* The scatter of the local step's corner forces by element colouring, a
  * cross-check of the atomic-free partial sums the step uses (Sec. 7.1's

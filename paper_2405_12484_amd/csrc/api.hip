@@ -202,10 +202,11 @@ size_t launch_set_bytes(const vh::Plan& P) {
 
 }  // namespace
 
-int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta, const vh::DevMesh* G) {
+int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta, const vh::DevMesh* G,
+          bool resid) {
     {
         ProfScope ps(m, s, 3);
-        VH_HIP(vh::launch_interior_fwd(with_record(L.ifwd, G), L.lds_fwd, s));
+        VH_HIP(vh::launch_interior_fwd(with_record(L.ifwd, G), L.lds_fwd, s, resid));
     }
     {
         ProfScope ps(m, s, 4);
@@ -230,12 +231,9 @@ int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s, const vh::DevMes
         ProfScope ps(m, s, 1);
         VH_HIP(vh::launch_local(with_record(L.local, G), s, false));
     }
-    {
-        ProfScope ps(m, s, 2);
-        VH_HIP(vh::launch_residual(with_record(L.residual, G), s));
-    }
+    // the residual r = b - L x is formed by the interior forward solve
     const bool refine = L.refine_steps > 0;
-    VH_TRY(solve(m, L, s, true, refine, G));
+    VH_TRY(solve(m, L, s, true, refine, G, true));
     for (int32_t k = 0; k < L.refine_steps; ++k) {
         {
             ProfScope ps(m, s, 6);
@@ -1002,7 +1000,8 @@ int vh_debug_scatter_colored(vh_mesh* m, const double* x, double* f, int32_t* n_
     return VH_OK;
 }
 
-int vh_debug_residual(vh_mesh* m, const double* x, const double* y, double* r) {
+namespace {
+int debug_residual(vh_mesh* m, const double* x, const double* y, double* r, bool in_solve) {
     VH_TRY(check_solo(m));
     if (!x || !y || !r) return fail(VH_EINVAL, "null argument");
     VH_TRY(set_device(m));
@@ -1011,9 +1010,19 @@ int vh_debug_residual(vh_mesh* m, const double* x, const double* y, double* r) {
     VH_TRY(put_user(m, y, d.y, true, nullptr));
     VH_HIP(vh::launch_refresh_u(d, nullptr));
     VH_HIP(vh::launch_local(m->ls.local, nullptr, false));
-    VH_HIP(vh::launch_residual(m->ls.residual, nullptr));
+    if (in_solve) VH_HIP(vh::launch_interior_fwd(m->ls.ifwd, m->ls.lds_fwd, nullptr, true));
+    else VH_HIP(vh::launch_residual(m->ls.residual, nullptr));
     VH_HIP(hipDeviceSynchronize());
     return get_user(m, d.r, r, d.n_free, nullptr);
+}
+}  // namespace
+
+int vh_debug_residual(vh_mesh* m, const double* x, const double* y, double* r) {
+    return debug_residual(m, x, y, r, false);
+}
+
+int vh_debug_residual_in_solve(vh_mesh* m, const double* x, const double* y, double* r) {
+    return debug_residual(m, x, y, r, true);
 }
 
 int vh_debug_interface_factor(vh_mesh* m, double* out, int64_t* count) {
@@ -1055,13 +1064,14 @@ int vh_mesh_time_kernel(vh_mesh* m, int32_t kernel_class, int32_t reps, void* st
         switch (kernel_class) {
             case 1: VH_HIP(vh::launch_local(m->ls.local, s, false)); break;
             case 2: VH_HIP(vh::launch_residual(m->ls.residual, s)); break;
-            case 3: VH_HIP(vh::launch_interior_fwd(m->ls.ifwd, m->ls.lds_fwd, s)); break;
+            case 3: VH_HIP(vh::launch_interior_fwd(m->ls.ifwd, m->ls.lds_fwd, s, true)); break;
             case 4:
                 for (const auto& c : m->ls.cfwd) VH_HIP(vh::launch_coarse(c.ref, c.kind, c.group, s));
                 for (const auto& c : m->ls.cbwd) VH_HIP(vh::launch_coarse(c.ref, c.kind, c.group, s));
                 break;
             case 5: VH_HIP(vh::launch_interior_bwd(m->ls.ibwd, m->ls.lds_bwd, s, false, false)); break;
-            default: return fail(VH_EINVAL, "kernel_class must be 1..5");
+            case 6: VH_HIP(vh::launch_interior_fwd(m->ls.ifwd, m->ls.lds_fwd, s, false)); break;
+            default: return fail(VH_EINVAL, "kernel_class must be 1..6");
         }
     }
     return VH_OK;

@@ -98,7 +98,9 @@ hipError_t launch_local(const LaunchRef& r, hipStream_t s, bool debug);
 // stress dbg_T, into dbg_b
 hipError_t launch_scatter_colour(const DevMesh& d, const int32_t* list, int32_t count, hipStream_t s);
 hipError_t launch_residual(const LaunchRef& r, hipStream_t s);
-hipError_t launch_interior_fwd(const LaunchRef& r, size_t lds, hipStream_t s);
+// resid: compute the PD residual r first (as launch_residual does) instead of
+// reading it
+hipError_t launch_interior_fwd(const LaunchRef& r, size_t lds, hipStream_t s, bool resid);
 hipError_t launch_coarse(const LaunchRef& r, int32_t kind, int32_t group, hipStream_t s);
 hipError_t launch_interior_bwd(const LaunchRef& r, size_t lds, hipStream_t s, bool apply, bool keep_delta);
 hipError_t launch_refine_residual(const LaunchRef& r, hipStream_t s);

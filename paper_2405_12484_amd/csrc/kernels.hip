@@ -681,23 +681,13 @@ __global__ __launch_bounds__(BLK) void k_predict(const DevMesh* __restrict__ GM,
 }
 
 // r_a = m_a (y_a - x_a) / dt^2 + the sum of the vertex's per-workgroup force
-// partials (ascending workgroup order, so the result is deterministic).
-__global__ __launch_bounds__(BLK) void k_residual(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
-                                                  const int32_t* __restrict__ active) {
-    Slot sl;
-    if (!slot_of(L, active, sl)) return;
-    const DevMesh& M = GM[sl.g];
-    const int32_t n_free = M.n_free;
-    const int32_t* __restrict__ vpart_ptr = M.vpart_ptr;
-    const int32_t* __restrict__ vpart = M.vpart;
-    const float4* __restrict__ part = M.part;
-    const double* __restrict__ mass = M.mass;
-    const double* __restrict__ x = M.x;
-    const double* __restrict__ y = M.y;
-    double* __restrict__ r = M.r;
-    const double inv_dt2 = 1.0 / (M.dt * M.dt);
-    const int32_t a = sl.lb * BLK + threadIdx.x;
-    if (a >= n_free) return;
+// partials (ascending workgroup order, so the result is deterministic).  The
+// PD iterations compute it inside the interior forward solve (its prologue);
+// this kernel serves the debug and timing entry points.
+// (The pointers are plain or global-qualified views of the same arrays.)
+template <class IP, class FP, class DP>
+__device__ __forceinline__ void vertex_residual(IP vpart_ptr, IP vpart, FP part, DP mass, DP x, DP y, double inv_dt2,
+                                                int32_t a, double& r0, double& r1, double& r2) {
     const int32_t j0 = vpart_ptr[a], j1 = vpart_ptr[a + 1];
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     // up to four partials per round: their indices, then their values, are
@@ -706,9 +696,9 @@ __global__ __launch_bounds__(BLK) void k_residual(const DevMesh* __restrict__ GM
         int32_t id[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) id[u] = (j + u < j1) ? vpart[j + u] : -1;
-        float4 f[4];
+        f32x4 f[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) f[u] = (id[u] >= 0) ? part[id[u]] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int u = 0; u < 4; ++u) f[u] = (id[u] >= 0) ? part[id[u]] : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             fx += f[u].x;
@@ -717,9 +707,25 @@ __global__ __launch_bounds__(BLK) void k_residual(const DevMesh* __restrict__ GM
         }
     }
     const double m = mass[a] * inv_dt2;
-    r[3 * a + 0] = m * (y[3 * a + 0] - x[3 * a + 0]) + (double)fx;
-    r[3 * a + 1] = m * (y[3 * a + 1] - x[3 * a + 1]) + (double)fy;
-    r[3 * a + 2] = m * (y[3 * a + 2] - x[3 * a + 2]) + (double)fz;
+    r0 = m * (y[3 * a + 0] - x[3 * a + 0]) + (double)fx;
+    r1 = m * (y[3 * a + 1] - x[3 * a + 1]) + (double)fy;
+    r2 = m * (y[3 * a + 2] - x[3 * a + 2]) + (double)fz;
+}
+
+__global__ __launch_bounds__(BLK) void k_residual(const DevMesh* __restrict__ GM, const int32_t* __restrict__ L,
+                                                  const int32_t* __restrict__ active) {
+    Slot sl;
+    if (!slot_of(L, active, sl)) return;
+    const DevMesh& M = GM[sl.g];
+    const int32_t a = sl.lb * BLK + threadIdx.x;
+    if (a >= M.n_free) return;
+    double r0, r1, r2;
+    vertex_residual(M.vpart_ptr, M.vpart, reinterpret_cast<const f32x4*>(M.part), M.mass, M.x, M.y,
+                    1.0 / (M.dt * M.dt), a, r0, r1, r2);
+    double* __restrict__ r = M.r;
+    r[3 * a + 0] = r0;
+    r[3 * a + 1] = r1;
+    r[3 * a + 2] = r2;
 }
 
 // Embedded points (Eq. m2y): p = N x over the four vertices of the point's tet,
@@ -1126,7 +1132,12 @@ struct SolveArgs {
     const CTask* ctasks;
     const int32_t *cslots, *cgidx;
     const double* dvals;
-    const double* r;
+    double* r;
+    // the residual computed by the forward solve's prologue (vertex_residual)
+    const int32_t *vpart_ptr, *vpart;
+    const float4* part;
+    const double *mass, *y;
+    double dt;
     float* zf;                   // [n_int][3] interior z
     float* cgf;                  // [n_cgf][3] contributions of interior supernodes to interface rows
     double* cgd;                 // [n_cgd][3] contributions of interface supernodes
@@ -1155,6 +1166,12 @@ __host__ __device__ __forceinline__ SolveArgs solve_args(const DevMesh& m) {
     a.cgidx = m.cgidx;
     a.dvals = m.dvals;
     a.r = m.r;
+    a.vpart_ptr = m.vpart_ptr;
+    a.vpart = m.vpart;
+    a.part = m.part;
+    a.mass = m.mass;
+    a.y = m.y;
+    a.dt = m.dt;
     a.zf = m.zf;
     a.cgf = m.cgf;
     a.cgd = m.cgd;
@@ -1319,7 +1336,7 @@ __device__ __forceinline__ void chunk_pipeline(const Chunk* __restrict__ chunks,
 // chunk is read into registers while the current one is computed.
 __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict__ GM,
                                                         const int32_t* __restrict__ L,
-                                                        const int32_t* __restrict__ active) {
+                                                        const int32_t* __restrict__ active, int32_t resid) {
     Slot sl;
     if (!slot_of(L, active, sl)) return;
     const SolveArgs a = solve_args(GM[sl.g]);
@@ -1337,7 +1354,32 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
     // the residual is staged before the chunk program starts: vector loads
     // complete in issue order, so chunk loads issued first would hold it up
-    for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)as_global(a.r)[3 * base + i];
+    if (resid) {
+        // r = b - L x of the PD iteration, computed here rather than by a
+        // launch of its own: this subdomain's interior rows, and a slice of
+        // the interface rows (the interface solve reads them from r)
+        const int32_t q = (a.n_gamma + a.D - 1) / a.D;
+        const int32_t g0 = a.n_int + min(d * q, a.n_gamma);
+        const int32_t g1 = a.n_int + min((d + 1) * q, a.n_gamma);
+        const double inv_dt2 = 1.0 / (a.dt * a.dt);
+        for (int32_t i = tid; i < n_loc + (g1 - g0); i += BLKI) {
+            const int32_t v = (i < n_loc) ? base + i : g0 + (i - n_loc);
+            double r0, r1, r2;
+            vertex_residual(as_global(a.vpart_ptr), as_global(a.vpart), as_global(reinterpret_cast<const f32x4*>(a.part)),
+                            as_global(a.mass), as_global((const double*)a.x), as_global(a.y), inv_dt2, v, r0, r1, r2);
+            VH_GLOBAL double* rp = as_global(a.r) + 3 * (size_t)v;
+            rp[0] = r0;
+            rp[1] = r1;
+            rp[2] = r2;
+            if (i < n_loc) {
+                R[3 * i + 0] = (float)r0;
+                R[3 * i + 1] = (float)r1;
+                R[3 * i + 2] = (float)r2;
+            }
+        }
+    } else {
+        for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)as_global(a.r)[3 * base + i];
+    }
     ChunkStart st;
     chunk_first(a.chunks, iv4, c0, c1, cd, st);
     const int wave = tid / 64, lane = tid % 64;
@@ -1968,9 +2010,9 @@ hipError_t interior_set_lds_limit(size_t bytes) {
     return e;
 }
 
-hipError_t launch_interior_fwd(const LaunchRef& r, size_t lds, hipStream_t s) {
+hipError_t launch_interior_fwd(const LaunchRef& r, size_t lds, hipStream_t s, bool resid) {
     if (r.nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_interior_fwd, dim3(r.nblocks), dim3(BLKI), lds, s, r.G, r.L, r.active);
+    hipLaunchKernelGGL(k_interior_fwd, dim3(r.nblocks), dim3(BLKI), lds, s, r.G, r.L, r.active, (int32_t)resid);
     return hipGetLastError();
 }
 

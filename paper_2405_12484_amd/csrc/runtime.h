@@ -164,9 +164,10 @@ int get_user(vh_mesh* m, const double* dev_int, double* host, int32_t rows, hipS
 // user-ordered host [nv][3] -> internal device rows (pinned rows: X if positions, else 0); synchronises s
 int put_user(vh_mesh* m, const double* host, double* dev_int, bool positions, hipStream_t s);
 
-// d = K^{-1} r on the mesh's device vectors (r -> delta; apply: x += d)
+// d = K^{-1} r on the mesh's device vectors (r -> delta; apply: x += d);
+// resid: r is first formed as the PD residual from the local step's partials
 int solve(vh_mesh* m, const LaunchSet& L, hipStream_t s, bool apply, bool keep_delta,
-          const vh::DevMesh* G = nullptr);
+          const vh::DevMesh* G = nullptr, bool resid = false);
 // one local/global iteration (local step, residual, solve with refinement, x += d)
 int pd_iteration(vh_mesh* m, const LaunchSet& L, hipStream_t s, const vh::DevMesh* G = nullptr);
 

@@ -108,6 +108,7 @@ SIGNATURES = {
     "vh_mesh_profile_read": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_debug_local_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vh_debug_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "vh_debug_residual_in_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_debug_scatter_colored": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "vh_debug_interface_factor": (ctypes.c_int, [_vp, _vp, _vp]),
     "vh_debug_solve": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -350,7 +351,8 @@ class Mesh:
 
     def time_kernel(self, kernel_class: str, reps: int, stream=None):
         """Launch one kernel class `reps` times back to back (for event timing)."""
-        idx = {"local": 1, "residual": 2, "interior_fwd": 3, "interface": 4, "interior_bwd": 5}[kernel_class]
+        idx = {"local": 1, "residual": 2, "interior_fwd": 3, "interface": 4, "interior_bwd": 5,
+               "interior_fwd_plain": 6}[kernel_class]
         _check(_lib.vh_mesh_time_kernel(self.h, idx, int(reps), _stream_ptr(stream)))
 
     def profile_read(self):
@@ -400,11 +402,14 @@ class Mesh:
         _check(_lib.vh_debug_local_step(self.h, _ptr(x), _ptr(T), _ptr(sig), _ptr(s)))
         return T.reshape(self.nt, 3, 3), sig, s
 
-    def debug_residual(self, x, y):
+    def debug_residual(self, x, y, in_solve=False):
+        """r = b(x) - K x [nv][3]; in_solve: formed as the PD iterations form it
+        (inside the interior forward solve) instead of by its own launch."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.ascontiguousarray(y, dtype=np.float64)
         r = np.empty((self.nv, 3))
-        _check(_lib.vh_debug_residual(self.h, _ptr(x), _ptr(y), _ptr(r)))
+        fn = _lib.vh_debug_residual_in_solve if in_solve else _lib.vh_debug_residual
+        _check(fn(self.h, _ptr(x), _ptr(y), _ptr(r)))
         return r
 
     def debug_scatter_colored(self, x):

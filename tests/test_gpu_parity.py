@@ -243,6 +243,30 @@ def test_residual_matches_oracle(vh, ctx, name):
     m.close()
 
 
+@pytest.mark.parametrize("name,D", [("box", 4), ("box", 2), ("box", 1), ("shell_small", 8), ("slab", 8)])
+def test_residual_in_solve_is_bitwise_standalone(vh, ctx, name, D):
+    """The PD iterations form the residual inside the interior forward solve
+    (each subdomain's workgroup its interior rows and a share of ceil(n_G / D)
+    of the n_G interface rows, the last share shorter unless D divides n_G;
+    D = 1 has no interface): bit for bit the residual of the gather's own
+    launch, and within FP32 rounding of the oracle."""
+    say(f"[residual in solve] {name} D={D}")
+    p = synth.problem_by_name(name)
+    m = make_mesh(vh, ctx, p, n_subdomains=D)
+    x = deformed(p, amp=2e-3, seed=4)
+    y = deformed(p, amp=1e-3, seed=5)
+    r_own = m.debug_residual(x, y)
+    m.debug_residual(p.X, p.X)                    # another r in between
+    r_in = m.debug_residual(x, y, in_solve=True)
+    say(f"  interface rows {m.info()['n_interface']}, subdomains {D}")
+    assert np.array_equal(r_in, r_own)
+    sim = oracle.OracleSim.from_problem(p)
+    loc = oracle.local_step(x, sim.tets, sim.grads, sim.w_s, sim.w_v)
+    rref = sim.rhs(y, loc["P"]) - sim.L_ff @ x[sim.free]
+    assert np.linalg.norm(r_in[sim.free] - rref) <= 1e-5 * np.linalg.norm(rref)
+    m.close()
+
+
 @pytest.mark.parametrize("name", ["box", "shell_small", "slab"])
 def test_scatter_matches_element_colouring(vh, ctx, name):
     """The atomic-free scatter (per-workgroup LDS partial sums, then a gather
