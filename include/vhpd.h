@@ -107,6 +107,12 @@ int vh_ctx_set_hbm_budget(vh_ctx* ctx, size_t hbm_budget_bytes);
  *                      changes the trajectory (an error to report against the
  *                      exact solve); it needs refine_steps == 0 and is not
  *                      differentiated by the adjoint entry points.
+ *   interior_desc_table (default 64, 1..64): the interior solves copy the
+ *                      descriptors of a subdomain's first this many program
+ *                      chunks to LDS at kernel start and read later ones from
+ *                      global memory (a subdomain's program rarely exceeds 40
+ *                      chunks; a smaller table exercises the global reads).
+ *                      Results do not depend on it.
  * vh_ctx_set_config validates and copies *cfg (VH_EINVAL on out-of-range
  * values); it applies to meshes prefactored and servers opened afterwards, and
  * use_graphs also to later vh_mesh_step calls of meshes already resident. */
@@ -116,6 +122,7 @@ typedef struct vh_config {
     int32_t thin_separators;
     int32_t iface_merge_max_cols;
     int32_t cms_modes, cms_sweeps;
+    int32_t interior_desc_table;
 } vh_config;
 int vh_ctx_get_config(const vh_ctx* ctx, vh_config* cfg);
 int vh_ctx_set_config(vh_ctx* ctx, const vh_config* cfg);

@@ -562,6 +562,7 @@ int upload_device(vh_mesh* m) {
     d.max_sub_n = std::max(P.max_sub_n, 1);
     d.max_nb = P.max_nb;
     d.max_cint = P.max_cint;
+    d.desc_table = m->ctx->cfg.interior_desc_table;
     d.dt = P.dt;
     for (int c = 0; c < 3; ++c) d.g[c] = P.gravity[c];
     int r = alloc_plan(m);
@@ -639,6 +640,8 @@ int vh_ctx_set_config(vh_ctx* ctx, const vh_config* cfg) {
     if (cfg->iface_merge_max_cols < 0) return fail(VH_EINVAL, "iface_merge_max_cols must be >= 0");
     if (cfg->cms_modes < 0 || cfg->cms_modes > 256 || cfg->cms_sweeps < 0 || cfg->cms_sweeps > 10000)
         return fail(VH_EINVAL, "cms_modes must be in 0..256 and cms_sweeps in 0..10000");
+    if (cfg->interior_desc_table < 1 || cfg->interior_desc_table > 64)
+        return fail(VH_EINVAL, "interior_desc_table must be in 1..64");
     ctx->cfg = *cfg;
     return VH_OK;
 }

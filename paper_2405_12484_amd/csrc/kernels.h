@@ -37,6 +37,7 @@ struct DevMesh {
     float* ivals = nullptr;
     int32_t *bnd = nullptr, *bnd_off = nullptr;
     int32_t max_nb = 0, max_cint = 0;
+    int32_t desc_table = 64;        // chunk descriptors held in the interior kernels' LDS table (1..64)
     double* dvals = nullptr;
     CTask* ctasks = nullptr;
     int32_t *cslots = nullptr, *cgidx = nullptr;

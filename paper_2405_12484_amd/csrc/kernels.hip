@@ -1125,7 +1125,7 @@ __device__ __forceinline__ T group_sum(T v) {
 }
 
 struct SolveArgs {
-    int32_t n_int, n_gamma, D, max_n, max_nb, max_cint;
+    int32_t n_int, n_gamma, D, max_n, max_nb, max_cint, desc_table;
     const int32_t *sub_off, *sub_fwd_ch, *sub_bwd_ch, *bnd, *bnd_off;
     const Chunk* chunks;
     const float* ivals;          // packed interior chunks
@@ -1154,6 +1154,7 @@ __host__ __device__ __forceinline__ SolveArgs solve_args(const DevMesh& m) {
     a.max_n = m.max_sub_n;
     a.max_nb = m.max_nb;
     a.max_cint = m.max_cint;
+    a.desc_table = m.desc_table;
     a.sub_off = m.sub_off;
     a.sub_fwd_ch = m.sub_fwd_ch;
     a.sub_bwd_ch = m.sub_bwd_ch;
@@ -1218,8 +1219,9 @@ __device__ __forceinline__ void chunk_store(float4* dst, const ChunkRegs& reg) {
     dst[j + 2 * BLKI] = make_float4(reg.c0, reg.c1, reg.c2, reg.c3);
 }
 
-// Descriptors of a subdomain's first CHD chunks are copied to LDS at kernel
-// start, so the chunk pipeline never waits on a global descriptor read.
+// Descriptors of a subdomain's first tab <= CHD chunks are copied to LDS at
+// kernel start, so the chunk pipeline does not wait on a global descriptor
+// read for them; later chunks read theirs from global memory.
 constexpr int32_t CHD = 64;
 
 // kind, ntasks, v0, nv of chunk c, read from global memory
@@ -1233,10 +1235,10 @@ __device__ __forceinline__ Chunk chunk_desc_global(const Chunk* __restrict__ chu
     return K;
 }
 
-__device__ __forceinline__ Chunk chunk_desc(const Chunk* __restrict__ chunks, const int4* cd, int32_t c0,
-                                            int32_t c) {
+__device__ __forceinline__ Chunk chunk_desc(const Chunk* __restrict__ chunks, const int4* cd, int32_t tab,
+                                            int32_t c0, int32_t c) {
     Chunk K;
-    if (c - c0 < CHD) {
+    if (c - c0 < tab) {
         const int4 v = cd[c - c0];
         K.kind = v.x;
         K.ntasks = v.y;
@@ -1262,11 +1264,11 @@ struct ChunkStart {
     ChunkRegs ra;
 };
 __device__ __forceinline__ void chunk_first(const Chunk* __restrict__ chunks, const float4* __restrict__ iv4,
-                                            int32_t c0, int32_t c1, int4* cd, ChunkStart& st) {
+                                            int32_t c0, int32_t c1, int4* cd, int32_t tab, ChunkStart& st) {
     if (c0 >= c1) return;
     st.K0 = chunk_desc_global(chunks, c0);
     chunk_load(iv4 + st.K0.v0 / 4, (st.K0.nv + 3) / 4, st.ra);
-    for (int32_t c = c0 + (int32_t)threadIdx.x; c < min(c1, c0 + CHD); c += BLKI) {
+    for (int32_t c = c0 + (int32_t)threadIdx.x; c < min(c1, c0 + tab); c += BLKI) {
         const Chunk K = chunk_desc_global(chunks, c);
         cd[c - c0] = make_int4(K.kind, K.ntasks, K.v0, K.nv);
     }
@@ -1279,8 +1281,8 @@ __device__ __forceinline__ void chunk_first(const Chunk* __restrict__ chunks, co
 // compute to complete.  compute is called by every thread; ends with a barrier.
 template <class F>
 __device__ __forceinline__ void chunk_pipeline(const Chunk* __restrict__ chunks, const float4* __restrict__ iv4,
-                                               int32_t c0, int32_t c1, float* sm, int4* cd, ChunkStart& st,
-                                               F&& compute) {
+                                               int32_t c0, int32_t c1, float* sm, int4* cd, int32_t tab,
+                                               ChunkStart& st, F&& compute) {
     // st: chunk_first's first chunk (registers) and descriptor table (LDS)
     if (c0 >= c1) {
         __syncthreads();   // the caller's LDS writes before the pipeline stay ordered before its reads after
@@ -1298,7 +1300,7 @@ __device__ __forceinline__ void chunk_pipeline(const Chunk* __restrict__ chunks,
     // wait-count pass a path on which staged registers looked pending, and it
     // then waited for every load in flight at the top of each phase.
     chunk_store(reinterpret_cast<float4*>(buf0), ra);
-    Chunk N1 = chunk_desc(chunks, cd, c0, min(c0 + 1, last));
+    Chunk N1 = chunk_desc(chunks, cd, tab, c0, min(c0 + 1, last));
     chunk_load(iv4 + N1.v0 / 4, (N1.nv + 3) / 4, ra);
     Chunk K1 = N1;
     __syncthreads();
@@ -1307,14 +1309,14 @@ __device__ __forceinline__ void chunk_pipeline(const Chunk* __restrict__ chunks,
     int32_t c = c0;
     for (; c + 1 < c1; c += 2) {
         // chunk c in buffer 0, chunk c + 1 in ra
-        const Chunk N0 = chunk_desc(chunks, cd, c0, min(c + 2, last));
+        const Chunk N0 = chunk_desc(chunks, cd, tab, c0, min(c + 2, last));
         chunk_load(iv4 + N0.v0 / 4, (N0.nv + 3) / 4, rb);
         compute(K0, buf0, buf1);
         chunk_store(reinterpret_cast<float4*>(buf1), ra);
         K1 = N1;
         __syncthreads();
         // chunk c + 1 in buffer 1, chunk c + 2 in rb
-        N1 = chunk_desc(chunks, cd, c0, min(c + 3, last));
+        N1 = chunk_desc(chunks, cd, tab, c0, min(c + 3, last));
         chunk_load(iv4 + N1.v0 / 4, (N1.nv + 3) / 4, ra);
         compute(K1, buf1, buf0);
         chunk_store(reinterpret_cast<float4*>(buf0), rb);
@@ -1351,6 +1353,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
     const int32_t n_loc = as_global(a.sub_off)[d + 1] - base;
     const int tid = threadIdx.x;
     const int32_t c0 = as_global(a.sub_fwd_ch)[d], c1 = as_global(a.sub_fwd_ch)[d + 1];
+    const int32_t tab = min(max(a.desc_table, 1), CHD);
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
     // the residual is staged before the chunk program starts: vector loads
     // complete in issue order, so chunk loads issued first would hold it up
@@ -1381,10 +1384,10 @@ __global__ __launch_bounds__(BLKI) void k_interior_fwd(const DevMesh* __restrict
         for (int32_t i = tid; i < 3 * n_loc; i += BLKI) R[i] = (float)as_global(a.r)[3 * base + i];
     }
     ChunkStart st;
-    chunk_first(a.chunks, iv4, c0, c1, cd, st);
+    chunk_first(a.chunks, iv4, c0, c1, cd, tab, st);
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
-    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, st, [&](const Chunk& K, const float* cur, float*) {
+    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, tab, st, [&](const Chunk& K, const float* cur, float*) {
         const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
         if (K.kind == PULLSUM) {
             const int32_t* idat = desc + 4 * K.ntasks;
@@ -1597,9 +1600,10 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
     const int32_t b0 = as_global(a.bnd_off)[d], nb = as_global(a.bnd_off)[d + 1] - b0;
     const int tid = threadIdx.x;
     const int32_t c0 = as_global(a.sub_bwd_ch)[d], c1 = as_global(a.sub_bwd_ch)[d + 1];
+    const int32_t tab = min(max(a.desc_table, 1), CHD);
     const float4* iv4 = reinterpret_cast<const float4*>(a.ivals);
     ChunkStart st;
-    chunk_first(a.chunks, iv4, c0, c1, cd, st);
+    chunk_first(a.chunks, iv4, c0, c1, cd, tab, st);
     for (int32_t i = tid; i < 3 * n_loc; i += BLKI) Z[i] = as_global(a.zf)[3 * base + i];
     for (int32_t i = tid; i < 3 * nb; i += BLKI) {
         const int32_t k = i / 3, c = i - 3 * k;
@@ -1646,7 +1650,7 @@ __global__ __launch_bounds__(BLKI) void k_interior_bwd(const DevMesh* __restrict
     }
     const int wave = tid / 64, lane = tid % 64;
     constexpr int NW = BLKI / 64;
-    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, st, [&](const Chunk& K, const float* cur, float* spare) {
+    chunk_pipeline(a.chunks, iv4, c0, c1, sm, cd, tab, st, [&](const Chunk& K, const float* cur, float* spare) {
         const int32_t* desc = reinterpret_cast<const int32_t*>(cur);
         const float* dat = cur + 8 * K.ntasks;
         const int32_t* idat = reinterpret_cast<const int32_t*>(dat);

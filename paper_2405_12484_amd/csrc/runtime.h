@@ -57,7 +57,7 @@ struct Server;
 
 struct vh_ctx {
     int device = 0;
-    vh_config cfg{1, 96, 384, 1, 3000, 0, 10};
+    vh_config cfg{1, 96, 384, 1, 3000, 0, 10, 64};
     void* scratch = nullptr;        // device address of the step scratch array (vh_mesh_step_noalloc)
     void* blas = nullptr;           // rocBLAS handle of the interface factorization (created on first use)
     size_t budget = 0;

@@ -58,7 +58,7 @@ class Config(ctypes.Structure):
     _fields_ = [("use_graphs", ctypes.c_int32), ("iface_lanes32_min", ctypes.c_int32),
                 ("iface_lanes64_min", ctypes.c_int32), ("thin_separators", ctypes.c_int32),
                 ("iface_merge_max_cols", ctypes.c_int32), ("cms_modes", ctypes.c_int32),
-                ("cms_sweeps", ctypes.c_int32)]
+                ("cms_sweeps", ctypes.c_int32), ("interior_desc_table", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

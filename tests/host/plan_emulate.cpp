@@ -36,6 +36,22 @@ void* vhp_build(const double* X, int nv, const int* tets, int nt, const double* 
     return P;
 }
 
+// as vhp_build, with interior chunks of at most chunk_floats 32-bit words
+void* vhp_build_chunks(const double* X, int nv, const int* tets, int nt, const double* gs, const double* gv,
+                       const double* mass, const unsigned char* pinned, const double* g, double dt, int iters,
+                       int D, int leaf_max, int chunk_floats, int* rc, char* msg, int msglen) {
+    Plan* P = new Plan();
+    std::string m;
+    *rc = build_plan(X, nv, tets, nt, gs, gv, mass, pinned, g, dt, iters, D, 0, leaf_max, chunk_floats, PlanOptions(),
+                     *P, m);
+    std::snprintf(msg, msglen, "%s", m.c_str());
+    if (*rc != 0) {
+        delete P;
+        return nullptr;
+    }
+    return P;
+}
+
 void vhp_free(void* h) { delete static_cast<Plan*>(h); }
 
 // the plan's interface factor values (host FP64 numeric factorization); their

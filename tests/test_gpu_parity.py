@@ -650,6 +650,38 @@ def test_budget_refuses(vh):
     c.close()
 
 
+@pytest.mark.parametrize("name,D", [("box", 4), ("box", 1), ("shell_small", 8)])
+def test_chunk_descriptors_from_global_memory(vh, ctx, name, D):
+    """The interior solves read the descriptors of program chunks past their
+    LDS table from global memory.  With a table of one entry every chunk
+    after a subdomain's first takes that path: the solve and three frames are
+    bitwise those of the full table, and the solve is exact."""
+    say(f"[descriptor table] {name} D={D}")
+    p = synth.problem_by_name(name)
+    rhs = np.random.default_rng(7).standard_normal((p.nv, 3))
+    res = []
+    for tab in (64, 1):
+        c = vh.Context(0)
+        c.set_config(interior_desc_table=tab)
+        assert c.config()["interior_desc_table"] == tab
+        m = make_mesh(vh, c, p, n_subdomains=D)
+        d = m.debug_solve(rhs)
+        m.step(3)
+        x, v = m.read_state()
+        res.append((d, x, v))
+        m.close()
+        c.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+    sim = oracle.OracleSim.from_problem(p)
+    xe = sim._solve(rhs[sim.free])
+    assert np.linalg.norm(res[1][0][sim.free] - xe) <= 5e-7 * np.linalg.norm(xe)
+    for bad in (0, 65):
+        with pytest.raises(vh.VHError) as ei:
+            ctx.set_config(interior_desc_table=bad)
+        assert ei.value.code == vh.VH_EINVAL
+
+
 def test_graph_replay_equals_direct_launches(vh, ctx):
     """The frame replayed as a HIP graph is bitwise equal to direct launches,
     on every replay."""

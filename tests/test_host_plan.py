@@ -90,6 +90,47 @@ def test_long_interior_program(hl):
         hl.vhp_free(h)
 
 
+@pytest.mark.parametrize("name,D,words", [("box", 1, 2048), ("box", 2, 2048), ("shell_small", 8, 4096)])
+def test_small_chunks_solve_exactly(hl, name, D, words):
+    """Interior programs cut into chunks of at most `words` 32-bit words
+    instead of the kernels' 12,288 (more chunks, the same phases): the
+    emulated solve is the one the full-size chunks give, to FP32 rounding, and
+    exact; a chunk size that cannot hold a supernode's block is refused."""
+    p = synth.problem_by_name(name)
+    a = lambda x, t: np.ascontiguousarray(x, dtype=t)
+    keep = [a(p.X, np.float64), a(p.tets, np.int32), a(p.gamma_s, np.float64), a(p.gamma_v, np.float64),
+            a(p.mass, np.float64), a(p.pinned, np.uint8), a(p.gravity, np.float64)]
+    hl.vhp_build_chunks.restype = _vp
+    hl.vhp_build_chunks.argtypes = [_vp, _ci, _vp, _ci, _vp, _vp, _vp, _vp, _vp, _cd, _ci, _ci, _ci, _ci, _vp, _vp,
+                                    _ci]
+    rhs = np.random.default_rng(3).standard_normal((p.nv, 3))
+    sim = oracle.OracleSim.from_problem(p)
+    xe = sim._solve(rhs[sim.free])
+    out = {}
+    for w in (12288, words, 256):
+        rc = ctypes.c_int(0)
+        msg = ctypes.create_string_buffer(256)
+        h = hl.vhp_build_chunks(keep[0].ctypes.data, p.nv, keep[1].ctypes.data, p.nt, keep[2].ctypes.data,
+                                keep[3].ctypes.data, keep[4].ctypes.data, keep[5].ctypes.data, keep[6].ctypes.data,
+                                p.dt, p.pd_iters, D, 32, w, ctypes.byref(rc), msg, 256)
+        if w == 256:
+            assert not h and rc.value != 0 and "chunk" in msg.value.decode()
+            continue
+        assert h, msg.value.decode()
+        try:
+            info = np.zeros(17, dtype=np.int64)
+            hl.vhp_info(h, info.ctypes.data)
+            d = np.zeros((p.nv, 3))
+            hl.vhp_solve(h, rhs.ctypes.data, d.ctypes.data)
+            out[w] = (int(info[15]), d)
+        finally:
+            hl.vhp_free(h)
+    assert out[words][0] > out[12288][0]
+    d0, d1 = out[12288][1], out[words][1]
+    assert np.linalg.norm(d1 - d0) <= 1e-7 * np.linalg.norm(d0)
+    assert np.linalg.norm(d1[sim.free] - xe) <= 2e-7 * np.linalg.norm(xe)
+
+
 def test_refactor_matches_fresh_plan(hl):
     """A plan refactored with new stiffness solves exactly as a plan built
     from scratch with that stiffness (bitwise: the same matrix assembly and
