@@ -1198,14 +1198,21 @@ struct ChunkRegs {
     float a0, a1, a2, a3, b0, b1, b2, b3, c0, c1, c2, c3;
 };
 // Loads are unconditional (indices clamped into the chunk, nv4 >= 1) so the
-// registers are always defined; only the stores are predicated.
+// registers are always defined; only the stores are predicated.  They are
+// non-temporal: a solve streams the interior programs (about 90 MB for the
+// 390K-tet shell) once, and as ordinary loads they pushed the interface
+// factor, which both sweeps of every solve read, and the local step's
+// element records out of L2 and the MALL (interface solve 1.00 -> 0.85 ms
+// per frame with these loads streamed; the same hint on the interface
+// factor's loads made it slower).
 __device__ __forceinline__ void chunk_load(const float4* __restrict__ src_, int32_t nv4, ChunkRegs& reg) {
     const int32_t j = threadIdx.x, last = nv4 - 1;
-    f32x4 t = load_global4(src_ + min(j, last));
+    const VH_GLOBAL f32x4* src = reinterpret_cast<const VH_GLOBAL f32x4*>(as_global(src_));
+    f32x4 t = __builtin_nontemporal_load(src + min(j, last));
     reg.a0 = t.x; reg.a1 = t.y; reg.a2 = t.z; reg.a3 = t.w;
-    t = load_global4(src_ + min(j + BLKI, last));
+    t = __builtin_nontemporal_load(src + min(j + BLKI, last));
     reg.b0 = t.x; reg.b1 = t.y; reg.b2 = t.z; reg.b3 = t.w;
-    t = load_global4(src_ + min(j + 2 * BLKI, last));
+    t = __builtin_nontemporal_load(src + min(j + 2 * BLKI, last));
     reg.c0 = t.x; reg.c1 = t.y; reg.c2 = t.z; reg.c3 = t.w;
 }
 // The stores fill the whole buffer (NV4I * BLKI float4, words past the chunk
@@ -1858,7 +1865,10 @@ __global__ __launch_bounds__(BLKC) void k_cms_back(const DevMesh* __restrict__ G
         }
 #pragma unroll 8
         for (int32_t j = 0; j < nb; ++j) {
-            const double f = (double)psi[(size_t)j * n + i];
+            // the boundary modes (about 100 MB for the shell) are read once
+            // per solve: streamed, so they do not evict the interface factor
+            // (3.28 -> 3.04 ms/frame; the interior modes, read twice, are not)
+            const double f = (double)__builtin_nontemporal_load(psi + (size_t)j * n + i);
             s0 += f * XB[3 * j];
             s1 += f * XB[3 * j + 1];
             s2 += f * XB[3 * j + 2];
