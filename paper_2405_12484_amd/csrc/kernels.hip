@@ -4,9 +4,11 @@
 //   k_local     Sec. 7.1 local step: per tet F, signed SVD, polar rotation R,
 //               volume projection (Eq. vol_pre), residual stress and corner
 //               forces, summed per vertex inside each workgroup (LDS, fixed order)
-//   k_residual  Sec. 7.1 global step right-hand side, as the residual
+//   vertex_residual
+//               Sec. 7.1 global step right-hand side, as the residual
 //               r = b - K x^(k): per vertex the sum of its workgroup partials,
-//               without atomics
+//               without atomics; in the PD iterations the first stage of
+//               k_interior_fwd, as its own launch k_residual elsewhere
 //   k_interior_fwd / k_coarse / k_interior_bwd
 //               Sec. 7.2 decomposed solve K d = r: interior triangular
 //               solves (one workgroup per subdomain, factor chunks and vectors
